@@ -1,0 +1,225 @@
+/*
+ * FP64 CPU oracle for Monte-Carlo GMI / MI estimation with exact per-bit LLRs.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product (the HIP library and its
+ * Python binding) may include, link, load or call this file; only the tests,
+ * the smoke check and the CPU-baseline leg of the benchmark use it.
+ *
+ * The paper defines the quantities only by name (glossary entries GMI, MI,
+ * LLR, BICM, BMD, AWGN, SNR); the definitions written out here are the
+ * standard information-theoretic ones for bit-interleaved coded modulation
+ * with bit-metric decoding over the AWGN channel, uniform priors:
+ *
+ *   channel        y = x_i + z,  z ~ N(0, sigma2 I_N),  i uniform on [0, M)
+ *   metric         t_j(y) = ||y - x_j||^2 / (2 sigma2)                 (nats)
+ *   LLR of bit k   lambda_k(y) = ln sum_{j: b_k(j)=1} e^{-t_j}
+ *                              - ln sum_{j: b_k(j)=0} e^{-t_j}
+ *                  (b_k(j) = bit k of labels[j], LSB first; positive means 1)
+ *   GMI cost       c_G(y, i) = sum_k log2(1 + exp(-(2 b_k(i) - 1) lambda_k))
+ *   MI cost        c_M(y, i) = log2 sum_j exp(-(t_j - t_i))
+ *   estimates      GMI = m - mean(c_G),  MI = m - mean(c_M)   (bits / symbol)
+ *                  SE  = sqrt(sum (c - mean)^2 / (N (N - 1)))
+ *
+ * Every class sum is its own max-subtracted log-sum-exp over all M distances,
+ * so nothing underflows however far a class lies. No blocking, folding or
+ * reordering: each sample is handled on its own, in the order above.
+ *
+ * The multilayer-perceptron demapper oracle (forward, loss, backward, Adam)
+ * follows at the end of the file.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define LN2 0.69314718055994530942
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+static int log2_exact(int M) {
+    int m = 0;
+    while ((1 << m) < M) m++;
+    return m;
+}
+
+/* t_j = ||y - x_j||^2 / (2 sigma2) for all j (nats). */
+static void metrics(const double* y, const double* X, int M, int dim, double sigma2, double* t) {
+    for (int j = 0; j < M; j++) {
+        double d = 0.0;
+        for (int q = 0; q < dim; q++) {
+            double e = y[q] - X[(size_t)j * dim + q];
+            d += e * e;
+        }
+        t[j] = d / (2.0 * sigma2);
+    }
+}
+
+/* ln sum_{j in class} e^{-t_j}, class = {j : bit k of labels[j] == b};
+ * k < 0 selects every point. Max-subtracted. Returns -INFINITY if empty. */
+static double class_lse(const double* t, const uint32_t* labels, int M, int k, int b) {
+    double mx = -INFINITY;
+    for (int j = 0; j < M; j++) {
+        if (k >= 0 && (int)((labels[j] >> k) & 1u) != b) continue;
+        if (-t[j] > mx) mx = -t[j];
+    }
+    if (mx == -INFINITY) return mx;
+    double s = 0.0;
+    for (int j = 0; j < M; j++) {
+        if (k >= 0 && (int)((labels[j] >> k) & 1u) != b) continue;
+        s += exp(-t[j] - mx);
+    }
+    return mx + log(s);
+}
+
+/* softplus(u) = ln(1 + e^u), stable for every u. */
+static double softplus(double u) {
+    return (u > 0.0 ? u : 0.0) + log1p(exp(-fabs(u)));
+}
+
+/* LLRs for one sample into llr[0..m-1] (nats); t is scratch of size M. */
+static void llr_one(const double* y, int dim, const double* X, const uint32_t* labels, int M,
+                    double sigma2, double* t, double* llr) {
+    int m = log2_exact(M);
+    metrics(y, X, M, dim, sigma2, t);
+    for (int k = 0; k < m; k++)
+        llr[k] = class_lse(t, labels, M, k, 1) - class_lse(t, labels, M, k, 0);
+}
+
+/* Per-bit LLRs (nats) of n samples; y is [n][dim], llr is [n][m]. */
+int oracle_llr(const double* y, int64_t n, int dim, const double* X, const uint32_t* labels,
+               int M, double sigma2, double* llr) {
+    int m = log2_exact(M);
+    int err = 0;
+#pragma omp parallel
+    {
+        double* t = (double*)malloc(sizeof(double) * (size_t)M);
+        if (!t) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t s = 0; s < n; s++)
+                llr_one(y + s * dim, dim, X, labels, M, sigma2, t, llr + s * m);
+            free(t);
+        }
+    }
+    return err ? -1 : 0;
+}
+
+/* Per-sample GMI and MI costs (bits). tx_idx[s] is the row of X sent.
+ * Either output pointer may be NULL. */
+int oracle_costs(const double* y, const uint32_t* tx_idx, int64_t n, int dim, const double* X,
+                 const uint32_t* labels, int M, double sigma2, double* c_gmi, double* c_mi) {
+    int m = log2_exact(M);
+    int err = 0;
+#pragma omp parallel
+    {
+        double* t = (double*)malloc(sizeof(double) * (size_t)M);
+        double* llr = (double*)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+        if (!t || !llr) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t s = 0; s < n; s++) {
+                const double* ys = y + s * dim;
+                uint32_t i = tx_idx[s];
+                llr_one(ys, dim, X, labels, M, sigma2, t, llr);
+                if (c_gmi) {
+                    double c = 0.0;
+                    for (int k = 0; k < m; k++) {
+                        int b = (int)((labels[i] >> k) & 1u);
+                        c += softplus(-(2.0 * b - 1.0) * llr[k]);
+                    }
+                    c_gmi[s] = c / LN2;
+                }
+                if (c_mi) {
+                    /* log sum_j e^{-(t_j - t_i)} = t_i + ln sum_j e^{-t_j} */
+                    c_mi[s] = (t[i] + class_lse(t, labels, M, -1, 0)) / LN2;
+                }
+            }
+        }
+        free(t);
+        free(llr);
+    }
+    return err ? -1 : 0;
+}
+
+/* Mean and standard error of n per-sample costs, summed in order in FP64
+ * with Kahan compensation. nonfinite counts entries that are NaN or inf. */
+static void mean_se(const double* c, int64_t n, double* mean, double* se, int64_t* nonfinite) {
+    double s = 0.0, comp = 0.0;
+    int64_t bad = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (!isfinite(c[i])) bad++;
+        double yk = c[i] - comp;
+        double tk = s + yk;
+        comp = (tk - s) - yk;
+        s = tk;
+    }
+    double mu = s / (double)n;
+    double v = 0.0, cv = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+        double d = c[i] - mu;
+        double yk = d * d - cv;
+        double tk = v + yk;
+        cv = (tk - v) - yk;
+        v = tk;
+    }
+    *mean = mu;
+    *se = n > 1 ? sqrt(v / ((double)n * (double)(n - 1))) : 0.0;
+    *nonfinite = bad;
+}
+
+/* GMI / MI estimate of one SNR point. out[0..5] = {GMI, MI, SE_GMI, SE_MI, N,
+ * n_nonfinite} with GMI and MI in bits per N-dimensional symbol. */
+int oracle_gmi(const double* y, const uint32_t* tx_idx, int64_t n, int dim, const double* X,
+               const uint32_t* labels, int M, double sigma2, double* out) {
+    if (n < 1) return -2;
+    double* cg = (double*)malloc(sizeof(double) * (size_t)n);
+    double* cm = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!cg || !cm) {
+        free(cg);
+        free(cm);
+        return -1;
+    }
+    int rc = oracle_costs(y, tx_idx, n, dim, X, labels, M, sigma2, cg, cm);
+    if (rc == 0) {
+        int m = log2_exact(M);
+        double mg, sg, mm, sm;
+        int64_t bg, bm;
+        mean_se(cg, n, &mg, &sg, &bg);
+        mean_se(cm, n, &mm, &sm, &bm);
+        int64_t bad = 0;
+        for (int64_t i = 0; i < n; i++)
+            if (!isfinite(cg[i]) || !isfinite(cm[i])) bad++;
+        out[0] = m - mg;
+        out[1] = m - mm;
+        out[2] = sg;
+        out[3] = sm;
+        out[4] = (double)n;
+        out[5] = (double)bad;
+        (void)bg;
+        (void)bm;
+    }
+    free(cg);
+    free(cm);
+    return rc;
+}
