@@ -1,0 +1,151 @@
+/*
+ * mdgmi — exact per-bit LLRs and Monte-Carlo GMI / MI of N-dimensional
+ * modulation formats over the AWGN channel, on AMD Instinct MI355X (gfx950).
+ *
+ * What is computed. The paper lists GMI, MI, LLR, BICM/BMD, AWGN and SNR in
+ * its glossary and names the 4D/8D polarization-ring-switching and
+ * two-amplitude 8PSK formats there; it gives no formula. The library follows
+ * the standard definitions for bit-interleaved coded modulation with
+ * bit-metric decoding, uniform priors:
+ *
+ *   y = x_i + z,  z ~ N(0, sigma2 I_N),  t_j(y) = ||y - x_j||^2 / (2 sigma2)
+ *   lambda_k(y) = ln sum_{j: b_k(j)=1} e^{-t_j} - ln sum_{j: b_k(j)=0} e^{-t_j}   (nats)
+ *   GMI = m - (1/n) sum_s sum_k log2(1 + exp(-(2 b_k(i_s) - 1) lambda_k(y_s)))
+ *   MI  = m - (1/n) sum_s log2 sum_j exp(-(t_j(y_s) - t_{i_s}(y_s)))
+ *
+ * with b_k(j) = bit k (LSB first) of the label of constellation row j and
+ * m = log2 M. LLR column k is label bit k; a positive LLR favours bit 1.
+ *
+ * Conventions shared by every call:
+ *  - Array arguments named "device" are device pointers on the device that
+ *    was current when the format was created; the caller owns them and keeps
+ *    them alive until the stream has passed the call. "host" arrays are read
+ *    before the call returns and are not retained.
+ *  - Arrays are row-major and contiguous.
+ *  - `stream` is a hipStream_t passed as void* (NULL: the default stream).
+ *    Launches are asynchronous on that stream; nothing synchronises it.
+ *  - Every argument is checked on the host before anything is launched; a
+ *    failed check returns a negative mdgmi_status and launches nothing.
+ *  - No call allocates device memory except mdgmi_format_create and the
+ *    MLP create/load calls. Scratch memory comes from the caller's workspace.
+ *  - Calls on distinct (stream, workspace, output) triples may overlap;
+ *    calls sharing a workspace must be ordered by the caller.
+ */
+#ifndef MDGMI_H
+#define MDGMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MDGMI_OK = 0,
+    MDGMI_E_NULL = -1,        /* a required pointer is NULL */
+    MDGMI_E_SHAPE = -2,       /* n < 1, n_snr < 1, dim or M out of range */
+    MDGMI_E_LABELS = -3,      /* labels are not a permutation of [0, M) */
+    MDGMI_E_SIGMA2 = -4,      /* a sigma2 is not finite and > 0 */
+    MDGMI_E_UNSUPPORTED = -5, /* path not available for this dim / M / SNR */
+    MDGMI_E_WORKSPACE = -6,   /* workspace NULL or smaller than required */
+    MDGMI_E_HIP = -7,         /* a HIP runtime call or launch failed */
+    MDGMI_E_DEVICE = -8,      /* current device differs from the format's */
+    MDGMI_E_ARG = -9          /* another argument is out of range */
+} mdgmi_status;
+
+/* Arithmetic of the demapper. The element type of y / LLR follows the path:
+ * double for MDGMI_PATH_F64, float for every other path. */
+typedef enum {
+    MDGMI_PATH_F64 = 0,              /* FP64 throughout, exact per class          */
+    MDGMI_PATH_F32_DIRECT = 1,       /* FP32 distances on the vector ALUs         */
+    MDGMI_PATH_F32_MFMA_F16SPLIT = 2,/* distance term on MFMA, fp16 hi+lo split,  */
+                                     /* FP32 accumulate; log-sum-exp in FP32      */
+    MDGMI_PATH_AUTO = 5              /* fastest FP32 exact path for the shape     */
+} mdgmi_path;
+
+/* Fields of one GMI/MI result row (doubles). */
+enum {
+    MDGMI_F_GMI = 0,       /* GMI estimate, bits per N-dimensional symbol   */
+    MDGMI_F_MI = 1,        /* MI estimate, bits per N-dimensional symbol    */
+    MDGMI_F_SE_GMI = 2,    /* standard error of the GMI estimate            */
+    MDGMI_F_SE_MI = 3,     /* standard error of the MI estimate             */
+    MDGMI_F_N = 4,         /* number of samples                              */
+    MDGMI_F_NONFINITE = 5, /* samples whose GMI or MI cost is NaN or inf    */
+    MDGMI_NFIELDS = 6
+};
+
+#define MDGMI_MAX_BITS 12   /* M <= 4096 */
+
+typedef struct mdgmi_format mdgmi_format;
+
+/* Human-readable text of a status code (static storage). */
+const char* mdgmi_status_string(int status);
+
+/* Host-side check that labels_host[0..M) is a permutation of [0, M).
+ * Returns MDGMI_OK or MDGMI_E_LABELS / MDGMI_E_NULL / MDGMI_E_SHAPE. */
+int mdgmi_validate_labels(const uint32_t* labels_host, int32_t M);
+
+/* Stage a constellation on the current device (once per format).
+ *   X_host      host [M][dim] double: the points, any scale (the channel model
+ *               above applies to them as given; formats are normally scaled
+ *               to unit average energy per N-dimensional symbol).
+ *   labels_host host [M] uint32: labels_host[j] is the m-bit label of row j.
+ *   M           2^m with 1 <= m <= MDGMI_MAX_BITS;  dim in {2, 4, 8}.
+ * On success *out receives a handle owning device memory; release it with
+ * mdgmi_format_destroy. Synchronous. */
+int mdgmi_format_create(const double* X_host, const uint32_t* labels_host, int32_t M, int32_t dim,
+                        mdgmi_format** out);
+int mdgmi_format_destroy(mdgmi_format* fmt);
+
+/* Seeded channel samples (the Monte-Carlo input), generated on the device.
+ * For SNR slot q (0 <= q < n_snr) and sample s (0 <= s < n) it draws, with
+ * Philox-4x32-10 (Salmon et al., SC'11) keyed by `seed` and counter
+ * (s mod 2^32, s / 2^32, snr_slot0 + q, call):
+ *   call 0, word 0    -> transmitted row i = word >> (32 - m)
+ *   calls 1..2        -> N(0,1) deviates by Box-Muller from word pairs,
+ *                        u = (word + 1/2) 2^-32
+ * and writes y[q][s][:] = x_i + sqrt(sigma2_host[q]) * z (computed in FP64,
+ * stored as double if y_is_f64 else float) and tx_idx[q][s] = i.
+ *   y       device [n_snr][n][dim];   tx_idx  device [n_snr][n] uint32. */
+int mdgmi_generate(const mdgmi_format* fmt, uint64_t seed, const double* sigma2_host, int32_t n_snr,
+                   int64_t n, int32_t snr_slot0, void* y, uint32_t* tx_idx, int32_t y_is_f64,
+                   void* stream);
+
+/* Bytes of workspace mdgmi_llr needs for n samples on `path`. */
+int mdgmi_llr_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t path, size_t* bytes);
+
+/* Exact per-bit LLRs of n samples at one noise variance.
+ *   y    device [n][dim] (double for MDGMI_PATH_F64, else float)
+ *   llr  device [n][m]   (same element type), nats, column k = label bit k
+ *   ws   device workspace of at least mdgmi_llr_workspace_size bytes. */
+int mdgmi_llr(const mdgmi_format* fmt, const void* y, int64_t n, double sigma2, void* llr,
+              int32_t path, void* ws, size_t ws_bytes, void* stream);
+
+/* Bytes of workspace mdgmi_gmi needs. */
+int mdgmi_gmi_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, int32_t path,
+                             size_t* bytes);
+
+/* GMI and MI estimates for n_snr SNR points of n samples each.
+ *   y           device [n_snr][n][dim] (double for MDGMI_PATH_F64, else float)
+ *   tx_idx      device [n_snr][n] uint32, the transmitted rows of X
+ *   sigma2_host host [n_snr] noise variance per real dimension
+ *   out         device [n_snr][MDGMI_NFIELDS] double
+ * The FP64 sum over samples is reduced in a fixed order: identical inputs
+ * give bit-identical outputs. NaN in y gives NaN estimates for that SNR and
+ * is counted in MDGMI_F_NONFINITE. */
+int mdgmi_gmi(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int64_t n,
+              const double* sigma2_host, int32_t n_snr, int32_t path, double* out, void* ws,
+              size_t ws_bytes, void* stream);
+
+/* Launch-shape override of the MFMA path for tuning sweeps: variant v in
+ * 0..3 selects (sample columns per wave, waves per block) = (1,4), (2,4),
+ * (1,8), (2,8); v < 0 restores the built-in choice. Process-wide; affects
+ * workspace sizes, so set it before sizing workspaces. Always MDGMI_OK. */
+int mdgmi_set_tuning(int mfma_variant);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDGMI_H */

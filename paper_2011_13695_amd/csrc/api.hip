@@ -1,0 +1,306 @@
+// C ABI of libmdgmi: argument checks on the host, format staging, workspace
+// carving and kernel dispatch. Every check happens before the first launch.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+
+namespace mdgmi {
+
+int device_cu_count() {
+    static std::mutex mu;
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> g(mu);
+    if (cache[dev] == 0) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
+            cu = 256;
+        cache[dev] = cu;
+    }
+    return cache[dev];
+}
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int check_device(const mdgmi_format* f) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return MDGMI_E_HIP;
+    return dev == f->device ? MDGMI_OK : MDGMI_E_DEVICE;
+}
+
+// Resolve MDGMI_PATH_AUTO and check that the path can serve the format at
+// the largest s = log2(e) / (2 sigma2) of the call.
+int resolve_path(const mdgmi_format* f, int path, double max_s, int* out) {
+    switch (path) {
+        case MDGMI_PATH_F64:
+        case MDGMI_PATH_F32_DIRECT:
+            *out = path;
+            return MDGMI_OK;
+        case MDGMI_PATH_F32_MFMA_F16SPLIT:
+            if (!mfma_supported(f, max_s)) return MDGMI_E_UNSUPPORTED;
+            *out = path;
+            return MDGMI_OK;
+        case MDGMI_PATH_AUTO:
+            *out = (f->M >= 32 && mfma_supported(f, max_s)) ? MDGMI_PATH_F32_MFMA_F16SPLIT : MDGMI_PATH_F32_DIRECT;
+            return MDGMI_OK;
+        default:
+            return MDGMI_E_ARG;
+    }
+}
+
+double s_of(double sigma2) { return kLog2e / (2.0 * sigma2); }
+
+struct GmiPlan {
+    int path;
+    LaunchCfg cfg;
+    size_t part_bytes, image_bytes, total;
+};
+
+GmiPlan plan_gmi(const mdgmi_format* f, int64_t n, int n_snr, int path) {
+    GmiPlan p{};
+    p.path = path;
+    const int per_launch = std::min(n_snr, kMaxSnrPerLaunch);
+    if (path == MDGMI_PATH_F64) {
+        p.cfg = f64_cfg(f, n);
+        p.image_bytes = 0;
+    } else if (path == MDGMI_PATH_F32_DIRECT) {
+        p.cfg = direct_cfg(f, n);
+        p.image_bytes = direct_image_bytes(f, per_launch);
+    } else {
+        p.cfg = mfma_cfg(f, n, n_snr);
+        p.image_bytes = mfma_image_bytes(f, per_launch);
+    }
+    p.part_bytes = (size_t)n_snr * p.cfg.blocks_per_snr * kNPart * sizeof(double);
+    p.total = align_up(p.part_bytes) + align_up(p.image_bytes);
+    return p;
+}
+
+SnrArgs snr_args(const double* sigma2, int q0, int cnt) {
+    SnrArgs sa{};
+    sa.n_snr = cnt;
+    sa.snr0 = q0;
+    for (int q = 0; q < cnt; q++) {
+        const double s2 = sigma2[q0 + q];
+        sa.s64[q] = s_of(s2);
+        sa.s32[q] = (float)sa.s64[q];
+        sa.inv2s2[q] = 1.0 / (2.0 * s2);
+    }
+    return sa;
+}
+
+}  // namespace
+}  // namespace mdgmi
+
+using namespace mdgmi;
+
+extern "C" {
+
+const char* mdgmi_status_string(int status) {
+    switch (status) {
+        case MDGMI_OK: return "ok";
+        case MDGMI_E_NULL: return "a required pointer is NULL";
+        case MDGMI_E_SHAPE: return "n, n_snr, dim or M out of range";
+        case MDGMI_E_LABELS: return "labels are not a permutation of [0, M)";
+        case MDGMI_E_SIGMA2: return "sigma2 must be finite and > 0";
+        case MDGMI_E_UNSUPPORTED: return "path not available for this format / SNR";
+        case MDGMI_E_WORKSPACE: return "workspace missing or too small";
+        case MDGMI_E_HIP: return "HIP runtime error";
+        case MDGMI_E_DEVICE: return "current device differs from the format's device";
+        case MDGMI_E_ARG: return "argument out of range";
+        default: return "unknown status";
+    }
+}
+
+int mdgmi_validate_labels(const uint32_t* labels_host, int32_t M) {
+    if (!labels_host) return MDGMI_E_NULL;
+    if (M < 1 || M > (1 << MDGMI_MAX_BITS)) return MDGMI_E_SHAPE;
+    std::vector<uint8_t> seen((size_t)M, 0);
+    for (int32_t j = 0; j < M; j++) {
+        uint32_t l = labels_host[j];
+        if (l >= (uint32_t)M || seen[l]) return MDGMI_E_LABELS;
+        seen[l] = 1;
+    }
+    return MDGMI_OK;
+}
+
+int mdgmi_format_create(const double* X_host, const uint32_t* labels_host, int32_t M, int32_t dim,
+                        mdgmi_format** out) {
+    if (!X_host || !labels_host || !out) return MDGMI_E_NULL;
+    *out = nullptr;
+    if (dim != 2 && dim != 4 && dim != 8) return MDGMI_E_SHAPE;
+    if (M < 2 || M > (1 << MDGMI_MAX_BITS) || (M & (M - 1)) != 0) return MDGMI_E_SHAPE;
+    int rc = mdgmi_validate_labels(labels_host, M);
+    if (rc != MDGMI_OK) return rc;
+    for (size_t i = 0; i < (size_t)M * dim; i++)
+        if (!std::isfinite(X_host[i])) return MDGMI_E_ARG;
+    mdgmi_format* f = new mdgmi_format();
+    f->M = M;
+    f->dim = dim;
+    f->m = 0;
+    while ((1 << f->m) < M) f->m++;
+    if (hipGetDevice(&f->device) != hipSuccess) {
+        delete f;
+        return MDGMI_E_HIP;
+    }
+    std::vector<double> X64((size_t)M * dim);
+    std::vector<float> X32((size_t)M * dim), n32((size_t)M);
+    for (int32_t r = 0; r < M; r++) {
+        const uint32_t slot = labels_host[r];
+        double n2 = 0.0;
+        for (int d = 0; d < dim; d++) {
+            const double x = X_host[(size_t)r * dim + d];
+            X64[(size_t)slot * dim + d] = x;
+            X32[(size_t)slot * dim + d] = (float)x;
+            n2 += x * x;
+            f->max_abs = std::max(f->max_abs, std::fabs(x));
+        }
+        n32[slot] = (float)n2;
+        f->max_norm2 = std::max(f->max_norm2, n2);
+    }
+    f->h_X64 = new double[(size_t)M * dim];
+    std::memcpy(f->h_X64, X64.data(), sizeof(double) * X64.size());
+    bool ok = hipMalloc(&f->d_X64, sizeof(double) * X64.size()) == hipSuccess &&
+              hipMalloc(&f->d_X32, sizeof(float) * X32.size()) == hipSuccess &&
+              hipMalloc(&f->d_n32, sizeof(float) * n32.size()) == hipSuccess &&
+              hipMalloc(&f->d_labels, sizeof(uint32_t) * (size_t)M) == hipSuccess;
+    ok = ok && hipMemcpy(f->d_X64, X64.data(), sizeof(double) * X64.size(), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(f->d_X32, X32.data(), sizeof(float) * X32.size(), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(f->d_n32, n32.data(), sizeof(float) * n32.size(), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(f->d_labels, labels_host, sizeof(uint32_t) * (size_t)M, hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        mdgmi_format_destroy(f);
+        return MDGMI_E_HIP;
+    }
+    *out = f;
+    return MDGMI_OK;
+}
+
+int mdgmi_format_destroy(mdgmi_format* f) {
+    if (!f) return MDGMI_E_NULL;
+    if (f->d_X64) (void)hipFree(f->d_X64);
+    if (f->d_X32) (void)hipFree(f->d_X32);
+    if (f->d_n32) (void)hipFree(f->d_n32);
+    if (f->d_labels) (void)hipFree(f->d_labels);
+    delete[] f->h_X64;
+    delete f;
+    return MDGMI_OK;
+}
+
+int mdgmi_generate(const mdgmi_format* fmt, uint64_t seed, const double* sigma2_host, int32_t n_snr, int64_t n,
+                   int32_t snr_slot0, void* y, uint32_t* tx_idx, int32_t y_is_f64, void* stream) {
+    if (!fmt || !sigma2_host || !y || !tx_idx) return MDGMI_E_NULL;
+    if (n < 1 || n_snr < 1) return MDGMI_E_SHAPE;
+    if (snr_slot0 < 0) return MDGMI_E_ARG;
+    for (int q = 0; q < n_snr; q++)
+        if (!finite_pos(sigma2_host[q])) return MDGMI_E_SIGMA2;
+    int rc = check_device(fmt);
+    if (rc != MDGMI_OK) return rc;
+    hipError_t e = launch_generate(fmt, seed, sigma2_host, n_snr, n, snr_slot0, y, tx_idx, y_is_f64 != 0,
+                                   (hipStream_t)stream);
+    return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+}
+
+int mdgmi_llr_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t path, size_t* bytes) {
+    if (!fmt || !bytes) return MDGMI_E_NULL;
+    if (n < 1) return MDGMI_E_SHAPE;
+    int p = path == MDGMI_PATH_AUTO ? (fmt->M >= 32 ? MDGMI_PATH_F32_MFMA_F16SPLIT : MDGMI_PATH_F32_DIRECT) : path;
+    if (p == MDGMI_PATH_F64)
+        *bytes = 0;
+    else if (p == MDGMI_PATH_F32_DIRECT)
+        *bytes = align_up(direct_image_bytes(fmt, 1));
+    else if (p == MDGMI_PATH_F32_MFMA_F16SPLIT)
+        *bytes = align_up(std::max(mfma_image_bytes(fmt, 1), direct_image_bytes(fmt, 1)));
+    else
+        return MDGMI_E_ARG;
+    return MDGMI_OK;
+}
+
+int mdgmi_llr(const mdgmi_format* fmt, const void* y, int64_t n, double sigma2, void* llr, int32_t path, void* ws,
+              size_t ws_bytes, void* stream) {
+    if (!fmt || !y || !llr) return MDGMI_E_NULL;
+    if (n < 1) return MDGMI_E_SHAPE;
+    if (!finite_pos(sigma2)) return MDGMI_E_SIGMA2;
+    int p = 0;
+    int rc = resolve_path(fmt, path, s_of(sigma2), &p);
+    if (rc != MDGMI_OK) return rc;
+    size_t need = 0;
+    rc = mdgmi_llr_workspace_size(fmt, n, p, &need);
+    if (rc != MDGMI_OK) return rc;
+    if (need > 0 && (!ws || ws_bytes < need)) return MDGMI_E_WORKSPACE;
+    rc = check_device(fmt);
+    if (rc != MDGMI_OK) return rc;
+    SnrArgs sa = snr_args(&sigma2, 0, 1);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (p == MDGMI_PATH_F64) {
+        e = launch_f64(fmt, (const double*)y, nullptr, n, sa, true, (double*)llr, nullptr, f64_cfg(fmt, n), st);
+    } else if (p == MDGMI_PATH_F32_DIRECT) {
+        e = launch_direct(fmt, (const float*)y, nullptr, n, sa, true, (float*)llr, nullptr, (float*)ws,
+                          direct_cfg(fmt, n), st);
+    } else {
+        e = launch_mfma(fmt, (const float*)y, nullptr, n, sa, true, (float*)llr, nullptr, ws, mfma_cfg(fmt, n, 1),
+                        st);
+    }
+    return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+}
+
+int mdgmi_gmi_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, int32_t path, size_t* bytes) {
+    if (!fmt || !bytes) return MDGMI_E_NULL;
+    if (n < 1 || n_snr < 1) return MDGMI_E_SHAPE;
+    int p = path;
+    if (p == MDGMI_PATH_AUTO) p = fmt->M >= 32 ? MDGMI_PATH_F32_MFMA_F16SPLIT : MDGMI_PATH_F32_DIRECT;
+    if (p != MDGMI_PATH_F64 && p != MDGMI_PATH_F32_DIRECT && p != MDGMI_PATH_F32_MFMA_F16SPLIT) return MDGMI_E_ARG;
+    GmiPlan pl = plan_gmi(fmt, n, n_snr, p);
+    // AUTO may fall back to the direct path at run time; size for the larger.
+    if (path == MDGMI_PATH_AUTO) pl.total = std::max(pl.total, plan_gmi(fmt, n, n_snr, MDGMI_PATH_F32_DIRECT).total);
+    *bytes = pl.total;
+    return MDGMI_OK;
+}
+
+int mdgmi_gmi(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int64_t n, const double* sigma2_host,
+              int32_t n_snr, int32_t path, double* out, void* ws, size_t ws_bytes, void* stream) {
+    if (!fmt || !y || !tx_idx || !sigma2_host || !out) return MDGMI_E_NULL;
+    if (n < 1 || n_snr < 1) return MDGMI_E_SHAPE;
+    double max_s = 0.0;
+    for (int q = 0; q < n_snr; q++) {
+        if (!finite_pos(sigma2_host[q])) return MDGMI_E_SIGMA2;
+        max_s = std::max(max_s, s_of(sigma2_host[q]));
+    }
+    int p = 0;
+    int rc = resolve_path(fmt, path, max_s, &p);
+    if (rc != MDGMI_OK) return rc;
+    GmiPlan pl = plan_gmi(fmt, n, n_snr, p);
+    if (!ws || ws_bytes < pl.total) return MDGMI_E_WORKSPACE;
+    rc = check_device(fmt);
+    if (rc != MDGMI_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    double* part = (double*)ws;
+    void* image = (char*)ws + align_up(pl.part_bytes);
+    for (int q0 = 0; q0 < n_snr; q0 += kMaxSnrPerLaunch) {
+        const int cnt = std::min(kMaxSnrPerLaunch, n_snr - q0);
+        SnrArgs sa = snr_args(sigma2_host, q0, cnt);
+        double* pq = part + (size_t)q0 * pl.cfg.blocks_per_snr * kNPart;
+        hipError_t e;
+        if (p == MDGMI_PATH_F64)
+            e = launch_f64(fmt, (const double*)y, tx_idx, n, sa, false, nullptr, pq, pl.cfg, st);
+        else if (p == MDGMI_PATH_F32_DIRECT)
+            e = launch_direct(fmt, (const float*)y, tx_idx, n, sa, false, nullptr, pq, (float*)image, pl.cfg, st);
+        else
+            e = launch_mfma(fmt, (const float*)y, tx_idx, n, sa, false, nullptr, pq, image, pl.cfg, st);
+        if (e != hipSuccess) return MDGMI_E_HIP;
+    }
+    hipError_t e = launch_reduce(part, n_snr, pl.cfg.blocks_per_snr, n, fmt->m, out, st);
+    return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,197 @@
+// Device helpers shared by the demapper kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace mdgmi {
+
+// v_exp_f32 / v_log_f32: base-2 transcendentals of the vector ALU.
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float lg2(float x) { return __builtin_amdgcn_logf(x); }
+
+// log2(1 + 2^x) for every x (base-2 softplus).
+__device__ __forceinline__ float softplus2(float x) {
+    return fmaxf(x, 0.0f) + lg2(1.0f + ex2(-fabsf(x)));
+}
+
+// log2(Sa / Sb) of two class sums, given also lsa = log2 Sa, lsb = log2 Sb.
+// Both logarithms are near the common offset (~kBias), so their difference
+// loses ~1e-5 to cancellation; the ratio form keeps full FP32 accuracy and is
+// used whenever the ratio stays well inside the float range. Sb = 0 gives
+// +inf, Sa = 0 gives -inf, NaN propagates.
+__device__ __forceinline__ float log2_ratio(float Sa, float Sb, float lsa, float lsb) {
+    const float d = lsa - lsb;
+    if (fabsf(d) < 60.0f) return lg2(Sa * __builtin_amdgcn_rcpf(Sb));
+    return d;
+}
+
+// MI cost log2(sum_j 2^(u_j - u_i)) = log2(tot * 2^-u_i) without the
+// cancellation of log2(tot) - u_i: the integer part of u_i is removed exactly
+// with ldexp first. tot >= 2^u_i always (the sent point is in the sum).
+__device__ __forceinline__ float mi_cost2(float tot, float ui) {
+    const float d = lg2(tot) - ui;
+    if (d < 60.0f) {
+        const float fl = floorf(ui);
+        return lg2(ldexpf(tot, -(int)fl)) - (ui - fl);
+    }
+    return d;
+}
+
+// Base-2 GMI cost of one bit, log2(1 + S_nb / S_b), from x = log2(S_nb / S_b).
+// S_nb = 0 gives x = -inf and cost 0; NaN propagates.
+__device__ __forceinline__ float bit_cost2(float x) { return softplus2(x); }
+
+// Class sums of the label bits above a group of G = 1, 2 or 4 consecutive
+// blocks of points (a block is a chunk of consecutive labels; the block
+// index supplies these bits). Inside a group the lowest log2(G) block-index
+// bits are known at compile time; the bits above come from the group index
+// and are applied without branches: each group total is added to the class
+// of each such bit through an FMA with a 0/1 factor formed in scalar
+// registers. Unused high bits accumulate values that are never read.
+template <int G, int MAXHI>
+struct HiAcc {
+    static constexpr int GB = G == 4 ? 2 : (G == 2 ? 1 : 0);
+    float R0[MAXHI > 0 ? MAXHI : 1], R1[MAXHI > 0 ? MAXHI : 1];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int l = 0; l < (MAXHI > 0 ? MAXHI : 1); l++) R0[l] = R1[l] = 0.0f;
+    }
+    // T[i]: total of block G*grp + i.
+    __device__ __forceinline__ void add_group(int grp, const float* T) {
+        if (G == 1 || MAXHI == 0) return;
+        float GT;
+        if (G == 2) {
+            R0[0] += T[0];
+            R1[0] += T[1];
+            GT = T[0] + T[1];
+        } else {
+            R0[0] += T[0] + T[2];
+            R1[0] += T[1] + T[3];
+            const float a = T[0] + T[1], b = T[2] + T[3];
+            R0[1] += a;
+            R1[1] += b;
+            GT = a + b;
+        }
+#pragma unroll
+        for (int l = GB; l < MAXHI; l++) {
+            const uint32_t bit = ((uint32_t)grp >> (l - GB)) & 1u;
+            const float one_if = __uint_as_float(bit * 0x3f800000u);
+            const float one_ifn = __uint_as_float((bit ^ 1u) * 0x3f800000u);
+            R1[l] = fmaf(GT, one_if, R1[l]);
+            R0[l] = fmaf(GT, one_ifn, R0[l]);
+        }
+    }
+};
+
+// Per-lane FP64 accumulators of the Monte-Carlo sums.
+struct CostAcc {
+    double sg = 0.0, sg2 = 0.0, sm = 0.0, sm2 = 0.0, bad = 0.0;
+    __device__ __forceinline__ void add(double cg, double cm) {
+        sg += cg;
+        sg2 += cg * cg;
+        sm += cm;
+        sm2 += cm * cm;
+        bool fin = (cg - cg == 0.0) && (cm - cm == 0.0);  // false for NaN and inf
+        bad += fin ? 0.0 : 1.0;
+    }
+};
+
+// Fixed-order reduction of the five partials over a block; thread 0 writes
+// them to dst[0..4]. The shuffle tree and the per-wave order are fixed, so
+// the result does not depend on scheduling.
+__device__ inline void block_reduce_store(CostAcc a, double* dst) {
+    __shared__ double red[16][kNPart];
+    double v[kNPart] = {a.sg, a.sg2, a.sm, a.sm2, a.bad};
+#pragma unroll
+    for (int q = 0; q < kNPart; q++) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
+    }
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < kNPart; q++) red[wave][q] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int nw = (blockDim.x + 63) >> 6;
+        for (int q = 0; q < kNPart; q++) {
+            double s = 0.0;
+            for (int w = 0; w < nw; w++) s += red[w][q];
+            dst[q] = s;
+        }
+    }
+}
+
+// Exact per-class evaluation of one sample in FP32, used when a class sum
+// taken relative to the common offset could have lost terms to underflow
+// (a class more than about 2*kBias log2-units away from y) or when the sent
+// point itself is that far. Each class gets its own reference: its nearest
+// point. t_j = s * ||y - x_j||^2 in log2 units, computed directly.
+// Outputs: lsb[k] = log2 sum_{j in class(k,b)} 2^-t_j  (k < m, b = 0, 1),
+//          ltot = log2 sum_j 2^-t_j,  ti = t of slot `sent` (if sent >= 0).
+template <int DIM>
+__device__ inline void exact_classes_f32(const float* yv, const float* __restrict__ X32, int M, int m,
+                                         float s, int sent, float* ls0, float* ls1, float& ltot, float& ti) {
+    float cmin0[MDGMI_MAX_BITS], cmin1[MDGMI_MAX_BITS];
+    float tmin = INFINITY;
+#pragma unroll
+    for (int k = 0; k < MDGMI_MAX_BITS; k++) cmin0[k] = cmin1[k] = INFINITY;
+    for (int j = 0; j < M; j++) {
+        float d = 0.0f;
+#pragma unroll
+        for (int q = 0; q < DIM; q++) {
+            float e = yv[q] - X32[j * DIM + q];
+            d = fmaf(e, e, d);
+        }
+        float t = s * d;
+        tmin = fminf(tmin, t);
+#pragma unroll
+        for (int k = 0; k < MDGMI_MAX_BITS; k++) {
+            if (k < m) {
+                if ((j >> k) & 1)
+                    cmin1[k] = fminf(cmin1[k], t);
+                else
+                    cmin0[k] = fminf(cmin0[k], t);
+            }
+        }
+        if (j == sent) ti = t;
+    }
+    float S0[MDGMI_MAX_BITS], S1[MDGMI_MAX_BITS];
+    float tot = 0.0f;
+#pragma unroll
+    for (int k = 0; k < MDGMI_MAX_BITS; k++) S0[k] = S1[k] = 0.0f;
+    for (int j = 0; j < M; j++) {
+        float d = 0.0f;
+#pragma unroll
+        for (int q = 0; q < DIM; q++) {
+            float e = yv[q] - X32[j * DIM + q];
+            d = fmaf(e, e, d);
+        }
+        float t = s * d;
+        tot += ex2(tmin - t);
+#pragma unroll
+        for (int k = 0; k < MDGMI_MAX_BITS; k++) {
+            if (k < m) {
+                if ((j >> k) & 1)
+                    S1[k] += ex2(cmin1[k] - t);
+                else
+                    S0[k] += ex2(cmin0[k] - t);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < MDGMI_MAX_BITS; k++) {
+        if (k < m) {
+            ls0[k] = lg2(S0[k]) - cmin0[k];
+            ls1[k] = lg2(S1[k]) - cmin1[k];
+        }
+    }
+    ltot = lg2(tot) - tmin;
+}
+
+}  // namespace mdgmi

@@ -1,0 +1,78 @@
+// Internal declarations of libmdgmi (HIP, gfx950). Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstddef>
+
+#include "../../include/mdgmi.h"
+
+struct mdgmi_format {
+    int32_t M = 0, dim = 0, m = 0;
+    int device = 0;
+    // Label-ordered copies: slot j holds the point whose label is j, so the
+    // label bits of a slot are the bits of its index.
+    double* d_X64 = nullptr;      // [M][dim]
+    float* d_X32 = nullptr;       // [M][dim]
+    float* d_n32 = nullptr;       // [M] ||x||^2
+    uint32_t* d_labels = nullptr; // [M] caller row -> label (= slot)
+    double max_abs = 0.0;         // max_j,d |x_jd|
+    double max_norm2 = 0.0;       // max_j ||x_j||^2
+    double* h_X64 = nullptr;      // host copy, label-ordered [M][dim]
+};
+
+namespace mdgmi {
+
+constexpr int kNPart = 5;           // per-block FP64 partials: sum cG, sum cG^2, sum cM, sum cM^2, nonfinite
+constexpr int kMaxSnrPerLaunch = 32;
+// Exponents are taken relative to a fixed offset: e_j = 2^(kBias - t_j) with
+// t_j = ||y - x_j||^2 / (2 sigma2) * log2(e) >= 0, so no term can overflow
+// (M * 2^kBias < 2^128) and any class whose nearest point lies within
+// 2 * kBias of y is summed without underflow.
+constexpr float kBias = 100.0f;
+constexpr float kFarLog2 = -100.0f;  // class sums below 2^-100 take the per-class path
+constexpr double kLog2e = 1.4426950408889634;
+constexpr double kLn2 = 0.6931471805599453;
+
+struct SnrArgs {
+    int n_snr;                 // SNR points in this launch
+    int snr0;                  // index of the first one in the caller's arrays
+    float s32[kMaxSnrPerLaunch];   // s = log2(e) / (2 sigma2)
+    double s64[kMaxSnrPerLaunch];
+    double inv2s2[kMaxSnrPerLaunch];  // 1 / (2 sigma2)
+};
+
+struct LaunchCfg {
+    int blocks_per_snr;
+    int threads;
+};
+
+// ---- launchers (each in the .hip file holding the kernel) ----
+hipError_t launch_generate(const mdgmi_format* f, uint64_t seed, const double* sigma2, int n_snr,
+                           int64_t n, int snr_slot0, void* y, uint32_t* tx, bool f64, hipStream_t st);
+
+LaunchCfg f64_cfg(const mdgmi_format* f, int64_t n);
+hipError_t launch_f64(const mdgmi_format* f, const double* y, const uint32_t* tx, int64_t n,
+                      const SnrArgs& sa, bool llr_mode, double* llr, double* part, LaunchCfg cfg,
+                      hipStream_t st);
+
+LaunchCfg direct_cfg(const mdgmi_format* f, int64_t n);
+size_t direct_image_bytes(const mdgmi_format* f, int n_snr);
+hipError_t launch_direct(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
+                         const SnrArgs& sa, bool llr_mode, float* llr, double* part, float* image,
+                         LaunchCfg cfg, hipStream_t st);
+
+bool mfma_supported(const mdgmi_format* f, double max_s);
+LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr);
+size_t mfma_image_bytes(const mdgmi_format* f, int n_snr);
+hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
+                       const SnrArgs& sa, bool llr_mode, float* llr, double* part, void* image,
+                       LaunchCfg cfg, hipStream_t st);
+
+hipError_t launch_reduce(const double* part, int n_snr, int blocks_per_snr, int64_t n, int m,
+                         double* out, hipStream_t st);
+
+int device_cu_count();
+
+}  // namespace mdgmi

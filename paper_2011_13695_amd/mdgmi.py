@@ -1,0 +1,213 @@
+"""Thin ctypes binding of libmdgmi (include/mdgmi.h), same names as the C ABI.
+
+Argument marshalling only: torch tensors supply device pointers and the
+current HIP stream; every step of the computation runs in the library's HIP
+kernels. Importing this module never falls back to anything else: if the
+shared library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import re
+from pathlib import Path
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().with_name("libmdgmi.so")
+HEADER = Path(__file__).resolve().parents[1] / "include" / "mdgmi.h"
+
+MDGMI_OK = 0
+MDGMI_E_NULL = -1
+MDGMI_E_SHAPE = -2
+MDGMI_E_LABELS = -3
+MDGMI_E_SIGMA2 = -4
+MDGMI_E_UNSUPPORTED = -5
+MDGMI_E_WORKSPACE = -6
+MDGMI_E_HIP = -7
+MDGMI_E_DEVICE = -8
+MDGMI_E_ARG = -9
+
+MDGMI_PATH_F64 = 0
+MDGMI_PATH_F32_DIRECT = 1
+MDGMI_PATH_F32_MFMA_F16SPLIT = 2
+MDGMI_PATH_AUTO = 5
+PATHS = {"f64": MDGMI_PATH_F64, "direct": MDGMI_PATH_F32_DIRECT,
+         "mfma": MDGMI_PATH_F32_MFMA_F16SPLIT, "auto": MDGMI_PATH_AUTO}
+
+MDGMI_NFIELDS = 6
+FIELDS = ("gmi", "mi", "se_gmi", "se_mi", "n", "n_nonfinite")
+
+
+class MdgmiError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        self.code = code
+        super().__init__(f"{fn}: {mdgmi_status_string(code)} ({code})")
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def lib():
+    """Load libmdgmi.so (built in-tree by paper_2011_13695_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2011_13695_amd.build`")
+        L = ctypes.CDLL(str(LIB_PATH))
+        L.mdgmi_status_string.restype = ctypes.c_char_p
+        L.mdgmi_status_string.argtypes = [ctypes.c_int]
+        L.mdgmi_validate_labels.argtypes = [_P, ctypes.c_int32]
+        L.mdgmi_format_create.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]
+        L.mdgmi_format_destroy.argtypes = [_P]
+        L.mdgmi_generate.argtypes = [_P, ctypes.c_uint64, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                     _P, _P, ctypes.c_int32, _P]
+        L.mdgmi_llr_workspace_size.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+        L.mdgmi_llr.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_double, _P, ctypes.c_int32, _P, ctypes.c_size_t, _P]
+        L.mdgmi_gmi_workspace_size.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_size_t)]
+        L.mdgmi_gmi.argtypes = [_P, _P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int32, _P, _P,
+                                ctypes.c_size_t, _P]
+        L.mdgmi_set_tuning.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def declared_functions() -> list[str]:
+    """Names of the functions include/mdgmi.h declares."""
+    text = HEADER.read_text()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w[\w\s\*]*?\b(mdgmi_\w+)\s*\(", text, re.M)))
+
+
+def _check(fn: str, code: int):
+    if code != MDGMI_OK:
+        raise MdgmiError(fn, code)
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _path(path) -> int:
+    return PATHS[path] if isinstance(path, str) else int(path)
+
+
+def mdgmi_status_string(code: int) -> str:
+    return lib().mdgmi_status_string(int(code)).decode()
+
+
+def mdgmi_validate_labels(labels) -> int:
+    lab = np.ascontiguousarray(labels, dtype=np.uint32)
+    return int(lib().mdgmi_validate_labels(lab.ctypes.data_as(_P), lab.size))
+
+
+def mdgmi_set_tuning(mfma_variant: int) -> None:
+    lib().mdgmi_set_tuning(int(mfma_variant))
+
+
+class Format:
+    """An mdgmi_format handle: a constellation staged on the current device."""
+
+    def __init__(self, X, labels):
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        lab = np.ascontiguousarray(labels, dtype=np.uint32)
+        self.M, self.dim = X.shape
+        self.m = int(self.M).bit_length() - 1
+        h = _P()
+        _check("mdgmi_format_create",
+               lib().mdgmi_format_create(X.ctypes.data_as(_P), lab.ctypes.data_as(_P), self.M, self.dim,
+                                         ctypes.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def of(cls, fmt):
+        """From a workloads.Format (or anything with X and labels)."""
+        return cls(fmt.X, fmt.labels)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mdgmi_format_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mdgmi_generate(fmt: Format, seed: int, sigma2, n: int, snr_slot0: int = 0, y=None, tx_idx=None,
+                   dtype=None, stream=None):
+    """Seeded channel samples on the device: returns (y [n_snr, n, dim], tx [n_snr, n])."""
+    import torch
+    s2 = np.ascontiguousarray(np.atleast_1d(sigma2), dtype=np.float64)
+    n_snr = s2.size
+    dtype = dtype or (y.dtype if y is not None else torch.float32)
+    if y is None:
+        y = torch.empty((n_snr, n, fmt.dim), dtype=dtype, device="cuda")
+    if tx_idx is None:
+        tx_idx = torch.empty((n_snr, n), dtype=torch.int32, device="cuda")
+    assert y.is_contiguous() and tx_idx.is_contiguous() and y.dtype in (torch.float32, torch.float64)
+    assert tuple(y.shape) == (n_snr, n, fmt.dim) and tuple(tx_idx.shape) == (n_snr, n)
+    _check("mdgmi_generate",
+           lib().mdgmi_generate(fmt.handle, int(seed) & 0xFFFFFFFFFFFFFFFF, s2.ctypes.data_as(_P), n_snr, n,
+                                snr_slot0, _dptr(y), _dptr(tx_idx), int(y.dtype == torch.float64),
+                                _stream(stream)))
+    return y, tx_idx
+
+
+def mdgmi_llr_workspace_size(fmt: Format, n: int, path="auto") -> int:
+    b = ctypes.c_size_t()
+    _check("mdgmi_llr_workspace_size", lib().mdgmi_llr_workspace_size(fmt.handle, n, _path(path), ctypes.byref(b)))
+    return int(b.value)
+
+
+def mdgmi_gmi_workspace_size(fmt: Format, n: int, n_snr: int, path="auto") -> int:
+    b = ctypes.c_size_t()
+    _check("mdgmi_gmi_workspace_size",
+           lib().mdgmi_gmi_workspace_size(fmt.handle, n, n_snr, _path(path), ctypes.byref(b)))
+    return int(b.value)
+
+
+def workspace(nbytes: int):
+    import torch
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+
+
+def mdgmi_llr(fmt: Format, y, sigma2: float, path="auto", llr=None, ws=None, stream=None):
+    """Per-bit LLRs (nats) of y [n, dim] -> [n, m] (FP64 path: double, else float)."""
+    import torch
+    assert y.is_cuda and y.is_contiguous() and y.shape[-1] == fmt.dim
+    n = y.numel() // fmt.dim
+    p = _path(path)
+    if llr is None:
+        llr = torch.empty((n, fmt.m), dtype=y.dtype, device=y.device)
+    if ws is None:
+        ws = workspace(mdgmi_llr_workspace_size(fmt, n, p))
+    _check("mdgmi_llr", lib().mdgmi_llr(fmt.handle, _dptr(y), n, float(sigma2), _dptr(llr), p, _dptr(ws),
+                                        ws.numel(), _stream(stream)))
+    return llr
+
+
+def mdgmi_gmi(fmt: Format, y, tx_idx, sigma2, path="auto", out=None, ws=None, stream=None):
+    """GMI/MI per SNR: y [n_snr, n, dim], tx [n_snr, n] -> out [n_snr, 6] (double)."""
+    import torch
+    s2 = np.ascontiguousarray(np.atleast_1d(sigma2), dtype=np.float64)
+    n_snr = s2.size
+    assert y.is_cuda and y.is_contiguous() and tx_idx.is_contiguous()
+    n = y.numel() // (fmt.dim * n_snr)
+    assert y.numel() == n_snr * n * fmt.dim and tx_idx.numel() == n_snr * n
+    p = _path(path)
+    if out is None:
+        out = torch.empty((n_snr, MDGMI_NFIELDS), dtype=torch.float64, device=y.device)
+    if ws is None:
+        ws = workspace(mdgmi_gmi_workspace_size(fmt, n, n_snr, p))
+    _check("mdgmi_gmi", lib().mdgmi_gmi(fmt.handle, _dptr(y), _dptr(tx_idx), n, s2.ctypes.data_as(_P), n_snr, p,
+                                        _dptr(out), _dptr(ws), ws.numel(), _stream(stream)))
+    return out
