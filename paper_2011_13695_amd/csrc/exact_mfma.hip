@@ -221,7 +221,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_mfma(
     const int64_t ncoltiles = (n + 32 * NCOL - 1) / (32 * NCOL);
     for (int64_t ct = (int64_t)blockIdx.x * WAVES + wave; ct < ncoltiles; ct += (int64_t)gridDim.x * WAVES) {
         half8 bop[NCOL][NB];
-        float yv[NCOL][DIM], Keff[NCOL];
+        float yv[NCOL][DIM], Kc[NCOL];
         int64_t idx[NCOL];
 #pragma unroll
         for (int c = 0; c < NCOL; c++) {
@@ -234,9 +234,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_mfma(
                 ys2 = fmaf(yv[c][d], yv[c][d], ys2);
             }
             const float K = kBias - s * ys2;
-            _Float16 kh, kl;
-            split16f(K, kh, kl);
-            Keff[c] = (float)kh + (float)kl;
+            Kc[c] = K;
             make_b<DIM>(yv[c], K, h, bop[c]);
         }
         float bank[NCOL][16];
@@ -349,10 +347,27 @@ __global__ __launch_bounds__(WAVES * 64) void k_mfma(
                     const uint32_t row = txs[i];
                     const bool row_ok = row < (uint32_t)M;
                     const uint32_t slot = labels[row_ok ? row : 0u];
-                    // u of the sent point in FP32, with the same K as the MFMA saw
-                    float ui = Keff[c] - s * n32[slot];
+                    // u of the sent point from the very fp16 operands the MFMA saw
+                    // (every product is exact in FP32), so that the MI cost
+                    // log2 sum_j 2^(u_j - u_i) is free of the split rounding
+                    float ui = 0.0f;
+                    {
+                        half8 bb[2][NB];
+                        make_b<DIM>(yv[c], Kc[c], 0, bb[0]);
+                        make_b<DIM>(yv[c], Kc[c], 1, bb[1]);
+                        const int ti = (int)(slot >> 5), pi = (int)(slot & 31);
 #pragma unroll
-                    for (int d = 0; d < DIM; d++) ui = fmaf(2.0f * s * X32[(size_t)slot * DIM + d], yv[c][d], ui);
+                        for (int b = 0; b < NB; b++) {
+#pragma unroll
+                            for (int hh = 0; hh < 2; hh++) {
+                                H8 av, bv;
+                                av.u = A[((ti * NB + b) * 2 + hh) * 32 + pi];
+                                bv.v = bb[hh][b];
+#pragma unroll
+                                for (int q = 0; q < 8; q++) ui = fmaf((float)av.h[q], (float)bv.h[q], ui);
+                            }
+                        }
+                    }
                     float cg = 0.0f, cm;
                     if (ui >= kFarLog2) {
 #pragma unroll

@@ -154,7 +154,9 @@ def test_gmi_parity(orc, name, snrs, path):
     np.testing.assert_array_equal(out[:, 5], ref[:, 5])
     assert np.max(np.abs(out[:, 0] - ref[:, 0])) <= tol, (out[:, 0], ref[:, 0])
     assert np.max(np.abs(out[:, 1] - ref[:, 1])) <= tol, (out[:, 1], ref[:, 1])
-    np.testing.assert_allclose(out[:, 2:4], ref[:, 2:4], rtol=1e-3, atol=1e-6)
+    # SE: the MFMA path's per-sample MI cost carries the fp16-split rounding of
+    # u_i (~1e-4 at 20 dB), which shows where the exact per-sample costs are 0
+    np.testing.assert_allclose(out[:, 2:4], ref[:, 2:4], rtol=1e-3, atol=2e-5)
 
 
 def test_many_snrs_in_one_call(orc):
