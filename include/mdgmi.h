@@ -138,11 +138,68 @@ int mdgmi_gmi(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, in
               const double* sigma2_host, int32_t n_snr, int32_t path, double* out, void* ws,
               size_t ws_bytes, void* stream);
 
+/* ---- ragged batches ------------------------------------------------------
+ * Many (format, SNR, sample count) instances evaluated by one persistent
+ * kernel: the samples of every instance are cut into items of about 2^22
+ * sample*points, a persistent grid pulls items from an atomic counter and
+ * dispatches each to the direct or MFMA code of its (dim, M); per-item FP64
+ * partials are reduced per instance in item order (bit-reproducible). */
+typedef struct {
+    const mdgmi_format* fmt;  /* staged format of this instance (any dim, M)   */
+    const float* y;           /* device [n][dim] float                          */
+    const uint32_t* tx_idx;   /* device [n], the transmitted rows of the format */
+    int64_t n;                /* samples, >= 1                                  */
+    double sigma2;            /* noise variance per real dimension, > 0         */
+} mdgmi_instance;
+
+/* Bytes of workspace mdgmi_gmi_batched needs (host-side planning only). */
+int mdgmi_gmi_batched_workspace_size(const mdgmi_instance* inst_host, int32_t n_inst, int32_t path,
+                                     size_t* bytes);
+
+/* One-shot ragged batch. inst_host: host [n_inst]; out: device
+ * [n_inst][MDGMI_NFIELDS] double, row q for inst_host[q]. path:
+ * MDGMI_PATH_F32_DIRECT, MDGMI_PATH_F32_MFMA_F16SPLIT (every instance needs
+ * M >= 128) or MDGMI_PATH_AUTO (per instance: the autotuner's choice, else
+ * MFMA for M >= 128). The work list is copied into the workspace on `stream`. */
+int mdgmi_gmi_batched(const mdgmi_instance* inst_host, int32_t n_inst, int32_t path, double* out, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* A reusable batch plan: work list and per-instance operand images built
+ * once (device memory owned by the plan; y / tx_idx of every instance must
+ * stay valid while the plan is used). With path AUTO, (dim, M) classes the
+ * autotuner has not seen are tuned first. */
+typedef struct mdgmi_batch mdgmi_batch;
+int mdgmi_batch_create(const mdgmi_instance* inst_host, int32_t n_inst, int32_t path, mdgmi_batch** out);
+/* Evaluate the plan into out (device [n_inst][MDGMI_NFIELDS]). use_graph != 0
+ * replays a hipGraph of the three launches (counter reset, persistent kernel,
+ * reduction), captured on first use for this `out`; else launches directly. */
+int mdgmi_batch_run(mdgmi_batch* b, double* out, int32_t use_graph, void* stream);
+/* Items in the work list, and total sample*points of the batch. */
+int mdgmi_batch_info(const mdgmi_batch* b, int64_t* n_items, int64_t* pairs);
+int mdgmi_batch_destroy(mdgmi_batch* b);
+
+/* ---- autotuner --------------------------------------------------------------
+ * Times the FP32 direct kernel and every MFMA launch variant on synthetic
+ * samples of (dim, M) on the current device and records the fastest; the
+ * table steers MDGMI_PATH_AUTO and batch plans. Rates in sample*points/s. */
+typedef struct {
+    int32_t dim, M;
+    int32_t path;          /* MDGMI_PATH_F32_DIRECT or MDGMI_PATH_F32_MFMA_F16SPLIT */
+    int32_t mfma_variant;  /* fastest MFMA launch variant, -1 if none ran     */
+    double direct_rate, mfma_rate;
+} mdgmi_tune_entry;
+int mdgmi_autotune(int32_t dim, int32_t M, int32_t force, mdgmi_tune_entry* out);
+int mdgmi_tune_lookup(int32_t dim, int32_t M, mdgmi_tune_entry* out);  /* MDGMI_E_ARG if untuned */
+int mdgmi_tune_save(const char* path);   /* JSON */
+int mdgmi_tune_load(const char* path);
+int mdgmi_tune_clear(void);
+
 /* Launch-shape override of the MFMA path for tuning sweeps: variant v in
- * 0..3 selects (sample columns per wave, waves per block) = (1,4), (2,4),
- * (1,8), (2,8); v < 0 restores the built-in choice. Process-wide; affects
+ * 0..5 selects (sample columns per wave, waves per block) = (1,4), (2,4),
+ * (1,8), (2,8), (1,16), (1,12); v < 0 restores the built-in choice. Process-wide; affects
  * workspace sizes, so set it before sizing workspaces. Always MDGMI_OK. */
 int mdgmi_set_tuning(int mfma_variant);
+int mdgmi_get_tuning(void);   /* the current override, -1 if none */
 
 #ifdef __cplusplus
 }

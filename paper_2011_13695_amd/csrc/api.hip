@@ -50,9 +50,15 @@ int resolve_path(const mdgmi_format* f, int path, double max_s, int* out) {
             if (!mfma_supported(f, max_s)) return MDGMI_E_UNSUPPORTED;
             *out = path;
             return MDGMI_OK;
-        case MDGMI_PATH_AUTO:
-            *out = (f->M >= 32 && mfma_supported(f, max_s)) ? MDGMI_PATH_F32_MFMA_F16SPLIT : MDGMI_PATH_F32_DIRECT;
+        case MDGMI_PATH_AUTO: {
+            const bool mfma_ok = f->M >= 32 && mfma_supported(f, max_s);
+            const int t = tuned_path(f->dim, f->M);
+            if (t == MDGMI_PATH_F32_DIRECT || (t == MDGMI_PATH_F32_MFMA_F16SPLIT && mfma_ok))
+                *out = t;
+            else
+                *out = mfma_ok ? MDGMI_PATH_F32_MFMA_F16SPLIT : MDGMI_PATH_F32_DIRECT;
             return MDGMI_OK;
+        }
         default:
             return MDGMI_E_ARG;
     }

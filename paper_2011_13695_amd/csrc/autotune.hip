@@ -1,0 +1,254 @@
+// Autotuner: per (dim, M) it times the FP32 direct kernel and every MFMA
+// launch variant on synthetic samples of that shape on the current device,
+// and records the fastest. The table steers MDGMI_PATH_AUTO calls and the
+// per-instance path of ragged batches; it can be saved to and loaded from a
+// small JSON file ({"arch": ..., "entries": [{"dim", "M", "path",
+// "variant", "direct_rate", "mfma_rate"}, ...]}).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "batch.h"
+#include "internal.h"
+
+namespace mdgmi {
+
+namespace {
+
+std::mutex g_mu;
+std::map<std::pair<int, int>, mdgmi_tune_entry> g_table;
+
+// Synthetic format for timing only: two shells (radius 1 and 1.6) in `dim`
+// dimensions with Box-Muller directions from a fixed xorshift stream, unit
+// average energy, label = index.
+void synth_format(int dim, int M, std::vector<double>& X, std::vector<uint32_t>& lab) {
+    X.assign((size_t)M * dim, 0.0);
+    lab.resize(M);
+    uint64_t st = 0x9E3779B97F4A7C15ull ^ ((uint64_t)dim << 32) ^ (uint64_t)M;
+    auto next = [&]() {
+        st ^= st << 13;
+        st ^= st >> 7;
+        st ^= st << 17;
+        return ((st >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    };
+    double e = 0.0;
+    for (int j = 0; j < M; j++) {
+        double nrm = 0.0;
+        for (int d = 0; d < dim; d += 2) {
+            const double r = std::sqrt(-2.0 * std::log(next())), a = 6.283185307179586 * next();
+            X[(size_t)j * dim + d] = r * std::cos(a);
+            if (d + 1 < dim) X[(size_t)j * dim + d + 1] = r * std::sin(a);
+        }
+        for (int d = 0; d < dim; d++) nrm += X[(size_t)j * dim + d] * X[(size_t)j * dim + d];
+        const double rad = j < M / 2 ? 1.0 : 1.6;
+        for (int d = 0; d < dim; d++) X[(size_t)j * dim + d] *= rad / std::sqrt(nrm);
+        e += rad * rad;
+        lab[j] = (uint32_t)j;
+    }
+    const double sc = 1.0 / std::sqrt(e / M);
+    for (double& v : X) v *= sc;
+}
+
+}  // namespace
+
+int tuned_batch_kind(int dim, int M) {
+    std::lock_guard<std::mutex> g(g_mu);
+    auto it = g_table.find({dim, M});
+    if (it == g_table.end()) return -1;
+    return it->second.path == MDGMI_PATH_F32_MFMA_F16SPLIT ? kKindMfma : kKindDirect;
+}
+
+int tuned_path(int dim, int M) {
+    std::lock_guard<std::mutex> g(g_mu);
+    auto it = g_table.find({dim, M});
+    return it == g_table.end() ? -1 : it->second.path;
+}
+
+int tuned_mfma_variant(int dim, int M) {
+    std::lock_guard<std::mutex> g(g_mu);
+    auto it = g_table.find({dim, M});
+    return it == g_table.end() ? -1 : it->second.mfma_variant;
+}
+
+int64_t tuned_item_pairs() { return kItemPairsDefault; }
+
+}  // namespace mdgmi
+
+using namespace mdgmi;
+
+extern "C" {
+
+int mdgmi_tune_lookup(int32_t dim, int32_t M, mdgmi_tune_entry* out) {
+    if (!out) return MDGMI_E_NULL;
+    std::lock_guard<std::mutex> g(g_mu);
+    auto it = g_table.find({dim, M});
+    if (it == g_table.end()) return MDGMI_E_ARG;
+    *out = it->second;
+    return MDGMI_OK;
+}
+
+int mdgmi_tune_clear(void) {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_table.clear();
+    return MDGMI_OK;
+}
+
+int mdgmi_autotune(int32_t dim, int32_t M, int32_t force, mdgmi_tune_entry* out) {
+    if (dim != 2 && dim != 4 && dim != 8) return MDGMI_E_SHAPE;
+    if (M < 2 || M > (1 << MDGMI_MAX_BITS) || (M & (M - 1))) return MDGMI_E_SHAPE;
+    if (!force) {
+        std::lock_guard<std::mutex> g(g_mu);
+        auto it = g_table.find({dim, M});
+        if (it != g_table.end()) {
+            if (out) *out = it->second;
+            return MDGMI_OK;
+        }
+    }
+    std::vector<double> X;
+    std::vector<uint32_t> lab;
+    synth_format(dim, M, X, lab);
+    mdgmi_format* f = nullptr;
+    int rc = mdgmi_format_create(X.data(), lab.data(), M, dim, &f);
+    if (rc != MDGMI_OK) return rc;
+    // about 2^28 sample*points per timed call, at least 2^14 samples
+    int64_t n = std::max<int64_t>(int64_t(1) << 14, (int64_t(1) << 28) / M);
+    n = std::min<int64_t>(n, int64_t(1) << 22);
+    const double sigma2 = 1.0 / (dim * 10.0);  // 10 dB
+    float* y = nullptr;
+    uint32_t* tx = nullptr;
+    double* o = nullptr;
+    void* ws = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    mdgmi_tune_entry best{};
+    best.dim = dim;
+    best.M = M;
+    best.path = MDGMI_PATH_F32_DIRECT;
+    best.mfma_variant = -1;
+    size_t wsb = 0, t;
+    rc = MDGMI_E_HIP;
+    const int saved_override = mdgmi_get_tuning();
+    do {
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) break;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) break;
+        if (hipMalloc(&y, sizeof(float) * n * dim) != hipSuccess) break;
+        if (hipMalloc(&tx, sizeof(uint32_t) * n) != hipSuccess) break;
+        if (hipMalloc(&o, sizeof(double) * MDGMI_NFIELDS) != hipSuccess) break;
+        if (mdgmi_generate(f, 12345, &sigma2, 1, n, 0, y, tx, 0, st) != MDGMI_OK) break;
+        // workspace for the largest candidate
+        if (mdgmi_gmi_workspace_size(f, n, 1, MDGMI_PATH_F32_DIRECT, &wsb) != MDGMI_OK) break;
+        for (int v = 0; v < kMfmaVariants; v++) {
+            mdgmi_set_tuning(v);
+            if (mdgmi_gmi_workspace_size(f, n, 1, MDGMI_PATH_F32_MFMA_F16SPLIT, &t) == MDGMI_OK) wsb = std::max(wsb, t);
+        }
+        mdgmi_set_tuning(saved_override);
+        if (hipMalloc(&ws, wsb) != hipSuccess) break;
+        auto time_call = [&](int path) -> double {
+            if (mdgmi_gmi(f, y, tx, n, &sigma2, 1, path, o, ws, wsb, st) != MDGMI_OK) return -1.0;
+            float best_ms = 1e30f;
+            for (int r = 0; r < 3; r++) {
+                (void)hipEventRecord(e0, st);
+                if (mdgmi_gmi(f, y, tx, n, &sigma2, 1, path, o, ws, wsb, st) != MDGMI_OK) return -1.0;
+                (void)hipEventRecord(e1, st);
+                if (hipEventSynchronize(e1) != hipSuccess) return -1.0;
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                best_ms = std::min(best_ms, ms);
+            }
+            return (double)n * M / (best_ms * 1e-3);
+        };
+        best.direct_rate = time_call(MDGMI_PATH_F32_DIRECT);
+        double best_rate = best.direct_rate;
+        best.mfma_rate = 0.0;
+        if (M >= 32 && mfma_supported(f, kLog2e / (2.0 * sigma2))) {
+            for (int v = 0; v < kMfmaVariants; v++) {
+                mdgmi_set_tuning(v);
+                const double r = time_call(MDGMI_PATH_F32_MFMA_F16SPLIT);
+                if (r > best.mfma_rate) {
+                    best.mfma_rate = r;
+                    best.mfma_variant = v;
+                }
+            }
+            mdgmi_set_tuning(saved_override);
+            // (the batch kernel still runs MFMA only where M >= 128)
+            if (best.mfma_rate > best_rate) best.path = MDGMI_PATH_F32_MFMA_F16SPLIT;
+        }
+        rc = MDGMI_OK;
+    } while (0);
+    mdgmi_set_tuning(saved_override);
+    if (st) (void)hipStreamSynchronize(st);
+    if (ws) (void)hipFree(ws);
+    if (o) (void)hipFree(o);
+    if (tx) (void)hipFree(tx);
+    if (y) (void)hipFree(y);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    mdgmi_format_destroy(f);
+    if (rc != MDGMI_OK) return rc;
+    {
+        std::lock_guard<std::mutex> g(g_mu);
+        g_table[{dim, M}] = best;
+    }
+    if (out) *out = best;
+    return MDGMI_OK;
+}
+
+int mdgmi_tune_save(const char* path) {
+    if (!path) return MDGMI_E_NULL;
+    FILE* fp = std::fopen(path, "w");
+    if (!fp) return MDGMI_E_ARG;
+    std::lock_guard<std::mutex> g(g_mu);
+    std::fprintf(fp, "{\"arch\": \"gfx950\", \"entries\": [\n");
+    size_t k = 0;
+    for (const auto& kv : g_table) {
+        const mdgmi_tune_entry& e = kv.second;
+        std::fprintf(fp,
+                     "  {\"dim\": %d, \"M\": %d, \"path\": %d, \"variant\": %d, \"direct_rate\": %.6e, "
+                     "\"mfma_rate\": %.6e}%s\n",
+                     e.dim, e.M, e.path, e.mfma_variant, e.direct_rate, e.mfma_rate,
+                     ++k < g_table.size() ? "," : "");
+    }
+    std::fprintf(fp, "]}\n");
+    std::fclose(fp);
+    return MDGMI_OK;
+}
+
+int mdgmi_tune_load(const char* path) {
+    if (!path) return MDGMI_E_NULL;
+    FILE* fp = std::fopen(path, "r");
+    if (!fp) return MDGMI_E_ARG;
+    std::string text;
+    char buf[4096];
+    size_t r;
+    while ((r = std::fread(buf, 1, sizeof(buf), fp)) > 0) text.append(buf, r);
+    std::fclose(fp);
+    if (text.find("\"gfx950\"") == std::string::npos) return MDGMI_E_ARG;
+    int loaded = 0;
+    size_t pos = 0;
+    while ((pos = text.find("{\"dim\"", pos)) != std::string::npos) {
+        mdgmi_tune_entry e{};
+        if (std::sscanf(text.c_str() + pos,
+                        "{\"dim\": %d, \"M\": %d, \"path\": %d, \"variant\": %d, \"direct_rate\": %lf, "
+                        "\"mfma_rate\": %lf}",
+                        &e.dim, &e.M, &e.path, &e.mfma_variant, &e.direct_rate, &e.mfma_rate) == 6) {
+            const bool ok = (e.dim == 2 || e.dim == 4 || e.dim == 8) && e.M >= 2 && e.M <= (1 << MDGMI_MAX_BITS) &&
+                            (e.path == MDGMI_PATH_F32_DIRECT || e.path == MDGMI_PATH_F32_MFMA_F16SPLIT) &&
+                            e.mfma_variant < kMfmaVariants;
+            if (ok) {
+                std::lock_guard<std::mutex> g(g_mu);
+                g_table[{e.dim, e.M}] = e;
+                loaded++;
+            }
+        }
+        pos += 6;
+    }
+    return loaded > 0 ? MDGMI_OK : MDGMI_E_ARG;
+}
+
+}  // extern "C"

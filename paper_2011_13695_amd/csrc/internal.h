@@ -24,6 +24,7 @@ struct mdgmi_format {
 
 namespace mdgmi {
 
+constexpr int kMfmaVariants = 6;     // MFMA launch shapes (see mdgmi_set_tuning)
 constexpr int kNPart = 5;           // per-block FP64 partials: sum cG, sum cG^2, sum cM, sum cM^2, nonfinite
 constexpr int kMaxSnrPerLaunch = 32;
 // Exponents are taken relative to a fixed offset: e_j = 2^(kBias - t_j) with
@@ -74,5 +75,9 @@ hipError_t launch_reduce(const double* part, int n_snr, int blocks_per_snr, int6
                          double* out, hipStream_t st);
 
 int device_cu_count();
+
+// autotuner table (autotune.hip); -1 where (dim, M) is untuned
+int tuned_path(int dim, int M);
+int tuned_mfma_variant(int dim, int M);
 
 }  // namespace mdgmi

@@ -211,3 +211,134 @@ def mdgmi_gmi(fmt: Format, y, tx_idx, sigma2, path="auto", out=None, ws=None, st
     _check("mdgmi_gmi", lib().mdgmi_gmi(fmt.handle, _dptr(y), _dptr(tx_idx), n, s2.ctypes.data_as(_P), n_snr, p,
                                         _dptr(out), _dptr(ws), ws.numel(), _stream(stream)))
     return out
+
+
+# ------------------------------------------------------------------ batches
+class mdgmi_instance(ctypes.Structure):
+    _fields_ = [("fmt", _P), ("y", _P), ("tx_idx", _P), ("n", ctypes.c_int64), ("sigma2", ctypes.c_double)]
+
+
+class mdgmi_tune_entry(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("M", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("mfma_variant", ctypes.c_int32), ("direct_rate", ctypes.c_double), ("mfma_rate", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _batch_sigs():
+    L = lib()
+    if getattr(L, "_batch_sigs", False):
+        return L
+    IP = ctypes.POINTER(mdgmi_instance)
+    L.mdgmi_gmi_batched_workspace_size.argtypes = [IP, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    L.mdgmi_gmi_batched.argtypes = [IP, ctypes.c_int32, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P]
+    L.mdgmi_batch_create.argtypes = [IP, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_P)]
+    L.mdgmi_batch_run.argtypes = [_P, _P, ctypes.c_int32, _P]
+    L.mdgmi_batch_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    L.mdgmi_batch_destroy.argtypes = [_P]
+    L.mdgmi_autotune.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(mdgmi_tune_entry)]
+    L.mdgmi_tune_lookup.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(mdgmi_tune_entry)]
+    L.mdgmi_tune_save.argtypes = [ctypes.c_char_p]
+    L.mdgmi_tune_load.argtypes = [ctypes.c_char_p]
+    L._batch_sigs = True
+    return L
+
+
+def instances(items):
+    """items: sequence of (Format, y [n, dim] float32 tensor, tx [n] tensor, sigma2)."""
+    arr = (mdgmi_instance * len(items))()
+    for q, (f, y, tx, s2) in enumerate(items):
+        assert y.is_contiguous() and tx.is_contiguous() and y.dtype == __import__("torch").float32
+        n = y.numel() // f.dim
+        assert tx.numel() == n
+        arr[q] = mdgmi_instance(f.handle, y.data_ptr(), tx.data_ptr(), n, float(s2))
+    return arr
+
+
+def mdgmi_gmi_batched_workspace_size(inst, path="auto") -> int:
+    L = _batch_sigs()
+    b = ctypes.c_size_t()
+    _check("mdgmi_gmi_batched_workspace_size",
+           L.mdgmi_gmi_batched_workspace_size(inst, len(inst), _path(path), ctypes.byref(b)))
+    return int(b.value)
+
+
+def mdgmi_gmi_batched(inst, path="auto", out=None, ws=None, stream=None):
+    """One-shot ragged batch -> out [n_inst, 6] (double, device)."""
+    import torch
+    L = _batch_sigs()
+    if out is None:
+        out = torch.empty((len(inst), MDGMI_NFIELDS), dtype=torch.float64, device="cuda")
+    if ws is None:
+        ws = workspace(mdgmi_gmi_batched_workspace_size(inst, path))
+    _check("mdgmi_gmi_batched", L.mdgmi_gmi_batched(inst, len(inst), _path(path), _dptr(out), _dptr(ws),
+                                                    ws.numel(), _stream(stream)))
+    return out
+
+
+class Batch:
+    """mdgmi_batch plan handle (keeps the instance tensors alive)."""
+
+    def __init__(self, items, path="auto"):
+        L = _batch_sigs()
+        self._keep = list(items)
+        self.inst = instances(items)
+        h = _P()
+        _check("mdgmi_batch_create", L.mdgmi_batch_create(self.inst, len(self.inst), _path(path), ctypes.byref(h)))
+        self.handle = h
+        self.n_inst = len(self.inst)
+
+    def info(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check("mdgmi_batch_info", lib().mdgmi_batch_info(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return {"items": a.value, "pairs": b.value}
+
+    def run(self, out=None, use_graph=True, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.n_inst, MDGMI_NFIELDS), dtype=torch.float64, device="cuda")
+        _check("mdgmi_batch_run", lib().mdgmi_batch_run(self.handle, _dptr(out), int(bool(use_graph)),
+                                                        _stream(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mdgmi_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mdgmi_autotune(dim: int, M: int, force: bool = False) -> dict:
+    L = _batch_sigs()
+    e = mdgmi_tune_entry()
+    _check("mdgmi_autotune", L.mdgmi_autotune(dim, M, int(force), ctypes.byref(e)))
+    return e.as_dict()
+
+
+def mdgmi_tune_lookup(dim: int, M: int):
+    L = _batch_sigs()
+    e = mdgmi_tune_entry()
+    rc = L.mdgmi_tune_lookup(dim, M, ctypes.byref(e))
+    return e.as_dict() if rc == MDGMI_OK else None
+
+
+def mdgmi_tune_save(path) -> None:
+    _check("mdgmi_tune_save", _batch_sigs().mdgmi_tune_save(str(path).encode()))
+
+
+def mdgmi_tune_load(path) -> None:
+    _check("mdgmi_tune_load", _batch_sigs().mdgmi_tune_load(str(path).encode()))
+
+
+def mdgmi_tune_clear() -> None:
+    lib().mdgmi_tune_clear()
+
+
+def mdgmi_get_tuning() -> int:
+    return int(lib().mdgmi_get_tuning())
