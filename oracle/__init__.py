@@ -120,3 +120,73 @@ def gmi(y, tx_idx, X, labels, sigma2):
 def gmi_per_snr(y, tx_idx, X, labels, sigma2s):
     """Rows of gmi() for y (n_snr, n, N), tx (n_snr, n) and one sigma2 per SNR."""
     return np.stack([gmi(y[s], tx_idx[s], X, labels, s2) for s, s2 in enumerate(sigma2s)])
+
+
+# ---------------------------------------------------------------- MLP demapper
+def _mlp_sigs():
+    L = lib()
+    if getattr(L, "_mlp_sigs", False):
+        return L
+    P = ctypes.c_void_p
+    L.oracle_gelu.restype = ctypes.c_double
+    L.oracle_gelu.argtypes = [ctypes.c_double]
+    L.oracle_mlp_param_count.restype = ctypes.c_int64
+    L.oracle_mlp_param_count.argtypes = [P, ctypes.c_int]
+    L.oracle_mlp_forward.argtypes = [P, P, ctypes.c_int, P, ctypes.c_int64, P]
+    L.oracle_mlp_loss_grad.restype = ctypes.c_double
+    L.oracle_mlp_loss_grad.argtypes = [P, P, ctypes.c_int, P, P, ctypes.c_int64, P]
+    L.oracle_adam.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_double, ctypes.c_double]
+    L.oracle_gmi_cost_from_llr.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, P]
+    L._mlp_sigs = True
+    return L
+
+
+def gelu(x: float) -> float:
+    return float(_mlp_sigs().oracle_gelu(float(x)))
+
+
+def mlp_param_count(sizes) -> int:
+    s = _c(sizes, np.int32)
+    return int(_mlp_sigs().oracle_mlp_param_count(_ptr(s), len(sizes) - 1))
+
+
+def mlp_forward(params, sizes, x):
+    """Logits [n, sizes[-1]] (nats) of inputs x [n, sizes[0]]."""
+    s = _c(sizes, np.int32)
+    p = _c(params, np.float64)
+    assert p.size == mlp_param_count(sizes)
+    x = _c(np.reshape(x, (-1, sizes[0])), np.float64)
+    out = np.empty((x.shape[0], sizes[-1]))
+    rc = _mlp_sigs().oracle_mlp_forward(_ptr(p), _ptr(s), len(sizes) - 1, _ptr(x), x.shape[0], _ptr(out))
+    if rc != 0:
+        raise RuntimeError("oracle_mlp_forward failed")
+    return out
+
+
+def mlp_loss_grad(params, sizes, x, target):
+    """(mean BCE-with-logits loss in nats summed over outputs, gradient [P])."""
+    s = _c(sizes, np.int32)
+    p = _c(params, np.float64)
+    x = _c(np.reshape(x, (-1, sizes[0])), np.float64)
+    t = _c(np.reshape(target, (-1, sizes[-1])), np.float64)
+    g = np.empty_like(p)
+    loss = _mlp_sigs().oracle_mlp_loss_grad(_ptr(p), _ptr(s), len(sizes) - 1, _ptr(x), _ptr(t), x.shape[0], _ptr(g))
+    return float(loss), g
+
+
+def adam(params, grad, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays (step number t >= 1)."""
+    for a in (params, grad, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    _mlp_sigs().oracle_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.size, int(t), float(lr), float(b1),
+                            float(b2), float(eps))
+
+
+def gmi_cost_from_llr(llr, sent_label):
+    """Per-sample GMI cost (bits) of arbitrary LLRs [n, m] for the sent labels."""
+    llr = _c(llr, np.float64)
+    lab = _c(sent_label, np.uint32)
+    out = np.empty(llr.shape[0])
+    _mlp_sigs().oracle_gmi_cost_from_llr(_ptr(llr), _ptr(lab), llr.shape[0], llr.shape[1], _ptr(out))
+    return out

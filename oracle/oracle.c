@@ -223,3 +223,177 @@ int oracle_gmi(const double* y, const uint32_t* tx_idx, int64_t n, int dim, cons
     free(cm);
     return rc;
 }
+
+/* ------------------------------------------------------------------------
+ * MLP demapper oracle (FP64). A fully connected network maps the input
+ * features x (the received sample and an SNR feature) to m logits that are
+ * read as LLRs in nats:
+ *   h_0 = x;  z_l = W_l h_{l-1} + b_l;  h_l = gelu(z_l) for hidden layers,
+ *   logits = z_L (no activation on the output layer).
+ * W_l is [out][in] row-major; parameters are laid out flat as
+ * W_1, b_1, W_2, b_2, ..., W_L, b_L. GELU is the tanh form of Hendrycks &
+ * Gimpel (2016). Loss: binary cross-entropy with logits against target
+ * probabilities p (softplus(z) - p z per bit), summed over bits and
+ * averaged over samples, in nats. Optimiser: Adam (Kingma & Ba, 2015).
+ * ---------------------------------------------------------------------- */
+#define GELU_C 0.79788456080286535588 /* sqrt(2/pi) */
+#define GELU_A 0.044715
+
+double oracle_gelu(double x) {
+    return 0.5 * x * (1.0 + tanh(GELU_C * (x + GELU_A * x * x * x)));
+}
+
+static double gelu_grad(double x) {
+    double u = GELU_C * (x + GELU_A * x * x * x);
+    double t = tanh(u);
+    double du = GELU_C * (1.0 + 3.0 * GELU_A * x * x);
+    return 0.5 * (1.0 + t) + 0.5 * x * (1.0 - t * t) * du;
+}
+
+int64_t oracle_mlp_param_count(const int* sizes, int L) {
+    int64_t p = 0;
+    for (int l = 0; l < L; l++) p += (int64_t)sizes[l + 1] * sizes[l] + sizes[l + 1];
+    return p;
+}
+
+/* Forward of one sample; z and h hold every layer's pre- and post-activation
+ * values (layer l at offset off[l]). */
+static void mlp_forward_one(const double* params, const int* sizes, int L, const double* x, double* z, double* h,
+                            const int64_t* off) {
+    const double* prev = x;
+    const double* p = params;
+    for (int l = 0; l < L; l++) {
+        int in = sizes[l], out = sizes[l + 1];
+        const double* W = p;
+        const double* b = p + (int64_t)out * in;
+        p = b + out;
+        for (int o = 0; o < out; o++) {
+            double s = b[o];
+            for (int i = 0; i < in; i++) s += W[(int64_t)o * in + i] * prev[i];
+            z[off[l] + o] = s;
+            h[off[l] + o] = (l < L - 1) ? oracle_gelu(s) : s;
+        }
+        prev = h + off[l];
+    }
+}
+
+static int64_t* layer_offsets(const int* sizes, int L, int64_t* total) {
+    int64_t* off = (int64_t*)malloc(sizeof(int64_t) * (size_t)L);
+    int64_t t = 0;
+    for (int l = 0; l < L; l++) {
+        off[l] = t;
+        t += sizes[l + 1];
+    }
+    *total = t;
+    return off;
+}
+
+/* logits [n][sizes[L]] of x [n][sizes[0]]. */
+int oracle_mlp_forward(const double* params, const int* sizes, int L, const double* x, int64_t n, double* logits) {
+    int64_t tot;
+    int64_t* off = layer_offsets(sizes, L, &tot);
+    int err = 0;
+#pragma omp parallel
+    {
+        double* z = (double*)malloc(sizeof(double) * (size_t)tot);
+        double* h = (double*)malloc(sizeof(double) * (size_t)tot);
+        if (!z || !h) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t s = 0; s < n; s++) {
+                mlp_forward_one(params, sizes, L, x + s * sizes[0], z, h, off);
+                for (int k = 0; k < sizes[L]; k++) logits[s * sizes[L] + k] = h[off[L - 1] + k];
+            }
+        }
+        free(z);
+        free(h);
+    }
+    free(off);
+    return err ? -1 : 0;
+}
+
+/* Mean BCE-with-logits loss over n samples (summed over outputs) and its
+ * gradient with respect to every parameter (grad [P], overwritten). */
+double oracle_mlp_loss_grad(const double* params, const int* sizes, int L, const double* x, const double* target,
+                            int64_t n, double* grad) {
+    int64_t tot;
+    int64_t* off = layer_offsets(sizes, L, &tot);
+    const int64_t P = oracle_mlp_param_count(sizes, L);
+    const int out_dim = sizes[L];
+    int maxw = 0;
+    for (int l = 0; l <= L; l++)
+        if (sizes[l] > maxw) maxw = sizes[l];
+    for (int64_t i = 0; i < P; i++) grad[i] = 0.0;
+    double loss = 0.0;
+    double* z = (double*)malloc(sizeof(double) * (size_t)tot);
+    double* h = (double*)malloc(sizeof(double) * (size_t)tot);
+    double* d = (double*)malloc(sizeof(double) * (size_t)maxw);   /* dLoss/dz of the current layer */
+    double* dn = (double*)malloc(sizeof(double) * (size_t)maxw);
+    int64_t* poff = (int64_t*)malloc(sizeof(int64_t) * (size_t)L); /* offset of W_l in params */
+    int64_t q = 0;
+    for (int l = 0; l < L; l++) {
+        poff[l] = q;
+        q += (int64_t)sizes[l + 1] * sizes[l] + sizes[l + 1];
+    }
+    for (int64_t s = 0; s < n; s++) {
+        const double* xs = x + s * sizes[0];
+        mlp_forward_one(params, sizes, L, xs, z, h, off);
+        for (int k = 0; k < out_dim; k++) {
+            double zz = z[off[L - 1] + k], p = target[s * out_dim + k];
+            loss += softplus(zz) - p * zz;
+            d[k] = (1.0 / (1.0 + exp(-zz)) - p) / (double)n;
+        }
+        for (int l = L - 1; l >= 0; l--) {
+            int in = sizes[l], out = sizes[l + 1];
+            const double* prev = l > 0 ? h + off[l - 1] : xs;
+            double* gW = grad + poff[l];
+            double* gb = gW + (int64_t)out * in;
+            const double* W = params + poff[l];
+            for (int o = 0; o < out; o++) {
+                gb[o] += d[o];
+                for (int i = 0; i < in; i++) gW[(int64_t)o * in + i] += d[o] * prev[i];
+            }
+            if (l > 0) {
+                for (int i = 0; i < in; i++) {
+                    double acc = 0.0;
+                    for (int o = 0; o < out; o++) acc += W[(int64_t)o * in + i] * d[o];
+                    dn[i] = acc * gelu_grad(z[off[l - 1] + i]);
+                }
+                for (int i = 0; i < in; i++) d[i] = dn[i];
+            }
+        }
+    }
+    free(z);
+    free(h);
+    free(d);
+    free(dn);
+    free(poff);
+    free(off);
+    return loss / (double)n;
+}
+
+/* One Adam step (bias-corrected, step number t >= 1) on P parameters. */
+void oracle_adam(double* params, const double* grad, double* m, double* v, int64_t P, int64_t t, double lr,
+                 double b1, double b2, double eps) {
+    const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+    for (int64_t i = 0; i < P; i++) {
+        m[i] = b1 * m[i] + (1.0 - b1) * grad[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * grad[i] * grad[i];
+        params[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}
+
+/* GMI cost (bits) of given LLRs llr [n][m] for the sent labels. */
+int oracle_gmi_cost_from_llr(const double* llr, const uint32_t* sent_label, int64_t n, int m, double* cost) {
+    for (int64_t s = 0; s < n; s++) {
+        double c = 0.0;
+        for (int k = 0; k < m; k++) {
+            int b = (int)((sent_label[s] >> k) & 1u);
+            c += softplus(-(2.0 * b - 1.0) * llr[s * m + k]);
+        }
+        cost[s] = c / LN2;
+    }
+    return 0;
+}
