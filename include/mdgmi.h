@@ -194,6 +194,46 @@ int mdgmi_tune_save(const char* path);   /* JSON */
 int mdgmi_tune_load(const char* path);
 int mdgmi_tune_clear(void);
 
+/* ---- learned demapper (MLP) ----------------------------------------------
+ * A fully connected network from features x = [y, (SNR_dB - 9.5) / 4.5] to m
+ * logits read as LLRs in nats: z_l = W_l h_(l-1) + b_l, h_l = gelu(z_l) on
+ * hidden layers (tanh form of Hendrycks & Gimpel), logits = z_L. FP32 master
+ * parameters laid out flat as W_1 b_1 W_2 b_2 ... (W_l row-major [out][in]);
+ * bf16 copies feed v_mfma_f32_32x32x16_bf16 GEMMs with FP32 accumulation;
+ * activations and back-propagated gradients are bf16. Training minimises the
+ * binary cross-entropy with logits against p = sigmoid(lambda_exact), summed
+ * over bits and averaged over samples (nats), with Adam on the masters. */
+#define MDGMI_MLP_MAX_LAYERS 8
+typedef struct mdgmi_mlp mdgmi_mlp;
+/* sizes_host[0..n_layers]: widths (input, hidden..., output), each 1..4096.
+ * Initialisation: W, b ~ U(-1/sqrt(fan_in), +1/sqrt(fan_in)) from a 64-bit
+ * Mersenne twister seeded with `seed` (53-bit uniforms). Allocates. */
+int mdgmi_mlp_create(const int32_t* sizes_host, int32_t n_layers, uint64_t seed, mdgmi_mlp** out);
+int mdgmi_mlp_destroy(mdgmi_mlp* net);
+int mdgmi_mlp_param_count(const mdgmi_mlp* net, int64_t* count);
+/* Copy (synchronously) the FP32 masters (which = 0), the last gradient (1) or
+ * the Adam moments (2: first, 3: second) to host [count]. */
+int mdgmi_mlp_get_params(const mdgmi_mlp* net, float* host, int64_t count, int32_t which);
+/* Replace the masters (host [count]) and refresh the bf16 copies; synchronous. */
+int mdgmi_mlp_set_params(mdgmi_mlp* net, const float* host, int64_t count);
+/* Workspace for forward / loss_grad of n samples (activations, gradients). */
+int mdgmi_mlp_workspace_size(const mdgmi_mlp* net, int64_t n, size_t* bytes);
+/* Features: x [n][dim + 1] = [y, (snr_db - 9.5) / 4.5] from y [n][dim] (device). */
+int mdgmi_mlp_features(const float* y, int64_t n, int32_t dim, double snr_db, float* x, void* stream);
+/* logits [n][out] (device float) of x [n][in] (device float). */
+int mdgmi_mlp_forward(const mdgmi_mlp* net, const float* x, int64_t n, float* logits, void* ws, size_t ws_bytes,
+                      void* stream);
+/* Forward + backward: loss (device double, 1 value) and the parameter
+ * gradient, kept inside the network for mdgmi_mlp_adam_step.
+ * target_llr: device [n][out] exact LLRs (targets p = sigmoid(target)). */
+int mdgmi_mlp_loss_grad(mdgmi_mlp* net, const float* x, const float* target_llr, int64_t n, double* loss, void* ws,
+                        size_t ws_bytes, void* stream);
+/* One bias-corrected Adam step on the masters with the last gradient. */
+int mdgmi_mlp_adam_step(mdgmi_mlp* net, float lr, float beta1, float beta2, float eps, void* stream);
+/* Checkpoint: widths, step, masters and both Adam moments (binary). */
+int mdgmi_mlp_save(const mdgmi_mlp* net, const char* path);
+int mdgmi_mlp_load(mdgmi_mlp* net, const char* path);
+
 /* Launch-shape override of the MFMA path for tuning sweeps: variant v in
  * 0..5 selects (sample columns per wave, waves per block) = (1,4), (2,4),
  * (1,8), (2,8), (1,16), (1,12); v < 0 restores the built-in choice. Process-wide; affects

@@ -1,0 +1,484 @@
+// MLP demapper: parameters, training step and inference on the GPU.
+//
+// The network maps features x = [y, (SNR_dB - 9.5) / 4.5] through hidden
+// layers with GELU to m logits read as LLRs in nats. FP32 master weights
+// (flat, [W_1 b_1 W_2 b_2 ...], W_l row-major [out][in]) with bf16 copies of
+// every W_l and W_l^T for the GEMMs; bf16 activations and gradients, FP32
+// accumulation; Adam on the FP32 masters. Loss: binary cross-entropy with
+// logits against targets p = sigmoid(lambda_exact), summed over bits and
+// averaged over samples.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "internal.h"
+#include "mlp_gemm.h"
+
+using mdgmi::mlp::GemmArgs;
+
+struct mdgmi_mlp {
+    int L = 0;
+    int sizes[MDGMI_MLP_MAX_LAYERS + 1] = {0};
+    int64_t P = 0;
+    int64_t woff[MDGMI_MLP_MAX_LAYERS] = {0}, boff[MDGMI_MLP_MAX_LAYERS] = {0};
+    float* d_params = nullptr;  // FP32 masters
+    float* d_m = nullptr;
+    float* d_v = nullptr;
+    float* d_grad = nullptr;
+    __bf16* d_w[MDGMI_MLP_MAX_LAYERS] = {nullptr};   // [out][in]
+    __bf16* d_wt[MDGMI_MLP_MAX_LAYERS] = {nullptr};  // [in][out]
+    int64_t step = 0;
+    int device = 0;
+    int width = 0;  // widest layer
+};
+
+namespace mdgmi {
+namespace {
+
+using namespace mlp;
+
+constexpr int64_t kKSplit = 4096;  // samples per split-K slice of the weight gradients
+
+int64_t al(int64_t v) { return (v + 255) / 256 * 256; }
+
+// ---- elementwise kernels ----
+__global__ void k_to_bf16(const float* __restrict__ x, int64_t cnt, __bf16* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) out[i] = (__bf16)x[i];
+}
+
+__global__ void k_features(const float* __restrict__ y, int64_t n, int dim, float snr_feature,
+                           float* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int d = 0; d < dim; d++) x[i * (dim + 1) + d] = y[i * dim + d];
+    x[i * (dim + 1) + dim] = snr_feature;
+}
+
+// D = (sigmoid(z) - sigmoid(lambda)) / n in bf16, and per-block FP64 loss
+// partials sum_k softplus(z) - p z.
+__global__ __launch_bounds__(256) void k_bce(const float* __restrict__ logits, const float* __restrict__ target_llr,
+                                             int64_t n, int out, __bf16* __restrict__ D, double* __restrict__ part) {
+    const int64_t cnt = n * out;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+        const float z = logits[i];
+        const float p = 1.0f / (1.0f + expf(-target_llr[i]));
+        const float sz = 1.0f / (1.0f + expf(-z));
+        D[i] = (__bf16)((sz - p) / (float)n);
+        const double sp = (z > 0.0f ? (double)z : 0.0) + log1p(exp(-(double)fabsf(z)));
+        acc += sp - (double)p * (double)z;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_loss(const double* __restrict__ part, int nb, int64_t n, double* __restrict__ loss) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nb; b++) s += part[b];
+        *loss = s / (double)n;
+    }
+}
+
+// grad[o * in + i] = sum over splits of partial[s][o][i] (fixed order)
+__global__ void k_reduce_splits(const float* __restrict__ partial, int splits, int64_t cnt, float* __restrict__ grad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cnt) return;
+    float s = 0.0f;
+    for (int k = 0; k < splits; k++) s += partial[(int64_t)k * cnt + i];
+    grad[i] = s;
+}
+
+// db[o] = sum_s D[s][o], one thread per output, fixed order
+__global__ void k_colsum(const __bf16* __restrict__ D, int64_t n, int out, float* __restrict__ db) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= out) return;
+    float s = 0.0f;
+    for (int64_t i = 0; i < n; i++) s += (float)D[i * out + o];
+    db[o] = s;
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       int64_t P, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// bf16 copies W [out][in] and W^T [in][out] of one layer
+__global__ void k_refresh(const float* __restrict__ W, int out, int in, __bf16* __restrict__ w,
+                          __bf16* __restrict__ wt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)out * in) return;
+    const int o = (int)(i / in), j = (int)(i % in);
+    const __bf16 b = (__bf16)W[i];
+    w[i] = b;
+    wt[(int64_t)j * out + o] = b;
+}
+
+// ---- GEMM launch ----
+template <int EPI>
+hipError_t gemm(const GemmArgs& g, bool a_kc, bool b_kc, int splits, hipStream_t st) {
+    dim3 grid((g.N + kTile - 1) / kTile, (g.M + kTile - 1) / kTile, splits);
+    if (a_kc && b_kc)
+        hipLaunchKernelGGL((k_gemm<true, true, EPI>), grid, dim3(256), 0, st, g);
+    else if (a_kc)
+        hipLaunchKernelGGL((k_gemm<true, false, EPI>), grid, dim3(256), 0, st, g);
+    else if (b_kc)
+        hipLaunchKernelGGL((k_gemm<false, true, EPI>), grid, dim3(256), 0, st, g);
+    else
+        hipLaunchKernelGGL((k_gemm<false, false, EPI>), grid, dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+GemmArgs gargs() {
+    GemmArgs g;
+    std::memset(&g, 0, sizeof(g));
+    return g;
+}
+
+// Workspace layout for n samples.
+struct MlpWs {
+    int64_t x0, z[MDGMI_MLP_MAX_LAYERS], h[MDGMI_MLP_MAX_LAYERS], logits, d0, d1, part, lpart, total;
+};
+
+MlpWs mlp_ws(const mdgmi_mlp* net, int64_t n) {
+    MlpWs w{};
+    int64_t o = 0;
+    w.x0 = o;
+    o += al(n * net->sizes[0] * 2);
+    for (int l = 0; l < net->L; l++) {
+        w.z[l] = o;
+        o += al(n * net->sizes[l + 1] * 4);
+        w.h[l] = o;
+        o += al(n * net->sizes[l + 1] * 2);
+    }
+    w.logits = w.z[net->L - 1];
+    w.d0 = o;
+    o += al(n * net->width * 2);
+    w.d1 = o;
+    o += al(n * net->width * 2);
+    const int64_t splits = (n + kKSplit - 1) / kKSplit;
+    w.part = o;
+    o += al(splits * (int64_t)net->width * net->width * 4);
+    w.lpart = o;
+    o += al(1024 * 8);
+    w.total = o;
+    return w;
+}
+
+// Forward pass of n samples: Z_l (FP32) and H_l (bf16) of every layer into
+// the workspace; the last layer's Z is the logits.
+hipError_t forward(const mdgmi_mlp* net, const float* x, int64_t n, char* ws, const MlpWs& w, hipStream_t st) {
+    const int in0 = net->sizes[0];
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n * in0 + 255) / 256)), dim3(256), 0, st, x, n * in0,
+                       (__bf16*)(ws + w.x0));
+    const __bf16* prev = (const __bf16*)(ws + w.x0);
+    for (int l = 0; l < net->L; l++) {
+        const int in = net->sizes[l], out = net->sizes[l + 1];
+        GemmArgs g = gargs();
+        g.A = prev;
+        g.a_sm = in;
+        g.a_sk = 1;
+        g.B = net->d_w[l];
+        g.b_sk = 1;
+        g.b_sn = in;
+        g.M = (int)n;
+        g.N = out;
+        g.K = in;
+        g.k_per_split = ((in + kKStep - 1) / kKStep) * kKStep;
+        g.bias = net->d_params + net->boff[l];
+        g.C = (float*)(ws + w.z[l]);
+        g.ldc = out;
+        hipError_t e;
+        if (l < net->L - 1) {
+            g.H = (__bf16*)(ws + w.h[l]);
+            g.ldh = out;
+            e = gemm<kEpiGeluBf16>(g, true, true, 1, st);
+        } else {
+            e = gemm<kEpiF32>(g, true, true, 1, st);
+        }
+        if (e != hipSuccess) return e;
+        prev = (const __bf16*)(ws + w.h[l]);
+    }
+    return hipSuccess;
+}
+
+void refresh_all(mdgmi_mlp* net, hipStream_t st) {
+    for (int l = 0; l < net->L; l++) {
+        const int in = net->sizes[l], out = net->sizes[l + 1];
+        hipLaunchKernelGGL(k_refresh, dim3((unsigned)(((int64_t)out * in + 255) / 256)), dim3(256), 0, st,
+                           net->d_params + net->woff[l], out, in, net->d_w[l], net->d_wt[l]);
+    }
+}
+
+bool ok_sizes(const int32_t* sizes, int L) {
+    if (L < 1 || L > MDGMI_MLP_MAX_LAYERS) return false;
+    for (int l = 0; l <= L; l++)
+        if (sizes[l] < 1 || sizes[l] > 4096) return false;
+    return true;
+}
+
+}  // namespace
+}  // namespace mdgmi
+
+using namespace mdgmi;
+
+extern "C" {
+
+int mdgmi_mlp_create(const int32_t* sizes, int32_t n_layers, uint64_t seed, mdgmi_mlp** out) {
+    if (!sizes || !out) return MDGMI_E_NULL;
+    *out = nullptr;
+    if (!ok_sizes(sizes, n_layers)) return MDGMI_E_SHAPE;
+    mdgmi_mlp* net = new mdgmi_mlp();
+    net->L = n_layers;
+    int64_t p = 0;
+    for (int l = 0; l <= n_layers; l++) {
+        net->sizes[l] = sizes[l];
+        net->width = std::max(net->width, (int)sizes[l]);
+    }
+    for (int l = 0; l < n_layers; l++) {
+        net->woff[l] = p;
+        p += (int64_t)sizes[l + 1] * sizes[l];
+        net->boff[l] = p;
+        p += sizes[l + 1];
+    }
+    net->P = p;
+    (void)hipGetDevice(&net->device);
+    // PyTorch-style default init of a linear layer: W, b ~ U(-1/sqrt(in), 1/sqrt(in)),
+    // drawn from a 64-bit Mersenne twister seeded with `seed`.
+    std::vector<float> h(p);
+    std::mt19937_64 rng(seed);
+    for (int l = 0; l < n_layers; l++) {
+        const double bound = 1.0 / std::sqrt((double)sizes[l]);
+        for (int64_t i = net->woff[l]; i < net->boff[l] + sizes[l + 1]; i++)
+            h[i] = (float)((2.0 * ((rng() >> 11) * (1.0 / 9007199254740992.0)) - 1.0) * bound);
+    }
+    bool ok = hipMalloc(&net->d_params, sizeof(float) * p) == hipSuccess &&
+              hipMalloc(&net->d_m, sizeof(float) * p) == hipSuccess &&
+              hipMalloc(&net->d_v, sizeof(float) * p) == hipSuccess &&
+              hipMalloc(&net->d_grad, sizeof(float) * p) == hipSuccess;
+    for (int l = 0; ok && l < n_layers; l++) {
+        const int64_t cnt = (int64_t)sizes[l + 1] * sizes[l];
+        ok = hipMalloc(&net->d_w[l], 2 * cnt) == hipSuccess && hipMalloc(&net->d_wt[l], 2 * cnt) == hipSuccess;
+    }
+    ok = ok && hipMemcpy(net->d_params, h.data(), sizeof(float) * p, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemset(net->d_m, 0, sizeof(float) * p) == hipSuccess &&
+         hipMemset(net->d_v, 0, sizeof(float) * p) == hipSuccess &&
+         hipMemset(net->d_grad, 0, sizeof(float) * p) == hipSuccess;
+    if (ok) {
+        refresh_all(net, nullptr);
+        ok = hipDeviceSynchronize() == hipSuccess;
+    }
+    if (!ok) {
+        mdgmi_mlp_destroy(net);
+        return MDGMI_E_HIP;
+    }
+    *out = net;
+    return MDGMI_OK;
+}
+
+int mdgmi_mlp_destroy(mdgmi_mlp* net) {
+    if (!net) return MDGMI_E_NULL;
+    (void)hipFree(net->d_params);
+    (void)hipFree(net->d_m);
+    (void)hipFree(net->d_v);
+    (void)hipFree(net->d_grad);
+    for (int l = 0; l < net->L; l++) {
+        (void)hipFree(net->d_w[l]);
+        (void)hipFree(net->d_wt[l]);
+    }
+    delete net;
+    return MDGMI_OK;
+}
+
+int mdgmi_mlp_param_count(const mdgmi_mlp* net, int64_t* count) {
+    if (!net || !count) return MDGMI_E_NULL;
+    *count = net->P;
+    return MDGMI_OK;
+}
+
+int mdgmi_mlp_get_params(const mdgmi_mlp* net, float* host, int64_t count, int32_t which) {
+    if (!net || !host) return MDGMI_E_NULL;
+    if (count != net->P) return MDGMI_E_SHAPE;
+    const float* src = which == 0 ? net->d_params : which == 1 ? net->d_grad : which == 2 ? net->d_m : which == 3 ? net->d_v : nullptr;
+    if (!src) return MDGMI_E_ARG;
+    return hipMemcpy(host, src, sizeof(float) * count, hipMemcpyDeviceToHost) == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+}
+
+int mdgmi_mlp_set_params(mdgmi_mlp* net, const float* host, int64_t count) {
+    if (!net || !host) return MDGMI_E_NULL;
+    if (count != net->P) return MDGMI_E_SHAPE;
+    if (hipMemcpy(net->d_params, host, sizeof(float) * count, hipMemcpyHostToDevice) != hipSuccess) return MDGMI_E_HIP;
+    refresh_all(net, nullptr);
+    return hipDeviceSynchronize() == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+}
+
+int mdgmi_mlp_workspace_size(const mdgmi_mlp* net, int64_t n, size_t* bytes) {
+    if (!net || !bytes) return MDGMI_E_NULL;
+    if (n < 1 || n > (int64_t)1 << 30) return MDGMI_E_SHAPE;
+    *bytes = (size_t)mlp_ws(net, n).total;
+    return MDGMI_OK;
+}
+
+int mdgmi_mlp_features(const float* y, int64_t n, int32_t dim, double snr_db, float* x, void* stream) {
+    if (!y || !x) return MDGMI_E_NULL;
+    if (n < 1 || dim < 1 || dim > 16) return MDGMI_E_SHAPE;
+    const float feat = (float)((snr_db - 9.5) / 4.5);
+    hipLaunchKernelGGL(k_features, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, y, n, dim,
+                       feat, x);
+    return hipGetLastError() == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+}
+
+int mdgmi_mlp_forward(const mdgmi_mlp* net, const float* x, int64_t n, float* logits, void* ws, size_t ws_bytes,
+                      void* stream) {
+    if (!net || !x || !logits || !ws) return MDGMI_E_NULL;
+    if (n < 1 || n > (int64_t)1 << 30) return MDGMI_E_SHAPE;
+    const MlpWs w = mlp_ws(net, n);
+    if (ws_bytes < (size_t)w.total) return MDGMI_E_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    if (forward(net, x, n, (char*)ws, w, st) != hipSuccess) return MDGMI_E_HIP;
+    const int out = net->sizes[net->L];
+    return hipMemcpyAsync(logits, (char*)ws + w.logits, sizeof(float) * n * out, hipMemcpyDeviceToDevice, st) ==
+                   hipSuccess
+               ? MDGMI_OK
+               : MDGMI_E_HIP;
+}
+
+int mdgmi_mlp_loss_grad(mdgmi_mlp* net, const float* x, const float* target_llr, int64_t n, double* loss, void* ws,
+                        size_t ws_bytes, void* stream) {
+    if (!net || !x || !target_llr || !loss || !ws) return MDGMI_E_NULL;
+    if (n < 1 || n > (int64_t)1 << 30) return MDGMI_E_SHAPE;
+    const MlpWs w = mlp_ws(net, n);
+    if (ws_bytes < (size_t)w.total) return MDGMI_E_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)ws;
+    if (forward(net, x, n, base, w, st) != hipSuccess) return MDGMI_E_HIP;
+    const int L = net->L, outL = net->sizes[L];
+    const int nb = (int)std::min<int64_t>(1024, (n * outL + 255) / 256);
+    hipLaunchKernelGGL(k_bce, dim3(nb), dim3(256), 0, st, (const float*)(base + w.logits), target_llr, n, outL,
+                       (__bf16*)(base + w.d0), (double*)(base + w.lpart));
+    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(64), 0, st, (const double*)(base + w.lpart), nb, n, loss);
+    __bf16* D = (__bf16*)(base + w.d0);
+    __bf16* Dn = (__bf16*)(base + w.d1);
+    const int splits = (int)((n + kKSplit - 1) / kKSplit);
+    for (int l = L - 1; l >= 0; l--) {
+        const int in = net->sizes[l], out = net->sizes[l + 1];
+        const __bf16* Hprev = l > 0 ? (const __bf16*)(base + w.h[l - 1]) : (const __bf16*)(base + w.x0);
+        // dW_l [out][in] = sum_s D[s][o] Hprev[s][i]  (split over samples)
+        GemmArgs g = gargs();
+        g.A = D;
+        g.a_sm = 1;
+        g.a_sk = out;
+        g.B = Hprev;
+        g.b_sk = in;
+        g.b_sn = 1;
+        g.M = out;
+        g.N = in;
+        g.K = n;
+        g.k_per_split = kKSplit;
+        g.C = (float*)(base + w.part);
+        if (gemm<kEpiPartial>(g, false, false, splits, st) != hipSuccess) return MDGMI_E_HIP;
+        const int64_t cnt = (int64_t)out * in;
+        hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
+                           (const float*)(base + w.part), splits, cnt, net->d_grad + net->woff[l]);
+        hipLaunchKernelGGL(k_colsum, dim3((out + 63) / 64), dim3(64), 0, st, D, n, out, net->d_grad + net->boff[l]);
+        if (l > 0) {
+            // D_prev [n][in] = (D [n][out] W_l [out][in]) * gelu'(Z_{l-1})
+            GemmArgs h = gargs();
+            h.A = D;
+            h.a_sm = out;
+            h.a_sk = 1;
+            h.B = net->d_wt[l];  // B(k = o, n = i) = W^T[i][o]
+            h.b_sk = 1;
+            h.b_sn = out;
+            h.M = (int)n;
+            h.N = in;
+            h.K = out;
+            h.k_per_split = ((out + kKStep - 1) / kKStep) * kKStep;
+            h.H = Dn;
+            h.ldh = in;
+            h.Z = (const float*)(base + w.z[l - 1]);
+            h.ldz = in;
+            if (gemm<kEpiGeluGrad>(h, true, true, 1, st) != hipSuccess) return MDGMI_E_HIP;
+            std::swap(D, Dn);
+        }
+    }
+    return hipGetLastError() == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+}
+
+int mdgmi_mlp_adam_step(mdgmi_mlp* net, float lr, float beta1, float beta2, float eps, void* stream) {
+    if (!net) return MDGMI_E_NULL;
+    if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return MDGMI_E_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    net->step++;
+    const float c1 = (float)(1.0 - std::pow((double)beta1, (double)net->step));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, (double)net->step));
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((net->P + 255) / 256)), dim3(256), 0, st, net->d_params, net->d_grad,
+                       net->d_m, net->d_v, net->P, lr, beta1, beta2, eps, c1, c2);
+    refresh_all(net, st);
+    return hipGetLastError() == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+}
+
+int mdgmi_mlp_save(const mdgmi_mlp* net, const char* path) {
+    if (!net || !path) return MDGMI_E_NULL;
+    std::vector<float> p(net->P), m(net->P), v(net->P);
+    if (hipMemcpy(p.data(), net->d_params, 4 * net->P, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(m.data(), net->d_m, 4 * net->P, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(v.data(), net->d_v, 4 * net->P, hipMemcpyDeviceToHost) != hipSuccess)
+        return MDGMI_E_HIP;
+    FILE* fp = std::fopen(path, "wb");
+    if (!fp) return MDGMI_E_ARG;
+    const char magic[8] = {'M', 'D', 'G', 'M', 'I', 'M', 'L', '1'};
+    int32_t hdr[2 + MDGMI_MLP_MAX_LAYERS + 1] = {net->L};
+    for (int l = 0; l <= net->L; l++) hdr[1 + l] = net->sizes[l];
+    bool ok = std::fwrite(magic, 1, 8, fp) == 8 && std::fwrite(hdr, sizeof(hdr), 1, fp) == 1 &&
+              std::fwrite(&net->step, sizeof(int64_t), 1, fp) == 1 &&
+              std::fwrite(p.data(), 4, net->P, fp) == (size_t)net->P &&
+              std::fwrite(m.data(), 4, net->P, fp) == (size_t)net->P &&
+              std::fwrite(v.data(), 4, net->P, fp) == (size_t)net->P;
+    std::fclose(fp);
+    return ok ? MDGMI_OK : MDGMI_E_ARG;
+}
+
+int mdgmi_mlp_load(mdgmi_mlp* net, const char* path) {
+    if (!net || !path) return MDGMI_E_NULL;
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return MDGMI_E_ARG;
+    char magic[8];
+    int32_t hdr[2 + MDGMI_MLP_MAX_LAYERS + 1];
+    int64_t step = 0;
+    std::vector<float> p(net->P), m(net->P), v(net->P);
+    bool ok = std::fread(magic, 1, 8, fp) == 8 && std::memcmp(magic, "MDGMIML1", 8) == 0 &&
+              std::fread(hdr, sizeof(hdr), 1, fp) == 1 && hdr[0] == net->L;
+    for (int l = 0; ok && l <= net->L; l++) ok = hdr[1 + l] == net->sizes[l];
+    ok = ok && std::fread(&step, sizeof(int64_t), 1, fp) == 1 && std::fread(p.data(), 4, net->P, fp) == (size_t)net->P &&
+         std::fread(m.data(), 4, net->P, fp) == (size_t)net->P && std::fread(v.data(), 4, net->P, fp) == (size_t)net->P;
+    std::fclose(fp);
+    if (!ok) return MDGMI_E_ARG;
+    if (hipMemcpy(net->d_params, p.data(), 4 * net->P, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(net->d_m, m.data(), 4 * net->P, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(net->d_v, v.data(), 4 * net->P, hipMemcpyHostToDevice) != hipSuccess)
+        return MDGMI_E_HIP;
+    net->step = step;
+    refresh_all(net, nullptr);
+    return hipDeviceSynchronize() == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// bf16 MFMA GEMM with fused epilogues for the MLP demapper.
+//
+// C[M x N] = sum_k A(m, k) B(k, n), A and B in bf16 addressed by element
+// strides (so row-major, transposed and batched-transposed operands share
+// one kernel), FP32 accumulation on v_mfma_f32_32x32x16_bf16. A block of 4
+// waves owns a 64 x 64 output tile and walks K in steps of 32 through LDS;
+// each wave owns a 32 x 32 quarter. Tiles are stored k-contiguous in LDS,
+// so every lane's MFMA operand (8 consecutive k of one row / column) is one
+// 16-byte read. Operands whose k is contiguous in memory are fetched 8 at a
+// time; others are fetched along m / n and transposed on the way into LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+
+namespace mdgmi {
+namespace mlp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kTile = 64;
+constexpr int kKStep = 32;
+constexpr int kLdsPitch = kKStep + 8;  // bf16 elements per LDS row (16-byte aligned rows)
+
+// GELU, tanh form (Hendrycks & Gimpel 2016): x * sigmoid(2 sqrt(2/pi) (x + 0.044715 x^3)),
+// evaluated with the base-2 exponential and the hardware reciprocal.
+__device__ __forceinline__ float gelu_f(float x) {
+    const float k = -2.0f * 0.7978845608028654f * 1.4426950408889634f;  // -2 sqrt(2/pi) log2(e)
+    const float u = x * fmaf(0.044715f * k, x * x, k);
+    return x * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(u));
+}
+
+__device__ __forceinline__ float gelu_grad_f(float x) {
+    const float c = 0.7978845608028654f;
+    const float k = -2.0f * c * 1.4426950408889634f;
+    const float u = x * fmaf(0.044715f * k, x * x, k);
+    const float sg = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(u));  // sigmoid(2 t), t = c (x + a x^3)
+    // d/dx [x sigmoid(2t)] = sigmoid(2t) + x * 2 sigmoid(2t)(1 - sigmoid(2t)) dt/dx
+    const float dt = c * fmaf(3.0f * 0.044715f, x * x, 1.0f);
+    return fmaf(x * 2.0f * sg * (1.0f - sg), dt, sg);
+}
+
+enum Epi : int {
+    kEpiF32 = 0,        // C (FP32) = acc (+ bias[n] if bias)
+    kEpiGeluBf16 = 1,   // Z (FP32) = acc + bias[n]; H (bf16) = gelu(Z)
+    kEpiGeluGrad = 2,   // D (bf16) = acc * gelu'(Z[m][n])
+    kEpiPartial = 3     // C + split * M * N (FP32) = acc  (split-K partials)
+};
+
+struct GemmArgs {
+    const __bf16* A;
+    int64_t a_sm, a_sk;          // element strides of A(m, k)
+    const __bf16* B;
+    int64_t b_sk, b_sn;          // element strides of B(k, n)
+    int M, N;
+    int64_t K;
+    int64_t k_per_split;         // K range per grid.z slice (multiple of kKStep)
+    const float* bias;           // [N] or null
+    float* C;                    // FP32 output, row-major [M][ldc]
+    int64_t ldc;
+    __bf16* H;                   // bf16 output, row-major [M][ldh]
+    int64_t ldh;
+    const float* Z;              // pre-activation for kEpiGeluGrad, row-major [M][ldz]
+    int64_t ldz;
+};
+
+template <bool A_K_CONTIG>
+__device__ __forceinline__ void load_tile_a(const GemmArgs& g, int64_t m0, int64_t k0, int64_t k1, __bf16* As) {
+    const int t = threadIdx.x;  // 256 threads
+    if (A_K_CONTIG) {
+        const int mm = t >> 2, kk = (t & 3) * 8;
+        const int64_t m = m0 + mm;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int64_t k = k0 + kk + i;
+            As[mm * kLdsPitch + kk + i] = (m < g.M && k < k1) ? g.A[m * g.a_sm + k * g.a_sk] : (__bf16)0.0f;
+        }
+    } else {
+        // consecutive threads walk m (contiguous in memory), transposed store
+        const int mm = t & 63, kk = (t >> 6) * 8;
+        const int64_t m = m0 + mm;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int64_t k = k0 + kk + i;
+            As[mm * kLdsPitch + kk + i] = (m < g.M && k < k1) ? g.A[m * g.a_sm + k * g.a_sk] : (__bf16)0.0f;
+        }
+    }
+}
+
+template <bool B_K_CONTIG>
+__device__ __forceinline__ void load_tile_b(const GemmArgs& g, int64_t n0, int64_t k0, int64_t k1, __bf16* Bs) {
+    const int t = threadIdx.x;
+    if (B_K_CONTIG) {
+        const int nn = t >> 2, kk = (t & 3) * 8;
+        const int64_t n = n0 + nn;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int64_t k = k0 + kk + i;
+            Bs[nn * kLdsPitch + kk + i] = (n < g.N && k < k1) ? g.B[k * g.b_sk + n * g.b_sn] : (__bf16)0.0f;
+        }
+    } else {
+        const int nn = t & 63, kk = (t >> 6) * 8;
+        const int64_t n = n0 + nn;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int64_t k = k0 + kk + i;
+            Bs[nn * kLdsPitch + kk + i] = (n < g.N && k < k1) ? g.B[k * g.b_sk + n * g.b_sn] : (__bf16)0.0f;
+        }
+    }
+}
+
+template <bool A_K_CONTIG, bool B_K_CONTIG, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) __bf16 As[kTile * kLdsPitch];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[kTile * kLdsPitch];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;  // this wave's quarter
+    const int64_t m0 = (int64_t)blockIdx.y * kTile, n0 = (int64_t)blockIdx.x * kTile;
+    const int64_t kb = (int64_t)blockIdx.z * g.k_per_split;
+    const int64_t ke = kb + g.k_per_split < g.K ? kb + g.k_per_split : g.K;
+    f32x16 acc = {};
+    for (int64_t k0 = kb; k0 < ke; k0 += kKStep) {
+        load_tile_a<A_K_CONTIG>(g, m0, k0, ke, As);
+        load_tile_b<B_K_CONTIG>(g, n0, k0, ke, Bs);
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kKStep; ks += 16) {
+            const int kofs = ks + 8 * (lane >> 5);
+            const bf16x8 a = *(const bf16x8*)(As + (wm + (lane & 31)) * kLdsPitch + kofs);
+            const bf16x8 b = *(const bf16x8*)(Bs + (wn + (lane & 31)) * kLdsPitch + kofs);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // lane holds rows 8 (r >> 2) + 4 (lane >> 5) + (r & 3) of column lane & 31
+    const int64_t n = n0 + wn + (lane & 31);
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        const int64_t m = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (m >= g.M || n >= g.N) continue;
+        float v = acc[r];
+        if (EPI == kEpiF32) {
+            if (g.bias) v += g.bias[n];
+            g.C[m * g.ldc + n] = v;
+        } else if (EPI == kEpiGeluBf16) {
+            v += g.bias[n];
+            ((float*)g.C)[m * g.ldc + n] = v;  // pre-activation kept for the backward pass
+            g.H[m * g.ldh + n] = (__bf16)gelu_f(v);
+        } else if (EPI == kEpiGeluGrad) {
+            g.H[m * g.ldh + n] = (__bf16)(v * gelu_grad_f(g.Z[m * g.ldz + n]));
+        } else {
+            g.C[(int64_t)blockIdx.z * g.M * g.N + m * g.N + n] = v;
+        }
+    }
+}
+
+}  // namespace mlp
+}  // namespace mdgmi
