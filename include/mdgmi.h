@@ -230,13 +230,25 @@ int mdgmi_mlp_loss_grad(mdgmi_mlp* net, const float* x, const float* target_llr,
                         size_t ws_bytes, void* stream);
 /* One bias-corrected Adam step on the masters with the last gradient. */
 int mdgmi_mlp_adam_step(mdgmi_mlp* net, float lr, float beta1, float beta2, float eps, void* stream);
+/* GMI of the network's logits read as LLRs, per SNR point, for samples y
+ * [n_snr][n][dim] (device float) with sent rows tx_idx [n_snr][n] of fmt;
+ * snr_db_host [n_snr] feeds the SNR feature. Samples are processed in
+ * chunks of `chunk` (at most 1024 chunks per SNR point). out [n_snr][6]:
+ * GMI, NaN, SE_GMI, NaN, N, non-finite count. The network must have
+ * fmt->dim + 1 inputs and log2(M) outputs. */
+int mdgmi_mlp_gmi_workspace_size(const mdgmi_mlp* net, int64_t chunk, size_t* bytes);
+int mdgmi_mlp_gmi(const mdgmi_mlp* net, const mdgmi_format* fmt, const float* y, const uint32_t* tx_idx, int64_t n,
+                  const double* snr_db_host, int32_t n_snr, int64_t chunk, double* out, void* ws, size_t ws_bytes,
+                  void* stream);
 /* Checkpoint: widths, step, masters and both Adam moments (binary). */
 int mdgmi_mlp_save(const mdgmi_mlp* net, const char* path);
 int mdgmi_mlp_load(mdgmi_mlp* net, const char* path);
 
 /* Launch-shape override of the MFMA path for tuning sweeps: variant v in
- * 0..5 selects (sample columns per wave, waves per block) = (1,4), (2,4),
- * (1,8), (2,8), (1,16), (1,12); v < 0 restores the built-in choice. Process-wide; affects
+ * 0..7 selects (sample columns per wave, waves per block) = (1,4), (2,4),
+ * (1,8), (2,8), (1,16), (1,12) with the operand image in LDS, and (1,16),
+ * (1,8) reading it from L2; v < 0 restores the built-in choice (the
+ * autotuner's, else a default). Process-wide; affects
  * workspace sizes, so set it before sizing workspaces. Always MDGMI_OK. */
 int mdgmi_set_tuning(int mfma_variant);
 int mdgmi_get_tuning(void);   /* the current override, -1 if none */

@@ -1,5 +1,7 @@
 // FP32 exact demapper with the distance term on the matrix cores: per-SNR
 // kernels over one format (see mfma_core.h for the arithmetic and layouts).
+#include <algorithm>
+
 #include "mfma_core.h"
 
 namespace mdgmi {
@@ -77,9 +79,10 @@ hipError_t launch_v(const mdgmi_format* f, const float* y, const uint32_t* tx, i
     return hipGetLastError();
 }
 
-// Variants (sample columns per wave, waves per block): 0 = (1, 4),
-// 1 = (2, 4), 2 = (1, 8), 3 = (2, 8), 4 = (1, 16), 5 = (1, 12); LDS staging
-// when the image fits.
+// Variants (sample columns per wave, waves per block, A image in LDS):
+// 0 = (1, 4), 1 = (2, 4), 2 = (1, 8), 3 = (2, 8), 4 = (1, 16), 5 = (1, 12)
+// staged in LDS when the image fits; 6 = (1, 16), 7 = (1, 8) reading it from
+// L2.
 template <int DIM>
 hipError_t launch_d(int var, bool lds, const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
                     const SnrArgs& sa, bool llr_mode, float* llr, double* part, const uint4* img, int ntiles,
@@ -105,17 +108,20 @@ hipError_t launch_d(int var, bool lds, const mdgmi_format* f, const float* y, co
         case 3:
             MDGMI_V(2, 8)
         case 4:
+        case 6:
             MDGMI_V(1, 16)
-        default:
+        case 5:
             MDGMI_V(1, 12)
+        default:
+            MDGMI_V(1, 8)
     }
 #undef MDGMI_V
 #undef MDGMI_VG
 }
 
 constexpr int kNumVariants = kMfmaVariants;
-const MfmaVariant kVariants[kNumVariants] = {{1, 4, true}, {2, 4, true}, {1, 8, true},
-                                             {2, 8, true}, {1, 16, true}, {1, 12, true}};
+const MfmaVariant kVariants[kNumVariants] = {{1, 4, true},  {2, 4, true},  {1, 8, true},  {2, 8, true},
+                                             {1, 16, true}, {1, 12, true}, {1, 16, false}, {1, 8, false}};
 
 int pick_variant(const mdgmi_format* f) {
     if (g_variant_override >= 0 && g_variant_override < kNumVariants) return g_variant_override;
@@ -144,15 +150,20 @@ LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr) {
     const MfmaVariant& v = kVariants[pick_variant(f)];
     const int64_t cols = 32 * v.ncol;
     const int64_t tiles = (n + cols - 1) / cols;
-    int64_t want = (tiles + v.waves - 1) / v.waves;
-    // about 4 waves per SIMD in total, spread over the SNR points of a launch
-    int64_t cap = (int64_t)device_cu_count() * 16 / v.waves;
-    int snr_in_launch = n_snr < kMaxSnrPerLaunch ? n_snr : kMaxSnrPerLaunch;
-    cap = (cap + snr_in_launch - 1) / snr_in_launch;
-    if (cap < 1) cap = 1;
+    const int64_t want = (tiles + v.waves - 1) / v.waves;
+    // One resident round of blocks over all CUs: blocks per CU limited by
+    // the LDS image (160 KiB per CU) and by a target of 16 waves per CU.
+    const size_t img = image_bytes_per_snr(f);
+    const bool lds = v.lds && img <= 128 * 1024;
+    const int by_lds = lds ? std::max(1, (int)((160 * 1024) / (img + 2048))) : 8;
+    const int by_waves = std::max(1, 16 / v.waves);
+    const int64_t total = (int64_t)device_cu_count() * std::min(by_lds, by_waves);
+    const int snr_in_launch = n_snr < kMaxSnrPerLaunch ? n_snr : kMaxSnrPerLaunch;
+    int64_t per = std::max<int64_t>(1, total / snr_in_launch);
+    per = std::min<int64_t>(per, std::max<int64_t>(1, want));
     LaunchCfg c;
     c.threads = v.waves * 64;
-    c.blocks_per_snr = (int)(want < cap ? (want < 1 ? 1 : want) : cap);
+    c.blocks_per_snr = (int)per;
     return c;
 }
 
@@ -178,7 +189,7 @@ hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int var = pick_variant(f);
-    const bool lds = image_bytes_per_snr(f) <= 128 * 1024;
+    const bool lds = kVariants[var].lds && image_bytes_per_snr(f) <= 128 * 1024;
     switch (f->dim) {
         case 2:
             return launch_d<2>(var, lds, f, y, tx, n, sa, llr_mode, llr, part, img, ntiles, cfg.blocks_per_snr, st);

@@ -24,7 +24,7 @@ struct mdgmi_format {
 
 namespace mdgmi {
 
-constexpr int kMfmaVariants = 6;     // MFMA launch shapes (see mdgmi_set_tuning)
+constexpr int kMfmaVariants = 8;     // MFMA launch shapes (see mdgmi_set_tuning)
 constexpr int kNPart = 5;           // per-block FP64 partials: sum cG, sum cG^2, sum cM, sum cM^2, nonfinite
 constexpr int kMaxSnrPerLaunch = 32;
 // Exponents are taken relative to a fixed offset: e_j = 2^(kBias - t_j) with

@@ -228,7 +228,7 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5, col = lane & 31;
     half8 bop[NCOL][NB];
-    float yv[NCOL][DIM], Kc[NCOL];
+    float yv[NCOL][DIM];
     int64_t idx[NCOL];
 #pragma unroll
     for (int c = 0; c < NCOL; c++) {
@@ -240,8 +240,7 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
             yv[c][d] = valid ? ys[idx[c] * DIM + d] : 0.0f;
             ys2 = fmaf(yv[c][d], yv[c][d], ys2);
         }
-        const float K = kBias - s * ys2;
-        Kc[c] = K;
+        const float K = fmaf(-s, ys2, kBias);
         make_b<DIM>(yv[c], K, h, bop[c]);
     }
     float bank[NCOL][16];
@@ -296,120 +295,110 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
 #pragma unroll
         for (int c = 0; c < NCOL; c++) hi[c].add_group(g0 / G, T[c]);
     }
-    // ---- epilogue: class sums, LLRs / costs ----
+    // ---- epilogue: class sums one label bit at a time, then LLRs / costs ----
+    // (streamed per bit so that few values stay live; the exact per-class
+    // path below recomputes everything from y when it is needed)
 #pragma unroll
     for (int c = 0; c < NCOL; c++) {
-        // lane-local sums over the row bits held in r: label bits 0,1,3,4
-        float L0[4], L1[4], Lt = 0.0f;
+        const int64_t i = idx[c];
+        const bool mine = (h == 0) && (i < n);
+        uint32_t slot = 0;
+        bool row_ok = true;
+        float ui = 0.0f;
+        if (!LLR) {
+            // a sent row outside [0, M) gives a NaN cost instead of a stray read
+            const uint32_t row = i < n ? txs[i] : 0u;
+            row_ok = row < (uint32_t)M;
+            slot = labels[row_ok ? row : 0u];
+            // u of the sent point by the matrix cores themselves: one more MFMA
+            // whose row r is the sent point of sample r puts u_i(y) on the
+            // diagonal, bit-identical to the value inside the class sums, so
+            // the MI cost log2 sum_j 2^(u_j - u_i) carries no recomputation
+            // error. Diagonal element r sits in lane half (r >> 2) & 1,
+            // register ((r >> 3) << 2) | (r & 3).
+            half8 ad[NB];
+            load_a<NB>(A, (int)(slot >> 5), h, (int)(slot & 31), ad);
+            const f32x16 ud = tile_mfma<NB>(ad, bop[c]);
+            const int q = ((col >> 3) << 2) | (col & 3);
+            float dv = 0.0f;
 #pragma unroll
-        for (int q = 0; q < 4; q++) L0[q] = L1[q] = 0.0f;
-#pragma unroll
-        for (int r = 0; r < 16; r++) {
-            Lt += bank[c][r];
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                if ((r >> q) & 1)
-                    L1[q] += bank[c][r];
-                else
-                    L0[q] += bank[c][r];
-            }
+            for (int r = 0; r < 16; r++) dv = (r == q) ? ud[r] : dv;
+            const float other = __shfl_xor(dv, 32, 64);
+            ui = (h == ((col >> 2) & 1)) ? dv : other;
         }
-        float S0[MDGMI_MAX_BITS], S1[MDGMI_MAX_BITS];
-        const int rbit_of_label[5] = {0, 1, -1, 2, 3};
+        float Lt = 0.0f;
 #pragma unroll
-        for (int k = 0; k < 5; k++) {
-            if (k == 2) {
-                const float ot = __shfl_xor(Lt, 32, 64);
-                S0[2] = h ? ot : Lt;
-                S1[2] = h ? Lt : ot;
-            } else {
-                const int q = rbit_of_label[k];
-                S0[k] = L0[q] + __shfl_xor(L0[q], 32, 64);
-                S1[k] = L1[q] + __shfl_xor(L1[q], 32, 64);
-            }
-        }
+        for (int r = 0; r < 16; r++) Lt += bank[c][r];
+        const float ot = __shfl_xor(Lt, 32, 64);
+        const float tot = Lt + ot;
+        float smin = INFINITY, cg = 0.0f;
 #pragma unroll
-        for (int l = 0; l < MAXHI; l++) {
-            S0[5 + l] = hi[c].R0[l] + __shfl_xor(hi[c].R0[l], 32, 64);
-            S1[5 + l] = hi[c].R1[l] + __shfl_xor(hi[c].R1[l], 32, 64);
-        }
-        const float tot = Lt + __shfl_xor(Lt, 32, 64);
-        if (h == 0 && idx[c] < n) {
-            const int64_t i = idx[c];
-            float ls0[MDGMI_MAX_BITS], ls1[MDGMI_MAX_BITS];
-            float smin = INFINITY;
+        for (int k = 0; k < MDGMI_MAX_BITS; k++) {
+            if (k < m) {
+                float S0k, S1k;
+                if (k == 2) {  // the lane half
+                    S0k = h ? ot : Lt;
+                    S1k = h ? Lt : ot;
+                } else if (k < 5) {  // label bits 0, 1, 3, 4 are bits 0..3 of the register index
+                    const int q = k < 2 ? k : k - 1;
+                    float a0 = 0.0f, a1 = 0.0f;
 #pragma unroll
-            for (int k = 0; k < MDGMI_MAX_BITS; k++) {
-                if (k < m) {
-                    smin = fminf(smin, fminf(S0[k], S1[k]));
-                    ls0[k] = lg2(S0[k]);
-                    ls1[k] = lg2(S1[k]);
+                    for (int r = 0; r < 16; r++) {
+                        if ((r >> q) & 1)
+                            a1 += bank[c][r];
+                        else
+                            a0 += bank[c][r];
+                    }
+                    S0k = a0 + __shfl_xor(a0, 32, 64);
+                    S1k = a1 + __shfl_xor(a1, 32, 64);
+                } else {  // tile-index bits
+                    S0k = hi[c].R0[k - 5] + __shfl_xor(hi[c].R0[k - 5], 32, 64);
+                    S1k = hi[c].R1[k - 5] + __shfl_xor(hi[c].R1[k - 5], 32, 64);
                 }
-            }
-            if (LLR) {
-                if (smin >= ex2(kFarLog2)) {
-#pragma unroll
-                    for (int k = 0; k < MDGMI_MAX_BITS; k++)
-                        if (k < m) llr[i * m + k] = log2_ratio(S1[k], S0[k], ls1[k], ls0[k]) * (float)kLn2;
+                smin = fminf(smin, fminf(S0k, S1k));
+                const float l0 = lg2(S0k), l1 = lg2(S1k);
+                if (LLR) {
+                    if (mine) llr[i * m + k] = log2_ratio(S1k, S0k, l1, l0) * (float)kLn2;
                 } else {
-                    float ltot, ti;
-                    exact_classes_f32<DIM>(yv[c], X32, M, m, s, -1, ls0, ls1, ltot, ti);
-#pragma unroll
-                    for (int k = 0; k < MDGMI_MAX_BITS; k++)
-                        if (k < m) llr[i * m + k] = (ls1[k] - ls0[k]) * (float)kLn2;
+                    const bool b = (slot >> k) & 1;
+                    cg += bit_cost2(b ? log2_ratio(S0k, S1k, l0, l1) : log2_ratio(S1k, S0k, l1, l0));
                 }
-            } else {
-                // a sent row outside [0, M) gives a NaN cost instead of a stray read
-                const uint32_t row = txs[i];
-                const bool row_ok = row < (uint32_t)M;
-                const uint32_t slot = labels[row_ok ? row : 0u];
-                // u of the sent point from the very fp16 operands the MFMA saw
-                // (every product is exact in FP32), so that the MI cost
-                // log2 sum_j 2^(u_j - u_i) is free of the split rounding
-                float ui = 0.0f;
-                {
-                    half8 bb[2][NB];
-                    make_b<DIM>(yv[c], Kc[c], 0, bb[0]);
-                    make_b<DIM>(yv[c], Kc[c], 1, bb[1]);
-                    const int ti = (int)(slot >> 5), pi = (int)(slot & 31);
-#pragma unroll
-                    for (int b = 0; b < NB; b++) {
-#pragma unroll
-                        for (int hh = 0; hh < 2; hh++) {
-                            H8 av, bv;
-                            av.u = A[((ti * NB + b) * 2 + hh) * 32 + pi];
-                            bv.v = bb[hh][b];
-#pragma unroll
-                            for (int q = 0; q < 8; q++) ui = fmaf((float)av.h[q], (float)bv.h[q], ui);
-                        }
-                    }
-                }
-                float cg = 0.0f, cm;
-                if (ui >= kFarLog2) {
-#pragma unroll
-                    for (int k = 0; k < MDGMI_MAX_BITS; k++) {
-                        if (k < m) {
-                            bool b = (slot >> k) & 1;
-                            cg += bit_cost2(b ? log2_ratio(S0[k], S1[k], ls0[k], ls1[k])
-                                              : log2_ratio(S1[k], S0[k], ls1[k], ls0[k]));
-                        }
-                    }
-                    cm = mi_cost2(tot, ui);
-                } else {
-                    float ltot, ti = 0.0f;
-                    exact_classes_f32<DIM>(yv[c], X32, M, m, s, (int)slot, ls0, ls1, ltot, ti);
-#pragma unroll
-                    for (int k = 0; k < MDGMI_MAX_BITS; k++) {
-                        if (k < m) {
-                            bool b = (slot >> k) & 1;
-                            cg += bit_cost2(b ? ls0[k] - ls1[k] : ls1[k] - ls0[k]);
-                        }
-                    }
-                    cm = ltot + ti;
-                }
-                if (!row_ok) cg = cm = NAN;
-                acc.add((double)cg, (double)cm);
             }
+        }
+        if (!mine) continue;
+        if (LLR) {
+            if (!(smin >= ex2(kFarLog2))) {
+                // a class lies too far for the common offset: exact per-class path
+                float yc[DIM], ls0[MDGMI_MAX_BITS], ls1[MDGMI_MAX_BITS], ltot, ti;
+#pragma unroll
+                for (int d = 0; d < DIM; d++) yc[d] = ys[i * DIM + d];
+                exact_classes_f32<DIM>(yc, X32, M, m, s, -1, ls0, ls1, ltot, ti);
+#pragma unroll
+                for (int k = 0; k < MDGMI_MAX_BITS; k++)
+                    if (k < m) llr[i * m + k] = (ls1[k] - ls0[k]) * (float)kLn2;
+            }
+        } else {
+            float cm;
+            if (ui >= kFarLog2) {
+                cm = mi_cost2(tot, ui);
+            } else {
+                // the sent point itself is far from y (or y is not finite)
+                float yc[DIM], ls0[MDGMI_MAX_BITS], ls1[MDGMI_MAX_BITS], ltot, ti = 0.0f;
+#pragma unroll
+                for (int d = 0; d < DIM; d++) yc[d] = ys[i * DIM + d];
+                exact_classes_f32<DIM>(yc, X32, M, m, s, (int)slot, ls0, ls1, ltot, ti);
+                cg = 0.0f;
+#pragma unroll
+                for (int k = 0; k < MDGMI_MAX_BITS; k++) {
+                    if (k < m) {
+                        const bool b = (slot >> k) & 1;
+                        cg += bit_cost2(b ? ls0[k] - ls1[k] : ls1[k] - ls0[k]);
+                    }
+                }
+                cm = ltot + ti;
+            }
+            if (!row_ok) cg = cm = NAN;
+            acc.add((double)cg, (double)cm);
         }
     }
 }

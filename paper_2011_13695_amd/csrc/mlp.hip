@@ -14,7 +14,7 @@
 #include <random>
 #include <vector>
 
-#include "internal.h"
+#include "device_common.h"
 #include "mlp_gemm.h"
 
 using mdgmi::mlp::GemmArgs;
@@ -479,6 +479,120 @@ int mdgmi_mlp_load(mdgmi_mlp* net, const char* path) {
     net->step = step;
     refresh_all(net, nullptr);
     return hipDeviceSynchronize() == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- learned GMI
+namespace mdgmi {
+namespace {
+
+// Per-sample GMI cost of the logits (read as LLRs, nats) in bits, summed per
+// block in FP64: partials {sum c, sum c^2, 0, 0, non-finite count}.
+__global__ __launch_bounds__(256) void k_learned_cost(const float* __restrict__ logits, const uint32_t* __restrict__ tx,
+                                                      const uint32_t* __restrict__ labels, int64_t n, int M, int m,
+                                                      double* __restrict__ part) {
+    double s = 0.0, s2 = 0.0, bad = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t row = tx[i];
+        float c;
+        if (row < (uint32_t)M) {
+            const uint32_t lab = labels[row];
+            c = 0.0f;
+            for (int k = 0; k < m; k++) {
+                const float z = logits[i * m + k] * 1.4426950408889634f;  // to log2 units
+                const float x = ((lab >> k) & 1) ? -z : z;                 // log2(S_other / S_sent)
+                c += fmaxf(x, 0.0f) + __builtin_amdgcn_logf(1.0f + __builtin_amdgcn_exp2f(-fabsf(x)));
+            }
+        } else {
+            c = NAN;
+        }
+        const double d = (double)c;
+        s += d;
+        s2 += d * d;
+        bad += (d - d == 0.0) ? 0.0 : 1.0;
+    }
+    CostAcc a;
+    a.sg = s;
+    a.sg2 = s2;
+    a.bad = bad;
+    block_reduce_store(a, part + (size_t)blockIdx.x * kNPart);
+}
+
+__global__ void k_learned_finish(const double* __restrict__ part, int nb, int64_t n, int m, double* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0, s2 = 0.0, bad = 0.0;
+    for (int b = 0; b < nb; b++) {
+        s += part[(size_t)b * kNPart + 0];
+        s2 += part[(size_t)b * kNPart + 1];
+        bad += part[(size_t)b * kNPart + 4];
+    }
+    const double N = (double)n;
+    out[MDGMI_F_GMI] = m - s / N;
+    out[MDGMI_F_MI] = NAN;  // the learned demapper gives bit metrics only
+    const double v = n > 1 ? (s2 - s * s / N) / (N - 1.0) : 0.0;
+    out[MDGMI_F_SE_GMI] = sqrt(fmax(v, 0.0) / N);
+    out[MDGMI_F_SE_MI] = NAN;
+    out[MDGMI_F_N] = N;
+    out[MDGMI_F_NONFINITE] = bad;
+}
+
+constexpr int kLearnedBlocks = 1024;
+
+}  // namespace
+}  // namespace mdgmi
+
+extern "C" {
+
+int mdgmi_mlp_gmi_workspace_size(const mdgmi_mlp* net, int64_t chunk, size_t* bytes) {
+    if (!net || !bytes) return MDGMI_E_NULL;
+    if (chunk < 1 || chunk > (int64_t)1 << 26) return MDGMI_E_SHAPE;
+    const MlpWs w = mlp_ws(net, chunk);
+    *bytes = (size_t)(al(chunk * net->sizes[0] * 4) + w.total + al(kLearnedBlocks * kNPart * 8));
+    return MDGMI_OK;
+}
+
+int mdgmi_mlp_gmi(const mdgmi_mlp* net, const mdgmi_format* fmt, const float* y, const uint32_t* tx_idx, int64_t n,
+                  const double* snr_db_host, int32_t n_snr, int64_t chunk, double* out, void* ws, size_t ws_bytes,
+                  void* stream) {
+    if (!net || !fmt || !y || !tx_idx || !snr_db_host || !out || !ws) return MDGMI_E_NULL;
+    if (n < 1 || n_snr < 1 || chunk < 1) return MDGMI_E_SHAPE;
+    if (net->sizes[0] != fmt->dim + 1 || net->sizes[net->L] != fmt->m) return MDGMI_E_SHAPE;
+    for (int q = 0; q < n_snr; q++)
+        if (!std::isfinite(snr_db_host[q])) return MDGMI_E_ARG;
+    size_t need = 0;
+    int rc = mdgmi_mlp_gmi_workspace_size(net, chunk, &need);
+    if (rc != MDGMI_OK) return rc;
+    if (ws_bytes < need) return MDGMI_E_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)ws;
+    float* x = (float*)base;
+    char* mws = base + al(chunk * net->sizes[0] * 4);
+    const MlpWs w = mlp_ws(net, chunk);
+    double* part = (double*)(mws + w.total);
+    const int dim = fmt->dim, m = fmt->m;
+    for (int q = 0; q < n_snr; q++) {
+        const float* yq = y + (size_t)q * n * dim;
+        const uint32_t* tq = tx_idx + (size_t)q * n;
+        // chunks are processed in order; each writes its own block partials
+        const int64_t nchunks = (n + chunk - 1) / chunk;
+        const int per = std::max<int>(1, kLearnedBlocks / (int)std::min<int64_t>(nchunks, kLearnedBlocks));
+        int used = 0;
+        for (int64_t c0 = 0; c0 < n; c0 += chunk) {
+            const int64_t nc = std::min(chunk, n - c0);
+            if ((rc = mdgmi_mlp_features(yq + c0 * dim, nc, dim, snr_db_host[q], x, stream)) != MDGMI_OK) return rc;
+            if (forward(net, x, nc, mws, w, st) != hipSuccess) return MDGMI_E_HIP;
+            const int nb = (int)std::min<int64_t>(per, (nc + 255) / 256);
+            if (used + nb > kLearnedBlocks) return MDGMI_E_SHAPE;  // too many chunks for the partial table
+            hipLaunchKernelGGL(k_learned_cost, dim3(nb), dim3(256), 0, st, (const float*)(mws + w.logits), tq + c0,
+                               fmt->d_labels, nc, fmt->M, m, part + (size_t)used * kNPart);
+            used += nb;
+        }
+        hipLaunchKernelGGL(k_learned_finish, dim3(1), dim3(64), 0, st, part, used, n, m,
+                           out + (size_t)q * MDGMI_NFIELDS);
+        if (hipGetLastError() != hipSuccess) return MDGMI_E_HIP;
+    }
+    return MDGMI_OK;
 }
 
 }  // extern "C"

@@ -342,3 +342,144 @@ def mdgmi_tune_clear() -> None:
 
 def mdgmi_get_tuning() -> int:
     return int(lib().mdgmi_get_tuning())
+
+
+# ------------------------------------------------------------------ learned demapper
+def _mlp_sigs():
+    L = lib()
+    if getattr(L, "_mlp_sigs", False):
+        return L
+    L.mdgmi_mlp_create.argtypes = [_P, ctypes.c_int32, ctypes.c_uint64, ctypes.POINTER(_P)]
+    L.mdgmi_mlp_destroy.argtypes = [_P]
+    L.mdgmi_mlp_param_count.argtypes = [_P, ctypes.POINTER(ctypes.c_int64)]
+    L.mdgmi_mlp_get_params.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_int32]
+    L.mdgmi_mlp_set_params.argtypes = [_P, _P, ctypes.c_int64]
+    L.mdgmi_mlp_workspace_size.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
+    L.mdgmi_mlp_features.argtypes = [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_double, _P, _P]
+    L.mdgmi_mlp_forward.argtypes = [_P, _P, ctypes.c_int64, _P, _P, ctypes.c_size_t, _P]
+    L.mdgmi_mlp_loss_grad.argtypes = [_P, _P, _P, ctypes.c_int64, _P, _P, ctypes.c_size_t, _P]
+    L.mdgmi_mlp_adam_step.argtypes = [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]
+    L.mdgmi_mlp_save.argtypes = [_P, ctypes.c_char_p]
+    L.mdgmi_mlp_load.argtypes = [_P, ctypes.c_char_p]
+    L._mlp_sigs = True
+    return L
+
+
+class MLP:
+    """mdgmi_mlp handle: FP32 masters + bf16 copies on the device."""
+
+    def __init__(self, sizes, seed: int = 0):
+        L = _mlp_sigs()
+        self.sizes = [int(v) for v in sizes]
+        arr = (ctypes.c_int32 * len(self.sizes))(*self.sizes)
+        h = _P()
+        _check("mdgmi_mlp_create", L.mdgmi_mlp_create(ctypes.cast(arr, _P), len(self.sizes) - 1, int(seed),
+                                                      ctypes.byref(h)))
+        self.handle = h
+        c = ctypes.c_int64()
+        _check("mdgmi_mlp_param_count", L.mdgmi_mlp_param_count(h, ctypes.byref(c)))
+        self.P = c.value
+        self._ws = None
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mdgmi_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _get(self, which):
+        out = np.empty(self.P, dtype=np.float32)
+        _check("mdgmi_mlp_get_params", lib().mdgmi_mlp_get_params(self.handle, out.ctypes.data_as(_P), self.P, which))
+        return out
+
+    def params(self):
+        return self._get(0)
+
+    def grad(self):
+        return self._get(1)
+
+    def moments(self):
+        return self._get(2), self._get(3)
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.P
+        _check("mdgmi_mlp_set_params", lib().mdgmi_mlp_set_params(self.handle, p.ctypes.data_as(_P), self.P))
+
+    def workspace(self, n):
+        b = ctypes.c_size_t()
+        _check("mdgmi_mlp_workspace_size", lib().mdgmi_mlp_workspace_size(self.handle, n, ctypes.byref(b)))
+        if self._ws is None or self._ws.numel() < b.value:
+            self._ws = workspace(b.value)
+        return self._ws
+
+    def forward(self, x, out=None, stream=None):
+        import torch
+        n = x.shape[0]
+        assert x.is_contiguous() and x.dtype == torch.float32 and x.shape[1] == self.sizes[0]
+        if out is None:
+            out = torch.empty((n, self.sizes[-1]), dtype=torch.float32, device="cuda")
+        ws = self.workspace(n)
+        _check("mdgmi_mlp_forward", lib().mdgmi_mlp_forward(self.handle, _dptr(x), n, _dptr(out), _dptr(ws),
+                                                            ws.numel(), _stream(stream)))
+        return out
+
+    def loss_grad(self, x, target_llr, loss=None, stream=None):
+        import torch
+        n = x.shape[0]
+        assert x.is_contiguous() and target_llr.is_contiguous() and target_llr.shape == (n, self.sizes[-1])
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float64, device="cuda")
+        ws = self.workspace(n)
+        _check("mdgmi_mlp_loss_grad", lib().mdgmi_mlp_loss_grad(self.handle, _dptr(x), _dptr(target_llr), n,
+                                                                _dptr(loss), _dptr(ws), ws.numel(), _stream(stream)))
+        return loss
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check("mdgmi_mlp_adam_step", lib().mdgmi_mlp_adam_step(self.handle, lr, beta1, beta2, eps, _stream(stream)))
+
+    def save(self, path):
+        _check("mdgmi_mlp_save", lib().mdgmi_mlp_save(self.handle, str(path).encode()))
+
+    def load(self, path):
+        _check("mdgmi_mlp_load", lib().mdgmi_mlp_load(self.handle, str(path).encode()))
+
+
+def mdgmi_mlp_features(y, snr_db: float, x=None, stream=None):
+    """x [n, dim + 1] = [y, (snr_db - 9.5) / 4.5] on the device."""
+    import torch
+    n, dim = y.shape
+    if x is None:
+        x = torch.empty((n, dim + 1), dtype=torch.float32, device="cuda")
+    _check("mdgmi_mlp_features", _mlp_sigs().mdgmi_mlp_features(_dptr(y), n, dim, float(snr_db), _dptr(x),
+                                                                 _stream(stream)))
+    return x
+
+
+def mdgmi_mlp_gmi(net: "MLP", fmt: Format, y, tx_idx, snr_db, chunk: int = 1 << 20, out=None, ws=None, stream=None):
+    """Learned GMI per SNR point: y [n_snr, n, dim], tx [n_snr, n] -> out [n_snr, 6] (MI fields NaN)."""
+    import torch
+    L = _mlp_sigs()
+    if not getattr(L, "_mlp_gmi_sigs", False):
+        L.mdgmi_mlp_gmi_workspace_size.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
+        L.mdgmi_mlp_gmi.argtypes = [_P, _P, _P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int64, _P, _P,
+                                    ctypes.c_size_t, _P]
+        L._mlp_gmi_sigs = True
+    snr = np.ascontiguousarray(np.atleast_1d(snr_db), dtype=np.float64)
+    n_snr = snr.size
+    n = y.numel() // (fmt.dim * n_snr)
+    chunk = int(min(chunk, n))
+    if out is None:
+        out = torch.empty((n_snr, MDGMI_NFIELDS), dtype=torch.float64, device="cuda")
+    if ws is None:
+        b = ctypes.c_size_t()
+        _check("mdgmi_mlp_gmi_workspace_size", L.mdgmi_mlp_gmi_workspace_size(net.handle, chunk, ctypes.byref(b)))
+        ws = workspace(b.value)
+    _check("mdgmi_mlp_gmi", L.mdgmi_mlp_gmi(net.handle, fmt.handle, _dptr(y), _dptr(tx_idx), n, snr.ctypes.data_as(_P),
+                                            n_snr, chunk, _dptr(out), _dptr(ws), ws.numel(), _stream(stream)))
+    return out

@@ -154,9 +154,7 @@ def test_gmi_parity(orc, name, snrs, path):
     np.testing.assert_array_equal(out[:, 5], ref[:, 5])
     assert np.max(np.abs(out[:, 0] - ref[:, 0])) <= tol, (out[:, 0], ref[:, 0])
     assert np.max(np.abs(out[:, 1] - ref[:, 1])) <= tol, (out[:, 1], ref[:, 1])
-    # SE: the MFMA path's per-sample MI cost carries the fp16-split rounding of
-    # u_i (~1e-4 at 20 dB), which shows where the exact per-sample costs are 0
-    np.testing.assert_allclose(out[:, 2:4], ref[:, 2:4], rtol=1e-3, atol=2e-5)
+    np.testing.assert_allclose(out[:, 2:4], ref[:, 2:4], rtol=1e-3, atol=1e-6)
 
 
 def test_many_snrs_in_one_call(orc):
@@ -169,6 +167,9 @@ def test_many_snrs_in_one_call(orc):
         out = mdgmi.mdgmi_gmi(gf, dev(y.astype(np.float32), torch.float32), dev_u32(tx), s2, path=path).cpu().numpy()
         ref = orc.gmi_per_snr(y.astype(np.float32).astype(np.float64), tx, f.X, f.labels, s2)
         assert np.max(np.abs(out[:, :2] - ref[:, :2])) <= GMI_TOL32
+        # with the sent point's u taken from the matrix cores themselves the MI
+        # of the split path is as close as the direct path's
+        assert np.max(np.abs(out[:, 1] - ref[:, 1])) <= 1e-5
 
 
 @pytest.mark.parametrize("path", ["f64"] + F32_PATHS)
