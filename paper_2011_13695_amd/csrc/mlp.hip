@@ -30,12 +30,25 @@ struct mdgmi_mlp {
     float* d_grad = nullptr;
     __bf16* d_w[MDGMI_MLP_MAX_LAYERS] = {nullptr};   // [out][in]
     __bf16* d_wt[MDGMI_MLP_MAX_LAYERS] = {nullptr};  // [in][out]
+    __bf16* d_wf[4] = {nullptr};                     // fused-inference layout (fused shapes only)
+    bool fused = false;
     int64_t step = 0;
     int device = 0;
     int width = 0;  // widest layer
 };
 
 namespace mdgmi {
+
+// mlp_fused.hip
+bool fused_shape_ok(const int* sizes, int L);
+size_t fused_weight_bytes(int layer);
+hipError_t build_fused_weights(const float* W, int out, int in, int layer, __bf16* dst, hipStream_t st);
+int fused_grid();
+extern int g_fused_waves;
+hipError_t launch_mlp_gmi_fused(__bf16* const* wf, const float* const* bias, int in_dim, int out_dim, const float* y,
+                                int dim, const uint32_t* tx, const uint32_t* labels, int M, int64_t n, float snr_feat,
+                                double* part, int grid, hipStream_t st);
+
 namespace {
 
 using namespace mlp;
@@ -224,6 +237,7 @@ void refresh_all(mdgmi_mlp* net, hipStream_t st) {
         const int in = net->sizes[l], out = net->sizes[l + 1];
         hipLaunchKernelGGL(k_refresh, dim3((unsigned)(((int64_t)out * in + 255) / 256)), dim3(256), 0, st,
                            net->d_params + net->woff[l], out, in, net->d_w[l], net->d_wt[l]);
+        if (net->fused) (void)build_fused_weights(net->d_params + net->woff[l], out, in, l, net->d_wf[l], st);
     }
 }
 
@@ -277,6 +291,8 @@ int mdgmi_mlp_create(const int32_t* sizes, int32_t n_layers, uint64_t seed, mdgm
         const int64_t cnt = (int64_t)sizes[l + 1] * sizes[l];
         ok = hipMalloc(&net->d_w[l], 2 * cnt) == hipSuccess && hipMalloc(&net->d_wt[l], 2 * cnt) == hipSuccess;
     }
+    net->fused = fused_shape_ok(net->sizes, net->L);
+    for (int l = 0; ok && net->fused && l < 4; l++) ok = hipMalloc(&net->d_wf[l], fused_weight_bytes(l)) == hipSuccess;
     ok = ok && hipMemcpy(net->d_params, h.data(), sizeof(float) * p, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemset(net->d_m, 0, sizeof(float) * p) == hipSuccess &&
          hipMemset(net->d_v, 0, sizeof(float) * p) == hipSuccess &&
@@ -303,6 +319,8 @@ int mdgmi_mlp_destroy(mdgmi_mlp* net) {
         (void)hipFree(net->d_w[l]);
         (void)hipFree(net->d_wt[l]);
     }
+    for (int l = 0; l < 4; l++)
+        if (net->d_wf[l]) (void)hipFree(net->d_wf[l]);
     delete net;
     return MDGMI_OK;
 }
@@ -571,6 +589,21 @@ int mdgmi_mlp_gmi(const mdgmi_mlp* net, const mdgmi_format* fmt, const float* y,
     const MlpWs w = mlp_ws(net, chunk);
     double* part = (double*)(mws + w.total);
     const int dim = fmt->dim, m = fmt->m;
+    if (net->fused && g_fused_waves != 0 && fused_grid() <= kLearnedBlocks) {
+        const float* bias[4] = {net->d_params + net->boff[0], net->d_params + net->boff[1],
+                                net->d_params + net->boff[2], net->d_params + net->boff[3]};
+        const int grid = fused_grid();
+        for (int q = 0; q < n_snr; q++) {
+            const float feat = (float)((snr_db_host[q] - 9.5) / 4.5);
+            if (launch_mlp_gmi_fused(net->d_wf, bias, net->sizes[0], net->sizes[4], y + (size_t)q * n * dim, dim,
+                                     tx_idx + (size_t)q * n, fmt->d_labels, fmt->M, n, feat, part, grid, st) !=
+                hipSuccess)
+                return MDGMI_E_HIP;
+            hipLaunchKernelGGL(k_learned_finish, dim3(1), dim3(64), 0, st, part, grid, n, m,
+                               out + (size_t)q * MDGMI_NFIELDS);
+        }
+        return hipGetLastError() == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+    }
     for (int q = 0; q < n_snr; q++) {
         const float* yq = y + (size_t)q * n * dim;
         const uint32_t* tq = tx_idx + (size_t)q * n;

@@ -1,0 +1,295 @@
+// Fused inference of the MLP demapper with the GMI cost of its logits.
+//
+// Shape served: [in <= 16, 256, 256, 256, out <= 32]. Every layer is computed
+// transposed, H_l^T = W_l H_(l-1)^T, on v_mfma_f32_32x32x16_bf16 with the
+// weights as the A operand (rows = output features) and the activations as
+// the B operand (columns = 32 samples of one wave). The MFMA output leaves
+// each lane with 16 features of its sample; converted to bf16 they are
+// directly the B operand of the next layer's K-blocks, provided the
+// weights' input columns are permuted to match (layout built by
+// k_fused_weights): for a K-block of 16 inputs, lane half h holds inputs
+// {4h..4h+3, 8+4h..8+4h+3}. Activations never leave registers.
+//
+// LDS: W_1 (8 KiB), W_4 (16 KiB) and all biases stay resident; W_2 and W_3
+// (128 KiB each) are staged in turn into one buffer, once per block of 256
+// samples (8 waves x 32). The logits are turned into the per-sample GMI cost
+// in the kernel; only FP64 block partials are written.
+#include <algorithm>
+#include <cmath>
+
+#include "device_common.h"
+#include "mlp_gemm.h"
+
+namespace mdgmi {
+namespace fused {
+
+using mlp::bf16x8;
+using mlp::f32x16;
+
+constexpr int kH = 256;                 // hidden width
+constexpr int kTiles = kH / 32;         // output tiles of a hidden layer
+constexpr int kKB = kH / 16;            // K-blocks of a hidden layer input
+// LDS layout in 16-byte units
+constexpr int kW1U = kTiles * 1 * 64;           // 512
+constexpr int kW4U = 1 * kKB * 64;              // 1024
+constexpr int kWHU = kTiles * kKB * 64;         // 8192 (128 KiB)
+constexpr int kBiasF = 3 * kH + 32;             // floats
+
+union P8 {
+    bf16x8 v;
+    uint4 u;
+    __bf16 h[8];
+};
+
+__device__ __forceinline__ int perm_in(int h, int i) { return i < 4 ? 4 * h + i : 8 + 4 * h + (i - 4); }
+
+// Accumulator seeded with the bias of output tile ot: register r of lane
+// half h is row 8 (r >> 2) + 4 h + (r & 3), four runs of four consecutive
+// rows, i.e. four 16-byte LDS reads straight into the accumulator.
+__device__ __forceinline__ f32x16 bias_acc(const float* __restrict__ bias, int ot, int h) {
+    f32x16 a;
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+        const float4 v = *(const float4*)(bias + 32 * ot + 8 * g + 4 * h);
+        a[4 * g + 0] = v.x;
+        a[4 * g + 1] = v.y;
+        a[4 * g + 2] = v.z;
+        a[4 * g + 3] = v.w;
+    }
+    return a;
+}
+
+// Fused-layout weights of one layer: [out tile][K-block][lane][8] bf16.
+// Layer 0 takes its inputs in natural order; later layers in the order the
+// previous MFMA output lands in registers.
+__global__ void k_fused_weights(const float* __restrict__ W, int out, int in, int permute, int n_tiles, int n_kb,
+                                __bf16* __restrict__ dst) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one per (tile, kb, lane)
+    if (g >= (int64_t)n_tiles * n_kb * 64) return;
+    const int lane = (int)(g % 64), kb = (int)((g / 64) % n_kb), t = (int)(g / (64 * n_kb));
+    const int row = 32 * t + (lane & 31), h = lane >> 5;
+    P8 p;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const int k = 16 * kb + (permute ? perm_in(h, i) : 8 * h + i);
+        p.h[i] = (row < out && k < in) ? (__bf16)W[(int64_t)row * in + k] : (__bf16)0.0f;
+    }
+    ((uint4*)dst)[g] = p.u;
+}
+
+// One hidden layer: in activations act_in [kTiles][2] (bf16x8 per lane),
+// weights in LDS (fused layout), out activations gelu(W h + b) into act_out.
+// Output tiles go in two halves of four: per half, K-major order with four
+// independent accumulation chains, so the live set is 4 x 16 accumulators,
+// the resident input activations, one K-block of weight operands and the
+// output half done so far.
+__device__ __forceinline__ void hidden_layer(const uint4* __restrict__ Wl, const float* __restrict__ bias,
+                                             const bf16x8 (&act_in)[kTiles][2], bf16x8 (&act_out)[kTiles][2],
+                                             int lane) {
+    const int h = lane >> 5;
+    constexpr int kHalf = kTiles / 2;
+#pragma unroll
+    for (int half = 0; half < 2; half++) {
+        f32x16 acc[kHalf];
+#pragma unroll
+        for (int j = 0; j < kHalf; j++) acc[j] = bias_acc(bias, half * kHalf + j, h);
+#pragma unroll
+        for (int kb = 0; kb < kKB; kb++) {
+#pragma unroll
+            for (int j = 0; j < kHalf; j++) {
+                const int ot = half * kHalf + j;
+                P8 a;
+                a.u = Wl[(ot * kKB + kb) * 64 + lane];
+                acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, act_in[kb >> 1][kb & 1], acc[j], 0, 0, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int j = 0; j < kHalf; j++) {
+            const int ot = half * kHalf + j;
+            P8 o0, o1;
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const __bf16 v = (__bf16)mlp::gelu_f(acc[j][r]);
+                if (r < 8)
+                    o0.h[r] = v;
+                else
+                    o1.h[r - 8] = v;
+            }
+            act_out[ot][0] = o0.v;
+            act_out[ot][1] = o1.v;
+        }
+    }
+}
+
+template <int kWaves>
+__global__ __launch_bounds__(kWaves * 64) void k_mlp_gmi_fused(
+    const uint4* __restrict__ w1f, const uint4* __restrict__ w2f, const uint4* __restrict__ w3f,
+    const uint4* __restrict__ w4f, const float* __restrict__ b1, const float* __restrict__ b2,
+    const float* __restrict__ b3, const float* __restrict__ b4, int in_dim, int out_dim, const float* __restrict__ y,
+    int dim, const uint32_t* __restrict__ tx, const uint32_t* __restrict__ labels, int M, int64_t n, float snr_feat,
+    double* __restrict__ part) {
+    constexpr int kThreads = kWaves * 64;
+    extern __shared__ uint4 lds[];
+    uint4* sW1 = lds;
+    uint4* sW4 = sW1 + kW1U;
+    float* sB = (float*)(sW4 + kW4U);
+    uint4* sWH = (uint4*)(sB + kBiasF);  // kBiasF * 4 bytes is a multiple of 16
+    for (int k = threadIdx.x; k < kW1U; k += kThreads) sW1[k] = w1f[k];
+    for (int k = threadIdx.x; k < kW4U; k += kThreads) sW4[k] = w4f[k];
+    for (int k = threadIdx.x; k < kBiasF; k += kThreads) {
+        float v;
+        if (k < kH)
+            v = b1[k];
+        else if (k < 2 * kH)
+            v = b2[k - kH];
+        else if (k < 3 * kH)
+            v = b3[k - 2 * kH];
+        else
+            v = (k - 3 * kH) < out_dim ? b4[k - 3 * kH] : 0.0f;
+        sB[k] = v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, col = lane & 31;
+    CostAcc acc;
+    const int64_t nblk = (n + kWaves * 32 - 1) / (kWaves * 32);
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int64_t i = blk * (kWaves * 32) + wave * 32 + col;
+        const bool valid = i < n;
+        // ---- layer 1: B operand = features in natural order, lane half h holds 8h..8h+7
+        bf16x8 xin;
+        {
+            P8 p;
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int f = 8 * h + q;
+                float v = 0.0f;
+                if (valid) {
+                    if (f < dim)
+                        v = y[i * dim + f];
+                    else if (f == dim)
+                        v = snr_feat;
+                }
+                p.h[q] = (__bf16)v;
+            }
+            xin = p.v;
+        }
+        __syncthreads();  // sW1 / sB staged (first pass) or previous block done with sWH
+        bf16x8 actA[kTiles][2], actB[kTiles][2];
+#pragma unroll
+        for (int ot = 0; ot < kTiles; ot++) {
+            P8 a;
+            a.u = sW1[ot * 64 + lane];
+            f32x16 z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, xin, bias_acc(sB, ot, h), 0, 0, 0);
+            P8 o0, o1;
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const __bf16 v = (__bf16)mlp::gelu_f(z[r]);
+                if (r < 8)
+                    o0.h[r] = v;
+                else
+                    o1.h[r - 8] = v;
+            }
+            actA[ot][0] = o0.v;
+            actA[ot][1] = o1.v;
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // ---- layer 2
+        for (int k = threadIdx.x; k < kWHU; k += kThreads) sWH[k] = w2f[k];
+        __syncthreads();
+        hidden_layer(sWH, sB + kH, actA, actB, lane);
+        __syncthreads();
+        // ---- layer 3
+        for (int k = threadIdx.x; k < kWHU; k += kThreads) sWH[k] = w3f[k];
+        __syncthreads();
+        hidden_layer(sWH, sB + 2 * kH, actB, actA, lane);
+        // ---- layer 4: logits, one output tile of 32 rows
+        f32x16 zo = bias_acc(sB + 3 * kH, 0, h);
+#pragma unroll
+        for (int kb = 0; kb < kKB; kb++) {
+            P8 a;
+            a.u = sW4[kb * 64 + lane];
+            zo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, actA[kb >> 1][kb & 1], zo, 0, 0, 0);
+        }
+        // ---- per-sample GMI cost of the logits (bits), both lane halves.
+        // Rows >= out_dim have zero weights and bias, so their logit is
+        // exactly 0 and their cost exactly softplus2(0); every row is costed
+        // and those are taken off in FP64 (no per-row masks to keep live).
+        const uint32_t row = valid ? tx[i] : 0u;
+        const bool row_ok = row < (uint32_t)M;
+        const uint32_t labh = labels[row_ok ? row : 0u] >> (4 * h);
+        double c = 0.0;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const float z = zo[r] * 1.4426950408889634f;
+            const float xx = ((labh >> (8 * (r >> 2) + (r & 3))) & 1) ? -z : z;
+            c += (double)(fmaxf(xx, 0.0f) + lg2(1.0f + ex2(-fabsf(xx))));
+        }
+        const float zero = 0.0f * snr_feat;  // a runtime 0 so the constant is computed like the rows
+        const double pad_cost = (double)(fmaxf(zero, 0.0f) + lg2(1.0f + ex2(-fabsf(zero))));
+        c += __shfl_xor(c, 32, 64);
+        c -= (double)(32 - out_dim) * pad_cost;
+        if (h == 0 && valid) acc.add(row_ok ? c : NAN, 0.0);
+    }
+    block_reduce_store(acc, part + (size_t)blockIdx.x * kNPart);
+}
+
+constexpr size_t kLdsBytes = (size_t)(kW1U + kW4U) * 16 + (size_t)kBiasF * 4 + (size_t)kWHU * 16;
+
+}  // namespace fused
+
+bool fused_shape_ok(const int* sizes, int L) {
+    return L == 4 && sizes[0] >= 1 && sizes[0] <= 16 && sizes[1] == fused::kH && sizes[2] == fused::kH &&
+           sizes[3] == fused::kH && sizes[4] >= 1 && sizes[4] <= 32;
+}
+
+size_t fused_weight_bytes(int layer) {
+    using namespace fused;
+    return 16 * (size_t)(layer == 0 ? kW1U : layer == 3 ? kW4U : kWHU);
+}
+
+hipError_t build_fused_weights(const float* W, int out, int in, int layer, __bf16* dst, hipStream_t st) {
+    using namespace fused;
+    const int n_tiles = (out + 31) / 32, n_kb = (in + 15) / 16;
+    const int64_t cnt = (int64_t)n_tiles * n_kb * 64;
+    hipLaunchKernelGGL(k_fused_weights, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, W, out, in,
+                       layer == 0 ? 0 : 1, n_tiles, n_kb, dst);
+    return hipGetLastError();
+}
+
+int fused_grid() { return device_cu_count(); }
+
+int g_fused_waves = 4;  // 4: one wave per SIMD with the whole register file; 8: two, tighter registers
+
+template <int W>
+hipError_t launch_fused_w(__bf16* const* wf, const float* const* bias, int in_dim, int out_dim, const float* y, int dim,
+                          const uint32_t* tx, const uint32_t* labels, int M, int64_t n, float snr_feat, double* part,
+                          int grid, hipStream_t st) {
+    using namespace fused;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_mlp_gmi_fused<W>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)kLdsBytes);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_mlp_gmi_fused<W>), dim3(grid), dim3(W * 64), kLdsBytes, st, (const uint4*)wf[0],
+                       (const uint4*)wf[1], (const uint4*)wf[2], (const uint4*)wf[3], bias[0], bias[1], bias[2],
+                       bias[3], in_dim, out_dim, y, dim, tx, labels, M, n, snr_feat, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_gmi_fused(__bf16* const* wf, const float* const* bias, int in_dim, int out_dim, const float* y,
+                                int dim, const uint32_t* tx, const uint32_t* labels, int M, int64_t n, float snr_feat,
+                                double* part, int grid, hipStream_t st) {
+    if (g_fused_waves == 8)
+        return launch_fused_w<8>(wf, bias, in_dim, out_dim, y, dim, tx, labels, M, n, snr_feat, part, grid, st);
+    return launch_fused_w<4>(wf, bias, in_dim, out_dim, y, dim, tx, labels, M, n, snr_feat, part, grid, st);
+}
+
+}  // namespace mdgmi
+
+extern "C" int mdgmi_mlp_set_fused(int waves) {
+    if (waves != 0 && waves != 4 && waves != 8) return MDGMI_E_ARG;
+    mdgmi::g_fused_waves = waves;
+    return MDGMI_OK;
+}

@@ -483,3 +483,8 @@ def mdgmi_mlp_gmi(net: "MLP", fmt: Format, y, tx_idx, snr_db, chunk: int = 1 << 
     _check("mdgmi_mlp_gmi", L.mdgmi_mlp_gmi(net.handle, fmt.handle, _dptr(y), _dptr(tx_idx), n, snr.ctypes.data_as(_P),
                                             n_snr, chunk, _dptr(out), _dptr(ws), ws.numel(), _stream(stream)))
     return out
+
+
+def mdgmi_mlp_set_fused(waves: int) -> None:
+    """Inference kernel of mdgmi_mlp_gmi: 4 or 8 waves fused, 0 layer by layer."""
+    _check("mdgmi_mlp_set_fused", lib().mdgmi_mlp_set_fused(int(waves)))

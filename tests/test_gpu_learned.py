@@ -76,3 +76,29 @@ def test_fallback_routes_to_exact(qam16):
     net.set_params(p)
     ev, _, _ = learned.evaluate(net, gf, [5.0], 2000)
     assert ev.route == ["exact"] and np.isnan(ev.gmi_learned[0])
+
+
+@pytest.mark.parametrize("waves", [4, 8])
+def test_fused_inference_matches_layered_path(waves, orc):
+    """The fused kernel (activations in registers) gives the GMI of the same
+    network as the layer-by-layer GEMM path and as the oracle's cost of the
+    layered path's logits."""
+    f = w.format_8d2048()
+    gf = mdgmi.Format.of(f)
+    net = mdgmi.MLP([9, 256, 256, 256, 11], seed=11)
+    snr = np.array([5.0, 12.0])
+    y, tx = mdgmi.mdgmi_generate(gf, 21, learned.sigma2_of(snr, 8), 5003, dtype=torch.float32)
+    say(f"[learned] fused waves={waves}")
+    try:
+        mdgmi.mdgmi_mlp_set_fused(0)
+        ref = mdgmi.mdgmi_mlp_gmi(net, gf, y, tx, snr).cpu().numpy()
+        mdgmi.mdgmi_mlp_set_fused(waves)
+        out = mdgmi.mdgmi_mlp_gmi(net, gf, y, tx, snr).cpu().numpy()
+    finally:
+        mdgmi.mdgmi_mlp_set_fused(4)
+    np.testing.assert_array_equal(out[:, 4], ref[:, 4])
+    assert np.max(np.abs(out[:, 0] - ref[:, 0])) <= 1e-3, (out[:, 0], ref[:, 0])
+    x = mdgmi.mdgmi_mlp_features(y[0].contiguous(), float(snr[0]))
+    logits = net.forward(x).cpu().numpy().astype(np.float64)
+    cost = orc.gmi_cost_from_llr(logits, f.labels[tx[0].cpu().numpy().view(np.uint32)])
+    assert abs(ref[0, 0] - (11 - cost.mean())) <= 1e-5
