@@ -6,8 +6,12 @@ step = one mdgmi_gmi call over the whole batch (per-SNR staging, demapping
 with exact per-bit LLRs, fused FP64 GMI/MI reduction). Metric: demapped
 sample*points per second = n_snr * n * M / time.
 
-Prints one JSON line. `--gpus N` with N > 1 exits: this build measures the
-one-GPU share only.
+Beside it: the FP32 direct-distance path on the same samples, the learned
+demapper (trained on exact-LLR targets, then timed against the exact path on
+the same held-out samples with per-SNR fallback), and the FP64 CPU oracle on
+a bounded sample.
+
+Prints one JSON line. `--gpus N` with N > 1 exits: the figure is one GPU's.
 """
 from __future__ import annotations
 
@@ -22,11 +26,37 @@ from pathlib import Path
 ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
-# MI355X published peaks (vector ALU): FP32 157.3 TFLOP/s = 78.6e12 lane FMA/s;
-# the transcendental unit (v_exp_f32) issues at a quarter of the FMA rate.
-VALU_LANE_OPS = 157.3e12 / 2
-EXP_PEAK = VALU_LANE_OPS / 4
+# MI355X vector ALU: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = 39.3e12 lane
+# instructions/s for plain FP32 ops (the published 157.3 TFLOP/s counts 2
+# flops per FMA and 2 per packed lane); v_exp_f32 takes twice the issue time
+# of a plain op, so the exponential peak is 19.66e12/s = 157.3e12 / 8.
+VALU_LANE_OPS = 157.3e12 / 4
+EXP_PEAK = VALU_LANE_OPS / 2
 HBM_PEAK = 8.0e12
+
+# HBM traffic of one k_mfma launch on this workload, from two rocprofv3 --pmc
+# passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what
+# the same counter reads for a plain copy kernel of known size (a 1 GiB copy
+# reads FETCH_SIZE = 0.5 GiB and WRITE_SIZE = 1 GiB: factors 2.0 and 1.0).
+# Reported only while the kernel sources hash to the value they were taken on.
+TRAFFIC = {"sources_sha1": None, "fetch_kib": None, "write_kib": None, "fetch_scale": 2.0, "write_scale": 1.0}
+KERNEL_SOURCES = ("mfma_core.h", "device_common.h", "internal.h", "exact_mfma.hip")
+
+
+def kernel_sources_sha1() -> str:
+    import hashlib
+    h = hashlib.sha1()
+    for name in KERNEL_SOURCES:
+        h.update((ROOT / "paper_2011_13695_amd" / "csrc" / name).read_bytes())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    t = TRAFFIC
+    if t["sources_sha1"] is None or t["sources_sha1"] != kernel_sources_sha1():
+        return None
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+METRIC = "demapped sample\u00b7points/sec at 8D M=2048 (exact vs learned) at |\u0394GMI|\u22640.01 b"
 
 
 def parse():
@@ -39,6 +69,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true", help="skip timing the FP32 direct path beside")
+    ap.add_argument("--learned-samples", type=float, default=2e8,
+                    help="training samples of the learned demapper (0 skips the learned leg)")
+    ap.add_argument("--learned-eval", type=float, default=1e8, help="held-out samples over the 16 SNR points")
+    ap.add_argument("--copy-probe", type=float, default=0,
+                    help="only run a plain device copy of this many bytes (HBM counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -70,6 +105,79 @@ def cpu_baseline(wl, target_s: float):
                       f"({pairs:.3g} sample*points, {elapsed:.1f} s, FP64, {threads} threads)"}
 
 
+def copy_probe(nbytes: float):
+    """A plain elementwise copy kernel of known size, for scaling the HBM
+    byte counters of the profiler: reads and writes nbytes once each."""
+    import torch
+    n = int(nbytes) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4, "launches": 3}))
+
+
+def learned_leg(gf, wl, args, log):
+    """Learned demapper on the same format: train on exact-LLR targets, then
+    time learned vs exact GMI on the same held-out samples and route each SNR
+    point (learned where the paired GMI loss is at most 0.01 bit)."""
+    import numpy as np
+    import torch
+
+    from paper_2011_13695_amd import learned, mdgmi
+    cfg = learned.TrainConfig(steps=max(1, int(args.learned_samples) // 16384), log_every=250)
+    tr = learned.Trainer(gf, cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = tr.train(log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"trained {res.samples} samples in {train_s:.1f} s")
+    snr = np.asarray(wl.snr_db, dtype=np.float64)
+    n_snr = snr.size
+    n_eval = max(1024, int(args.learned_eval) // n_snr)
+    ev, y, tx = learned.evaluate(tr.net, gf, snr, n_eval)
+    s2 = learned.sigma2_of(snr, gf.dim)
+    stream = torch.cuda.current_stream()
+    out = torch.empty((n_snr, mdgmi.MDGMI_NFIELDS), dtype=torch.float64, device="cuda")
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    lws = mdgmi.workspace(mdgmi.mdgmi_mlp_gmi_workspace_size(tr.net, min(1 << 20, n_eval)))
+    ews = mdgmi.workspace(mdgmi.mdgmi_gmi_workspace_size(gf, n_eval, n_snr, "mfma"))
+    t_learned = timed(lambda: mdgmi.mdgmi_mlp_gmi(tr.net, gf, y, tx, snr, out=out, ws=lws))
+    t_exact = timed(lambda: mdgmi.mdgmi_gmi(gf, y, tx, s2, path="mfma", out=out, ws=ews))
+    routed = [r == "learned" for r in ev.route]
+    t_mixed = sum((t_learned if r else t_exact) / n_snr for r in routed)
+    pts = n_snr * n_eval * gf.M
+    return {
+        "train_samples": res.samples, "train_seconds": train_s,
+        "final_train_loss_nats": res.losses[-1][1] if res.losses else None,
+        "eval_samples_per_snr": n_eval,
+        "learned_value": pts / (t_learned * 1e-3), "learned_ms": t_learned,
+        "exact_value_same_samples": pts / (t_exact * 1e-3), "exact_ms": t_exact,
+        "speedup_learned_vs_exact": t_exact / t_learned,
+        "mixed_value": pts / (t_mixed * 1e-3), "speedup_mixed_vs_exact": t_exact / t_mixed,
+        "snr_db": [float(v) for v in snr],
+        "gmi_exact": [float(v) for v in ev.gmi_exact], "gmi_learned": [float(v) for v in ev.gmi_learned],
+        "gmi_loss": [float(v) for v in ev.loss], "route": ev.route,
+        "n_learned_snr": int(sum(routed)), "max_loss_bound": 0.01,
+        "note": "learned value counts n*M sample*points per sample demapped by the network; mixed routes "
+                "each SNR point to the learned kernel where its paired GMI loss <= 0.01 bit, else exact",
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -84,6 +192,9 @@ def main():
     from paper_2011_13695_amd import mdgmi
 
     torch.cuda.set_device(0)
+    if args.copy_probe > 0:
+        copy_probe(args.copy_probe)
+        return
     wl = w.workload_8d2048(n=args.n)
     f = wl.fmt
     gf = mdgmi.Format.of(f)
@@ -125,7 +236,7 @@ def main():
                                 "max_abs_dgmi_vs_timed_path": float(np.abs(dout[:, :2] - out[:, :2]).max())}
     achieved = pairs / (kernel_ms * 1e-3)
     line = {
-        "metric": "demapped sample*points/sec at 8D M=2048 (exact)",
+        "metric": METRIC,
         "value": value,
         "unit": "sample*points/s",
         "n_gpus": 1,
@@ -141,13 +252,18 @@ def main():
                    "n_per_snr": wl.n, "snr_db": [float(v) for v in wl.snr_db], "path": args.path,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": EXP_PEAK / 1e12, "unit": "Texp/s",
-                     "frac": achieved / EXP_PEAK, "traffic": None,
+                     "frac": achieved / EXP_PEAK, "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch",
                      "kernel": "k_mfma (demap + fused reduction); 1 v_exp_f32 per (sample, point)",
                      "kernel_ms": kernel_ms},
         "gmi": [float(v) for v in out[:, 0]],
         "mi": [float(v) for v in out[:, 1]],
     }
     line.update(extra)
+    if args.learned_samples > 0:
+        def log(msg):
+            print(f"[bench] learned: {msg}", file=sys.stderr, flush=True)
+        line["learned"] = learned_leg(gf, wl, args, log)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line))

@@ -45,7 +45,7 @@ __device__ __forceinline__ float mi_cost2(float tot, float ui) {
 // S_nb = 0 gives x = -inf and cost 0; NaN propagates.
 __device__ __forceinline__ float bit_cost2(float x) { return softplus2(x); }
 
-// Class sums of the label bits above a group of G = 1, 2 or 4 consecutive
+// Class sums of the label bits above a group of G = 1, 2, 4 or 8 consecutive
 // blocks of points (a block is a chunk of consecutive labels; the block
 // index supplies these bits). Inside a group the lowest log2(G) block-index
 // bits are known at compile time; the bits above come from the group index
@@ -54,7 +54,7 @@ __device__ __forceinline__ float bit_cost2(float x) { return softplus2(x); }
 // registers. Unused high bits accumulate values that are never read.
 template <int G, int MAXHI>
 struct HiAcc {
-    static constexpr int GB = G == 4 ? 2 : (G == 2 ? 1 : 0);
+    static constexpr int GB = G == 8 ? 3 : (G == 4 ? 2 : (G == 2 ? 1 : 0));
     float R0[MAXHI > 0 ? MAXHI : 1], R1[MAXHI > 0 ? MAXHI : 1];
     __device__ __forceinline__ void zero() {
 #pragma unroll
@@ -68,13 +68,23 @@ struct HiAcc {
             R0[0] += T[0];
             R1[0] += T[1];
             GT = T[0] + T[1];
-        } else {
+        } else if (G == 4) {
             R0[0] += T[0] + T[2];
             R1[0] += T[1] + T[3];
             const float a = T[0] + T[1], b = T[2] + T[3];
             R0[1] += a;
             R1[1] += b;
             GT = a + b;
+        } else {
+            R0[0] += (T[0] + T[2]) + (T[4] + T[6]);
+            R1[0] += (T[1] + T[3]) + (T[5] + T[7]);
+            const float a0 = T[0] + T[1], a1 = T[2] + T[3], a2 = T[4] + T[5], a3 = T[6] + T[7];
+            R0[1] += a0 + a2;
+            R1[1] += a1 + a3;
+            const float q0 = a0 + a1, q1 = a2 + a3;
+            R0[2] += q0;
+            R1[2] += q1;
+            GT = q0 + q1;
         }
 #pragma unroll
         for (int l = GB; l < MAXHI; l++) {

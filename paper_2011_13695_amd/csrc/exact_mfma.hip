@@ -91,7 +91,9 @@ hipError_t launch_d(int var, bool lds, const mdgmi_format* f, const float* y, co
     return lds ? launch_v<DIM, NC, W, G, true>(f, y, tx, n, sa, llr_mode, llr, part, img, ntiles, blocks, st) \
                : launch_v<DIM, NC, W, G, false>(f, y, tx, n, sa, llr_mode, llr, part, img, ntiles, blocks, st);
 #define MDGMI_V(NC, W)             \
-    if (ntiles >= 4) {             \
+    if (ntiles >= 8) {             \
+        MDGMI_VG(NC, W, 8)         \
+    } else if (ntiles == 4) {      \
         MDGMI_VG(NC, W, 4)         \
     } else if (ntiles == 2) {      \
         MDGMI_VG(NC, W, 2)         \
@@ -123,16 +125,18 @@ constexpr int kNumVariants = kMfmaVariants;
 const MfmaVariant kVariants[kNumVariants] = {{1, 4, true},  {2, 4, true},  {1, 8, true},  {2, 8, true},
                                              {1, 16, true}, {1, 12, true}, {1, 16, false}, {1, 8, false}};
 
+size_t image_bytes_per_snr(const mdgmi_format* f) {
+    int ntiles = (f->M + 31) / 32;
+    return (size_t)ntiles * (f->dim == 8 ? 2 : 1) * 64 * sizeof(uint4);
+}
+
 int pick_variant(const mdgmi_format* f) {
     if (g_variant_override >= 0 && g_variant_override < kNumVariants) return g_variant_override;
     const int t = tuned_mfma_variant(f->dim, f->M);
     if (t >= 0 && t < kNumVariants) return t;
-    return 3;
-}
-
-size_t image_bytes_per_snr(const mdgmi_format* f) {
-    int ntiles = (f->M + 31) / 32;
-    return (size_t)ntiles * (f->dim == 8 ? 2 : 1) * 64 * sizeof(uint4);
+    // untuned: a large image leaves room for one block per CU, so 16 waves
+    // per block fill the CU; small images run several 8-wave blocks per CU
+    return image_bytes_per_snr(f) > 32 * 1024 ? 4 : 2;
 }
 
 }  // namespace

@@ -28,8 +28,8 @@
 // in label order, label bits 0, 1, 3, 4 of the point are bits of r, bit 2 is
 // the lane half and bits 5.. are the tile index. Each lane keeps a running
 // bank[r] of its 16 exponentials (one add per pair) and adds the tile total
-// (15 adds per 16 pairs) to the classes of the tile-index bits; the two lane
-// halves are combined once per sample at the end.
+// (15 adds per 16 pairs) to the classes of the tile-index bits, eight tiles
+// at a time; the two lane halves are combined once per sample at the end.
 #include "device_common.h"
 
 namespace mdgmi {
@@ -196,14 +196,31 @@ __device__ __forceinline__ void make_b(const float* yv, float K, int h, half8* b
     }
 }
 
+// Operands of one tile for this lane: p points at [tile][blk 0][half][row]
+// of the lane's half and row; blocks are 64 uint4 apart.
 template <int NB>
-__device__ __forceinline__ void load_a(const uint4* __restrict__ A, int t, int h, int col, half8* a) {
+__device__ __forceinline__ void load_a_at(const uint4* __restrict__ p, half8* a) {
 #pragma unroll
     for (int b = 0; b < NB; b++) {
         H8 tmp;
-        tmp.u = A[((t * NB + b) * 2 + h) * 32 + col];
+        tmp.u = p[b * 64];
         a[b] = tmp.v;
     }
+}
+
+// Values of a register in the lower (lanes 0-31) and upper (32-63) half of
+// the wave, seen by every lane (v_permlane32_swap).
+struct Halves {
+    float lo, hi;
+};
+__device__ __forceinline__ Halves halves(float v) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return {__uint_as_float(r[0]), __uint_as_float(r[1])};
+}
+// lower + upper, formed in this order in every lane
+__device__ __forceinline__ float half_sum(float v) {
+    const Halves t = halves(v);
+    return t.lo + t.hi;
 }
 
 template <int NB>
@@ -252,28 +269,38 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
         hi[c].zero();
     }
     // Software pipeline: the MFMA of tile t+1 is in flight while the
-    // exponentials of tile t issue, and the LDS operands of tile t+2 are
-    // loaded meanwhile. Tile indices wrap (ntiles is a power of two), so
-    // the last step computes one unused tile instead of branching.
+    // exponentials of tile t issue, and the operands of tile t+2 are loaded
+    // meanwhile. Tile indices wrap (ntiles is a power of two and a multiple
+    // of G), so the last steps compute unused tiles instead of branching; the
+    // wrap is applied once per group through two base pointers (for G >= 2,
+    // tiles t + 2 past the group are the first two of the next group).
+    constexpr int TS = NB * 64;  // uint4 per tile of the image
     const int tmask = ntiles - 1;
+    const uint4* __restrict__ Al = A + h * 32 + col;
     half8 a_nxt[NB];
     f32x16 u_nxt[NCOL];
-    load_a<NB>(A, 0, h, col, a_nxt);
+    load_a_at<NB>(Al, a_nxt);
 #pragma unroll
     for (int c = 0; c < NCOL; c++) u_nxt[c] = tile_mfma<NB>(a_nxt, bop[c]);
-    load_a<NB>(A, 1 & tmask, h, col, a_nxt);
+    load_a_at<NB>(Al + (1 & tmask) * TS, a_nxt);
     for (int g0 = 0; g0 < ntiles; g0 += G) {
+        const uint4* __restrict__ Acur = Al + g0 * TS;
+        const uint4* __restrict__ Anxt = Al + ((g0 + G) & tmask) * TS;
         float T[NCOL][G];
 #pragma unroll
         for (int i = 0; i < G; i++) {
-            const int t = g0 + i;
             f32x16 u_cur[NCOL];
 #pragma unroll
             for (int c = 0; c < NCOL; c++) {
                 u_cur[c] = u_nxt[c];
                 u_nxt[c] = tile_mfma<NB>(a_nxt, bop[c]);
             }
-            load_a<NB>(A, (t + 2) & tmask, h, col, a_nxt);
+            if (G == 1)
+                load_a_at<NB>(Al + ((g0 + 2) & tmask) * TS, a_nxt);
+            else if (i + 2 < G)
+                load_a_at<NB>(Acur + (i + 2) * TS, a_nxt);
+            else
+                load_a_at<NB>(Anxt + (i + 2 - G) * TS, a_nxt);
 #pragma unroll
             for (int c = 0; c < NCOL; c++) {
                 float ev[16];
@@ -291,17 +318,71 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
                     T[c][i] = ev[0];
                 }
             }
+            // keep one tile's accumulators in flight: without this fence the
+            // independent MFMAs of the whole group are hoisted together
+            __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int c = 0; c < NCOL; c++) hi[c].add_group(g0 / G, T[c]);
     }
-    // ---- epilogue: class sums one label bit at a time, then LLRs / costs ----
-    // (streamed per bit so that few values stay live; the exact per-class
-    // path below recomputes everything from y when it is needed)
+    // ---- epilogue ----
+    // Each lane folds its own 16 rows into per-bit partial class sums; the
+    // two lane halves (rows differing in label bit 2) are combined with one
+    // lane swap per value, summed in the same order in both halves so that
+    // both hold identical class sums; each half then finishes every other
+    // label bit (half h takes bits h, h + 2, ...). Bits are streamed in pairs
+    // so that few class sums are live at a time.
 #pragma unroll
     for (int c = 0; c < NCOL; c++) {
         const int64_t i = idx[c];
-        const bool mine = (h == 0) && (i < n);
+        float* b = bank[c];
+        float p0[MDGMI_MAX_BITS], p1[MDGMI_MAX_BITS];  // this half's partial class sums
+        // label bits 0, 1, 3, 4 are bits 0..3 of the register index
+        p0[0] = ((b[0] + b[2]) + (b[4] + b[6])) + ((b[8] + b[10]) + (b[12] + b[14]));
+        p1[0] = ((b[1] + b[3]) + (b[5] + b[7])) + ((b[9] + b[11]) + (b[13] + b[15]));
+#pragma unroll
+        for (int j = 0; j < 8; j++) b[j] = b[2 * j] + b[2 * j + 1];
+        p0[1] = (b[0] + b[2]) + (b[4] + b[6]);
+        p1[1] = (b[1] + b[3]) + (b[5] + b[7]);
+#pragma unroll
+        for (int j = 0; j < 4; j++) b[j] = b[2 * j] + b[2 * j + 1];
+        p0[3] = b[0] + b[2];
+        p1[3] = b[1] + b[3];
+        p0[4] = b[0] + b[1];
+        p1[4] = b[2] + b[3];
+        p0[2] = p1[2] = p0[4] + p1[4];  // this half's total; label bit 2 is the lane half
+#pragma unroll
+        for (int k = 5; k < MDGMI_MAX_BITS; k++) {  // tile-index bits
+            p0[k] = k < m ? hi[c].R0[k - 5] : 1.0f;
+            p1[k] = k < m ? hi[c].R1[k - 5] : 1.0f;
+        }
+        // full class sums of bit k, identical in both halves
+        auto sums = [&](int k, float& S0k, float& S1k) {
+            if (k == 2) {
+                const Halves t = halves(p0[2]);
+                S0k = t.lo;
+                S1k = t.hi;
+            } else {
+                S0k = half_sum(p0[k]);
+                S1k = half_sum(p1[k]);
+            }
+        };
+        float S0t, S1t;
+        sums(2, S0t, S1t);
+        const float tot = S0t + S1t;
+        bool slow = false;
+        if (LLR) {
+            float smin = INFINITY;
+#pragma unroll
+            for (int k = 0; k < MDGMI_MAX_BITS; k++) {
+                if (k < m) {
+                    float S0k, S1k;
+                    sums(k, S0k, S1k);
+                    smin = fminf(smin, fminf(S0k, S1k));
+                }
+            }
+            slow = !(smin >= ex2(kFarLog2));
+        }
         uint32_t slot = 0;
         bool row_ok = true;
         float ui = 0.0f;
@@ -317,57 +398,43 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
             // error. Diagonal element r sits in lane half (r >> 2) & 1,
             // register ((r >> 3) << 2) | (r & 3).
             half8 ad[NB];
-            load_a<NB>(A, (int)(slot >> 5), h, (int)(slot & 31), ad);
+            load_a_at<NB>(A + (int)(slot >> 5) * TS + h * 32 + (int)(slot & 31), ad);
             const f32x16 ud = tile_mfma<NB>(ad, bop[c]);
             const int q = ((col >> 3) << 2) | (col & 3);
             float dv = 0.0f;
 #pragma unroll
             for (int r = 0; r < 16; r++) dv = (r == q) ? ud[r] : dv;
-            const float other = __shfl_xor(dv, 32, 64);
-            ui = (h == ((col >> 2) & 1)) ? dv : other;
+            const Halves d = halves(dv);
+            ui = ((col >> 2) & 1) ? d.hi : d.lo;
         }
-        float Lt = 0.0f;
+        float cg = 0.0f;
 #pragma unroll
-        for (int r = 0; r < 16; r++) Lt += bank[c][r];
-        const float ot = __shfl_xor(Lt, 32, 64);
-        const float tot = Lt + ot;
-        float smin = INFINITY, cg = 0.0f;
-#pragma unroll
-        for (int k = 0; k < MDGMI_MAX_BITS; k++) {
-            if (k < m) {
-                float S0k, S1k;
-                if (k == 2) {  // the lane half
-                    S0k = h ? ot : Lt;
-                    S1k = h ? Lt : ot;
-                } else if (k < 5) {  // label bits 0, 1, 3, 4 are bits 0..3 of the register index
-                    const int q = k < 2 ? k : k - 1;
-                    float a0 = 0.0f, a1 = 0.0f;
-#pragma unroll
-                    for (int r = 0; r < 16; r++) {
-                        if ((r >> q) & 1)
-                            a1 += bank[c][r];
-                        else
-                            a0 += bank[c][r];
-                    }
-                    S0k = a0 + __shfl_xor(a0, 32, 64);
-                    S1k = a1 + __shfl_xor(a1, 32, 64);
-                } else {  // tile-index bits
-                    S0k = hi[c].R0[k - 5] + __shfl_xor(hi[c].R0[k - 5], 32, 64);
-                    S1k = hi[c].R1[k - 5] + __shfl_xor(hi[c].R1[k - 5], 32, 64);
-                }
-                smin = fminf(smin, fminf(S0k, S1k));
-                const float l0 = lg2(S0k), l1 = lg2(S1k);
-                if (LLR) {
-                    if (mine) llr[i * m + k] = log2_ratio(S1k, S0k, l1, l0) * (float)kLn2;
+        for (int j = 0; j < (MDGMI_MAX_BITS + 1) / 2; j++) {
+            if (2 * j < m) {  // uniform
+                const int ke = 2 * j, ko = ke + 1 < MDGMI_MAX_BITS ? ke + 1 : ke;
+                float S0e, S1e, S0o = 1.0f, S1o = 1.0f;
+                if (ke == 2) {
+                    S0e = S0t;
+                    S1e = S1t;
                 } else {
-                    const bool b = (slot >> k) & 1;
-                    cg += bit_cost2(b ? log2_ratio(S0k, S1k, l0, l1) : log2_ratio(S1k, S0k, l1, l0));
+                    sums(ke, S0e, S1e);
+                }
+                if (ko < m) sums(ko, S0o, S1o);
+                const int k = ke + h;
+                const float s0 = h ? S0o : S0e, s1 = h ? S1o : S1e;
+                if (k < m) {
+                    const float lz = lg2(s0), lo = lg2(s1);
+                    if (LLR) {
+                        if (!slow && i < n) llr[i * m + k] = log2_ratio(s1, s0, lo, lz) * (float)kLn2;
+                    } else {
+                        const bool bk = (slot >> k) & 1;
+                        cg += bit_cost2(bk ? log2_ratio(s0, s1, lz, lo) : log2_ratio(s1, s0, lo, lz));
+                    }
                 }
             }
         }
-        if (!mine) continue;
         if (LLR) {
-            if (!(smin >= ex2(kFarLog2))) {
+            if (slow && h == 0 && i < n) {
                 // a class lies too far for the common offset: exact per-class path
                 float yc[DIM], ls0[MDGMI_MAX_BITS], ls1[MDGMI_MAX_BITS], ltot, ti;
 #pragma unroll
@@ -378,6 +445,8 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
                     if (k < m) llr[i * m + k] = (ls1[k] - ls0[k]) * (float)kLn2;
             }
         } else {
+            cg = half_sum(cg);
+            if (h != 0 || i >= n) continue;
             float cm;
             if (ui >= kFarLog2) {
                 cm = mi_cost2(tot, ui);
@@ -391,8 +460,8 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
 #pragma unroll
                 for (int k = 0; k < MDGMI_MAX_BITS; k++) {
                     if (k < m) {
-                        const bool b = (slot >> k) & 1;
-                        cg += bit_cost2(b ? ls0[k] - ls1[k] : ls1[k] - ls0[k]);
+                        const bool bk = (slot >> k) & 1;
+                        cg += bit_cost2(bk ? ls0[k] - ls1[k] : ls1[k] - ls0[k]);
                     }
                 }
                 cm = ltot + ti;

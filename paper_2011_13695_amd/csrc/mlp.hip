@@ -53,9 +53,13 @@ namespace {
 
 using namespace mlp;
 
-constexpr int64_t kKSplit = 4096;  // samples per split-K slice of the weight gradients
+constexpr int64_t kKSplit = 1024;  // samples per split-K slice of the weight gradients
+constexpr int64_t kColChunk = 128; // samples per partial column sum of the bias gradients
 
 int64_t al(int64_t v) { return (v + 255) / 256 * 256; }
+
+// chunk length of the bias-gradient column sums (at most 65535 chunks: grid.y)
+int64_t colsum_chunk(int64_t n) { return std::max<int64_t>(kColChunk, (n + 65534) / 65535); }
 
 // ---- elementwise kernels ----
 __global__ void k_to_bf16(const float* __restrict__ x, int64_t cnt, __bf16* __restrict__ out) {
@@ -112,12 +116,25 @@ __global__ void k_reduce_splits(const float* __restrict__ partial, int splits, i
     grad[i] = s;
 }
 
-// db[o] = sum_s D[s][o], one thread per output, fixed order
-__global__ void k_colsum(const __bf16* __restrict__ D, int64_t n, int out, float* __restrict__ db) {
+// db[o] = sum_s D[s][o] in a fixed order: chunk c of colsum_chunk(n) samples is
+// summed by thread (c, o) into part[c][o], then the chunk sums are added in
+// chunk order.
+__global__ void k_colsum_part(const __bf16* __restrict__ D, int64_t n, int out, int64_t chunk,
+                              float* __restrict__ part) {
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= out) return;
+    const int64_t r0 = (int64_t)blockIdx.y * chunk;
+    const int64_t r1 = r0 + chunk < n ? r0 + chunk : n;
+    float s = 0.0f;
+    for (int64_t i = r0; i < r1; i++) s += (float)D[i * out + o];
+    part[(int64_t)blockIdx.y * out + o] = s;
+}
+
+__global__ void k_colsum_final(const float* __restrict__ part, int64_t nchunks, int out, float* __restrict__ db) {
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= out) return;
     float s = 0.0f;
-    for (int64_t i = 0; i < n; i++) s += (float)D[i * out + o];
+    for (int64_t c = 0; c < nchunks; c++) s += part[c * out + o];
     db[o] = s;
 }
 
@@ -167,7 +184,7 @@ GemmArgs gargs() {
 
 // Workspace layout for n samples.
 struct MlpWs {
-    int64_t x0, z[MDGMI_MLP_MAX_LAYERS], h[MDGMI_MLP_MAX_LAYERS], logits, d0, d1, part, lpart, total;
+    int64_t x0, z[MDGMI_MLP_MAX_LAYERS], h[MDGMI_MLP_MAX_LAYERS], logits, d0, d1, part, cpart, lpart, total;
 };
 
 MlpWs mlp_ws(const mdgmi_mlp* net, int64_t n) {
@@ -189,6 +206,8 @@ MlpWs mlp_ws(const mdgmi_mlp* net, int64_t n) {
     const int64_t splits = (n + kKSplit - 1) / kKSplit;
     w.part = o;
     o += al(splits * (int64_t)net->width * net->width * 4);
+    w.cpart = o;
+    o += al((n + colsum_chunk(n) - 1) / colsum_chunk(n) * (int64_t)net->width * 4);
     w.lpart = o;
     o += al(1024 * 8);
     w.total = o;
@@ -415,7 +434,11 @@ int mdgmi_mlp_loss_grad(mdgmi_mlp* net, const float* x, const float* target_llr,
         const int64_t cnt = (int64_t)out * in;
         hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
                            (const float*)(base + w.part), splits, cnt, net->d_grad + net->woff[l]);
-        hipLaunchKernelGGL(k_colsum, dim3((out + 63) / 64), dim3(64), 0, st, D, n, out, net->d_grad + net->boff[l]);
+        const int64_t cc = colsum_chunk(n), nchunks = (n + cc - 1) / cc;
+        hipLaunchKernelGGL(k_colsum_part, dim3((out + 63) / 64, (unsigned)nchunks), dim3(64), 0, st, D, n, out, cc,
+                           (float*)(base + w.cpart));
+        hipLaunchKernelGGL(k_colsum_final, dim3((out + 63) / 64), dim3(64), 0, st, (const float*)(base + w.cpart),
+                           nchunks, out, net->d_grad + net->boff[l]);
         if (l > 0) {
             // D_prev [n][in] = (D [n][out] W_l [out][in]) * gelu'(Z_{l-1})
             GemmArgs h = gargs();

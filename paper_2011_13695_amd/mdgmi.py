@@ -461,15 +461,27 @@ def mdgmi_mlp_features(y, snr_db: float, x=None, stream=None):
     return x
 
 
-def mdgmi_mlp_gmi(net: "MLP", fmt: Format, y, tx_idx, snr_db, chunk: int = 1 << 20, out=None, ws=None, stream=None):
-    """Learned GMI per SNR point: y [n_snr, n, dim], tx [n_snr, n] -> out [n_snr, 6] (MI fields NaN)."""
-    import torch
+def _mlp_gmi_sigs():
     L = _mlp_sigs()
     if not getattr(L, "_mlp_gmi_sigs", False):
         L.mdgmi_mlp_gmi_workspace_size.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
         L.mdgmi_mlp_gmi.argtypes = [_P, _P, _P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int64, _P, _P,
                                     ctypes.c_size_t, _P]
         L._mlp_gmi_sigs = True
+    return L
+
+
+def mdgmi_mlp_gmi_workspace_size(net: "MLP", chunk: int) -> int:
+    b = ctypes.c_size_t()
+    _check("mdgmi_mlp_gmi_workspace_size",
+           _mlp_gmi_sigs().mdgmi_mlp_gmi_workspace_size(net.handle, int(chunk), ctypes.byref(b)))
+    return b.value
+
+
+def mdgmi_mlp_gmi(net: "MLP", fmt: Format, y, tx_idx, snr_db, chunk: int = 1 << 20, out=None, ws=None, stream=None):
+    """Learned GMI per SNR point: y [n_snr, n, dim], tx [n_snr, n] -> out [n_snr, 6] (MI fields NaN)."""
+    import torch
+    L = _mlp_gmi_sigs()
     snr = np.ascontiguousarray(np.atleast_1d(snr_db), dtype=np.float64)
     n_snr = snr.size
     n = y.numel() // (fmt.dim * n_snr)
@@ -477,9 +489,7 @@ def mdgmi_mlp_gmi(net: "MLP", fmt: Format, y, tx_idx, snr_db, chunk: int = 1 << 
     if out is None:
         out = torch.empty((n_snr, MDGMI_NFIELDS), dtype=torch.float64, device="cuda")
     if ws is None:
-        b = ctypes.c_size_t()
-        _check("mdgmi_mlp_gmi_workspace_size", L.mdgmi_mlp_gmi_workspace_size(net.handle, chunk, ctypes.byref(b)))
-        ws = workspace(b.value)
+        ws = workspace(mdgmi_mlp_gmi_workspace_size(net, chunk))
     _check("mdgmi_mlp_gmi", L.mdgmi_mlp_gmi(net.handle, fmt.handle, _dptr(y), _dptr(tx_idx), n, snr.ctypes.data_as(_P),
                                             n_snr, chunk, _dptr(out), _dptr(ws), ws.numel(), _stream(stream)))
     return out
