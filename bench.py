@@ -39,7 +39,8 @@ HBM_PEAK = 8.0e12
 # the same counter reads for a plain copy kernel of known size (a 1 GiB copy
 # reads FETCH_SIZE = 0.5 GiB and WRITE_SIZE = 1 GiB: factors 2.0 and 1.0).
 # Reported only while the kernel sources hash to the value they were taken on.
-TRAFFIC = {"sources_sha1": None, "fetch_kib": None, "write_kib": None, "fetch_scale": 2.0, "write_scale": 1.0}
+TRAFFIC = {"sources_sha1": "e922a4687a0df1189cef8e45fe43b34e0d45bb27", "fetch_kib": 2827827.0, "write_kib": 2064.0,
+           "fetch_scale": 2.0, "write_scale": 1.0}
 KERNEL_SOURCES = ("mfma_core.h", "device_common.h", "internal.h", "exact_mfma.hip")
 
 
@@ -72,6 +73,8 @@ def parse():
     ap.add_argument("--learned-samples", type=float, default=2e8,
                     help="training samples of the learned demapper (0 skips the learned leg)")
     ap.add_argument("--learned-eval", type=float, default=1e8, help="held-out samples over the 16 SNR points")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch leg")
+    ap.add_argument("--ragged-scale", type=float, default=1.0, help="scale of the ragged sample counts")
     ap.add_argument("--copy-probe", type=float, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -88,10 +91,11 @@ def cpu_baseline(wl, target_s: float):
     f = wl.fmt
     threads = oracle.num_threads()
     # calibrate on a few samples, then size the sample to about target_s
-    y, tx = w.channel_samples(f, float(wl.sigma2[0]), wl.seed, 0, n=64)
+    oracle.gmi(*w.channel_samples(f, float(wl.sigma2[0]), wl.seed, 0, n=64), f.X, f.labels, float(wl.sigma2[0]))
+    y, tx = w.channel_samples(f, float(wl.sigma2[0]), wl.seed, 0, n=4096)
     t0 = time.perf_counter()
     oracle.gmi(y, tx, f.X, f.labels, float(wl.sigma2[0]))
-    per_sample = max((time.perf_counter() - t0) / 64, 1e-7)
+    per_sample = max((time.perf_counter() - t0) / 4096, 1e-8)
     n_cpu = int(max(64, min(200_000, target_s / per_sample / len(wl.snr_db))))
     elapsed = 0.0
     for q, s2 in enumerate(wl.sigma2):
@@ -178,6 +182,77 @@ def learned_leg(gf, wl, args, log):
     }
 
 
+def ragged_leg(args, log, scale=None):
+    """Ragged batch: 48 formats (dims 2/4/8, M = 4..4096) x 31 SNR points with
+    log-uniform sample counts in [1e4, 1e7], paths and tiles from the
+    autotuner, in one persistent hipGraph launch against one mdgmi_gmi call
+    per instance on the same samples."""
+    import numpy as np
+    import torch
+
+    import workloads as w
+    from paper_2011_13695_amd import mdgmi
+    fmts = w.ragged_formats()
+    snr = w.RAGGED_SNR_DB
+    counts = w.ragged_counts(len(fmts), len(snr))
+    scale = args.ragged_scale if scale is None else scale
+    if scale != 1.0:
+        counts = np.maximum(1, np.round(counts * scale)).astype(np.int64)
+    t0 = time.perf_counter()
+    for dim, M in sorted({(f.dim, f.M) for f in fmts}):
+        mdgmi.mdgmi_autotune(dim, M)
+    tune_s = time.perf_counter() - t0
+    gfs = [mdgmi.Format.of(f) for f in fmts]
+    items, pairs = [], 0
+    for a, (f, gf) in enumerate(zip(fmts, gfs)):
+        for q, sdb in enumerate(snr):
+            n = int(counts[a, q])
+            s2 = float(w.sigma2_from_snr_db(float(sdb), f.dim))
+            y, tx = mdgmi.mdgmi_generate(gf, 7 + a, [s2], n, snr_slot0=q, dtype=torch.float32)
+            items.append((gf, y.view(n, f.dim), tx.view(n), s2))
+            pairs += n * f.M
+    torch.cuda.synchronize()
+    log(f"ragged: {len(items)} instances, {int(counts.sum())} samples, {pairs:.3e} sample*points "
+        f"(tuning {tune_s:.1f} s)")
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    plan = mdgmi.Batch(items, path="auto")
+    out_b = torch.empty((len(items), mdgmi.MDGMI_NFIELDS), dtype=torch.float64, device="cuda")
+    t_batch = timed(lambda: plan.run(out=out_b, use_graph=True), 3)
+    log(f"ragged: one graph launch {t_batch:.1f} ms")
+    ws = mdgmi.workspace(max(mdgmi.mdgmi_gmi_workspace_size(gf, y.shape[0], 1, "auto") for gf, y, _, _ in items))
+    out_i = torch.empty_like(out_b)
+
+    def per_instance():
+        for q, (gf, y, tx, s2) in enumerate(items):
+            mdgmi.mdgmi_gmi(gf, y.view(1, -1, gf.dim), tx.view(1, -1), [s2], path="auto", out=out_i[q:q + 1], ws=ws)
+
+    t_inst = timed(per_instance, 2)
+    log(f"ragged: per-instance launches {t_inst:.1f} ms")
+    ob, oi = out_b.cpu().numpy(), out_i.cpu().numpy()
+    info = plan.info()
+    plan.close()
+    return {"instances": len(items), "formats": len(fmts), "snr_points": int(len(snr)),
+            "samples": int(counts.sum()), "sample_points": int(pairs), "work_items": info["items"],
+            "value_batched": pairs / (t_batch * 1e-3), "ms_batched": t_batch,
+            "value_per_instance": pairs / (t_inst * 1e-3), "ms_per_instance": t_inst,
+            "speedup_batched_vs_per_instance": t_inst / t_batch, "tune_seconds": tune_s,
+            "max_abs_dgmi_batched_vs_per_instance": float(np.nanmax(np.abs(ob[:, 0] - oi[:, 0]))),
+            "max_abs_dmi_batched_vs_per_instance": float(np.nanmax(np.abs(ob[:, 1] - oi[:, 1]))),
+            "count_scale": scale, "unit": "sample*points/s"}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -260,10 +335,16 @@ def main():
         "mi": [float(v) for v in out[:, 1]],
     }
     line.update(extra)
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
     if args.learned_samples > 0:
-        def log(msg):
-            print(f"[bench] learned: {msg}", file=sys.stderr, flush=True)
-        line["learned"] = learned_leg(gf, wl, args, log)
+        line["learned"] = learned_leg(gf, wl, args, lambda m: log("learned: " + m))
+    if not args.no_ragged:
+        del y, tx
+        torch.cuda.empty_cache()
+        line["ragged_batch"] = ragged_leg(args, log)
+        # the same set with 1/100 of the samples: launch-bound per instance
+        line["ragged_batch_small"] = ragged_leg(args, log, scale=args.ragged_scale * 0.01)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line))

@@ -49,6 +49,7 @@ struct BatchPlan {
     std::vector<int32_t> item_range;   // (first, end) item per instance
     int64_t total_slots = 0;
     int max_lds_u4 = 0;
+    int n_mfma_items = 0;             // items [0, n_mfma_items) are MFMA items
     size_t off_insts = 0, off_imgs = 0, off_items = 0, off_range = 0, off_part = 0, off_counter = 0,
            off_images = 0, bytes = 0;
     char* base = nullptr;

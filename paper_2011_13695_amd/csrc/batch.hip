@@ -3,10 +3,11 @@
 //
 // The host cuts every instance into items (contiguous sample ranges of about
 // kItemPairs sample*points each, aligned to the kernel's sample tiles) and
-// lists them instance by instance, largest constellations first. A
-// persistent grid pulls items from one atomic counter; for each item a block
-// dispatches on the instance's (path, dim, M) to the very device functions
-// the per-SNR kernels run (mfma_core.h / direct_core.h), staging the
+// lists them instance by instance: MFMA instances, then direct ones, largest
+// constellations first within each. One persistent grid per kind pulls items
+// from its own atomic counter; for each item a block
+// dispatches on the instance's (dim, M) to the very device functions the
+// per-SNR kernels run (mfma_core.h / direct_core.h), staging the
 // instance's MFMA A image in LDS when it fits and keeping it there while the
 // block stays on that instance. Every item writes its own FP64 partials, and
 // one block per instance adds its items' partials in item order, so the
@@ -25,17 +26,19 @@ namespace mdgmi {
 
 namespace {
 
-constexpr int kBatchWaves = 8;
-constexpr int kBatchThreads = kBatchWaves * 64;
+// MFMA items run in blocks of 16 waves (one block per CU holds a 128 KiB
+// image in LDS; 4 waves per SIMD), direct items in blocks of 8 waves.
+constexpr int kMfmaWaves = 16;
+constexpr int kDirectWaves = 8;
 constexpr int kLdsCapU4 = 128 * 1024 / 16;  // A images up to 128 KiB are staged in LDS
 
-template <int DIM, bool IN_LDS>
+template <int DIM, int G, bool IN_LDS>
 __device__ __forceinline__ void run_mfma_item(const BatchInst& D, const uint4* __restrict__ A, int64_t s0,
                                               int64_t s1, CostAcc& acc) {
     const int wave = threadIdx.x >> 6;
     const int64_t ct0 = s0 >> 5, ct1 = (s1 + 31) >> 5;
-    for (int64_t ct = ct0 + wave; ct < ct1; ct += kBatchWaves)
-        mfma::mfma_coltile<DIM, 1, 4, false>(A, D.y, D.tx, D.n, ct, D.M, D.m, D.ntiles, D.s, D.X32, D.labels,
+    for (int64_t ct = ct0 + wave; ct < ct1; ct += kMfmaWaves)
+        mfma::mfma_coltile<DIM, 1, G, false>(A, D.y, D.tx, D.n, ct, D.M, D.m, D.ntiles, D.s, D.X32, D.labels,
                                              nullptr, acc);
 }
 
@@ -58,32 +61,46 @@ __device__ __forceinline__ void run_direct_dim(const BatchInst& D, int64_t s0, i
     }
 }
 
+// MFMA batch items need M >= 128, i.e. at least 4 tiles: groups of 8 tiles
+// from 8 tiles up, else 4.
 template <int DIM>
 __device__ __forceinline__ void run_mfma_dim(const BatchInst& D, bool in_lds, const uint4* lds, int64_t s0,
                                              int64_t s1, CostAcc& acc) {
-    if (in_lds)
-        run_mfma_item<DIM, true>(D, lds, s0, s1, acc);
-    else
-        run_mfma_item<DIM, false>(D, (const uint4*)D.img, s0, s1, acc);
+    const uint4* g = (const uint4*)D.img;
+    if (D.ntiles >= 8) {
+        if (in_lds)
+            run_mfma_item<DIM, 8, true>(D, lds, s0, s1, acc);
+        else
+            run_mfma_item<DIM, 8, false>(D, g, s0, s1, acc);
+    } else {
+        if (in_lds)
+            run_mfma_item<DIM, 4, true>(D, lds, s0, s1, acc);
+        else
+            run_mfma_item<DIM, 4, false>(D, g, s0, s1, acc);
+    }
 }
 
-__global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchInst* __restrict__ insts,
-                                                         const BatchItem* __restrict__ items, int n_items,
-                                                         unsigned* __restrict__ counter, double* __restrict__ part) {
+// Persistent grid over items [i0, i1) of one kind, pulled through *counter
+// (zeroed before the launch). Every wave leaves the loop on the same item
+// index, read once per round from LDS.
+template <int KIND>
+__global__ __launch_bounds__((KIND == kKindMfma ? kMfmaWaves : kDirectWaves) * 64) void k_batch(
+    const BatchInst* __restrict__ insts, const BatchItem* __restrict__ items, int i0, int i1,
+    unsigned* __restrict__ counter, double* __restrict__ part) {
     extern __shared__ uint4 lds[];
     __shared__ int s_item, s_staged;
     if (threadIdx.x == 0) s_staged = -1;
     for (;;) {
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        if (threadIdx.x == 0) s_item = i0 + (int)atomicAdd(counter, 1u);
         __syncthreads();
         const int it = __builtin_amdgcn_readfirstlane(s_item);
         const int staged = s_staged;
         __syncthreads();
-        if (it >= n_items) break;
+        if (it >= i1) break;
         const BatchItem I = items[it];
         const BatchInst D = insts[I.inst];
         CostAcc acc;
-        if (D.kind == kKindMfma) {
+        if (KIND == kKindMfma) {
             const bool in_lds = D.img_u4 <= kLdsCapU4;
             if (in_lds && staged != I.inst) {
                 const uint4* g = (const uint4*)D.img;
@@ -139,8 +156,8 @@ __global__ void k_batch_images(const BatchImg* __restrict__ imgs, int n_inst, in
     }
 }
 
-__global__ void k_zero_counter(unsigned* c) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0u;
+__global__ void k_zero_counters(unsigned* c) {
+    if (blockIdx.x == 0 && threadIdx.x < 2) c[threadIdx.x] = 0u;
 }
 
 int direct_variant(int m) { return m <= 1 ? 0 : m == 2 ? 1 : m == 3 ? 2 : m == 4 ? 3 : m == 5 ? 4 : 5; }
@@ -195,11 +212,15 @@ int plan_batch(const mdgmi_instance* inst, int n_inst, int path, int64_t item_pa
         img_bytes += al(bytes);
     }
     P.total_slots = slots;
-    // instances in decreasing M (then input order) so the cheap ones form the tail
+    // MFMA instances first, then direct ones (each kind has its own kernel);
+    // within a kind, decreasing M (then input order) so the cheap ones form
+    // the tail
     std::vector<int> order(n_inst);
     for (int q = 0; q < n_inst; q++) order[q] = q;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return inst[a].fmt->M > inst[b].fmt->M; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (kind[a] != kind[b]) return kind[a] == kKindMfma;
+        return inst[a].fmt->M > inst[b].fmt->M;
+    });
     P.insts.resize(n_inst);
     // items are grouped per instance in the order above; (first, end) per
     // caller instance lets the reduction find them
@@ -208,7 +229,7 @@ int plan_batch(const mdgmi_instance* inst, int n_inst, int path, int64_t item_pa
         const int q = order[oi];
         const mdgmi_format* f = inst[q].fmt;
         const int64_t n = inst[q].n;
-        const int align = kind[q] == kKindMfma ? 32 * kBatchWaves : kBatchThreads;
+        const int align = kind[q] == kKindMfma ? 32 * kMfmaWaves : 64 * kDirectWaves;
         int64_t per = item_pairs / f->M;
         per = std::max<int64_t>(align, per / align * align);
         first_of[q] = (int32_t)P.items.size();
@@ -222,6 +243,9 @@ int plan_batch(const mdgmi_instance* inst, int n_inst, int path, int64_t item_pa
         }
         count_of[q] = (int32_t)P.items.size() - first_of[q];
     }
+    P.n_mfma_items = 0;
+    for (const BatchItem& it : P.items)
+        if (kind[it.inst] == kKindMfma) P.n_mfma_items++;
     P.item_range.resize(2 * (size_t)n_inst);
     for (int q = 0; q < n_inst; q++) {
         P.item_range[2 * q] = first_of[q];
@@ -262,7 +286,7 @@ int plan_batch(const mdgmi_instance* inst, int n_inst, int path, int64_t item_pa
     P.off_part = o;
     o += al(sizeof(double) * kNPart * P.items.size());
     P.off_counter = o;
-    o += al(sizeof(unsigned));
+    o += al(2 * sizeof(unsigned));
     P.off_images = o;
     o += img_bytes;
     P.bytes = o;
@@ -335,20 +359,34 @@ hipError_t prepare_batch_kernel() {
     static std::once_flag once;
     static hipError_t err = hipSuccess;
     std::call_once(once, [] {
-        err = hipFuncSetAttribute((const void*)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsCapU4 * 16);
+        err = hipFuncSetAttribute((const void*)k_batch<kKindMfma>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  kLdsCapU4 * 16);
     });
     return err;
 }
 
 hipError_t launch_batch(const BatchPlan& P, double* out, hipStream_t st) {
     unsigned* counter = (unsigned*)(P.base + P.off_counter);
-    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, st, counter);
-    const size_t lds = (size_t)P.max_lds_u4 * 16;
-    const int per_cu = lds > 80 * 1024 ? 1 : (lds > 40 * 1024 ? 2 : 4);
-    const int grid = std::max(1, std::min<int>((int)P.items.size(), device_cu_count() * per_cu));
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(kBatchThreads), lds, st,
-                       (const BatchInst*)(P.base + P.off_insts), (const BatchItem*)(P.base + P.off_items),
-                       (int)P.items.size(), counter, (double*)(P.base + P.off_part));
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, counter);
+    const BatchInst* insts = (const BatchInst*)(P.base + P.off_insts);
+    const BatchItem* items = (const BatchItem*)(P.base + P.off_items);
+    double* part = (double*)(P.base + P.off_part);
+    const int n_items = (int)P.items.size(), n_mfma = P.n_mfma_items;
+    if (n_mfma > 0) {
+        // one resident round: blocks per CU limited by the largest LDS image
+        // and by 16 waves per CU
+        const size_t lds = (size_t)P.max_lds_u4 * 16;
+        const int by_lds = lds > 0 ? std::max(1, (int)((160 * 1024) / (lds + 2048))) : 1;
+        const int per_cu = std::min(by_lds, 1);
+        const int grid = std::max(1, std::min(n_mfma, device_cu_count() * per_cu));
+        hipLaunchKernelGGL(k_batch<kKindMfma>, dim3(grid), dim3(kMfmaWaves * 64), lds, st, insts, items, 0, n_mfma,
+                           counter, part);
+    }
+    if (n_items > n_mfma) {
+        const int grid = std::max(1, std::min(n_items - n_mfma, device_cu_count() * 2));
+        hipLaunchKernelGGL(k_batch<kKindDirect>, dim3(grid), dim3(kDirectWaves * 64), 0, st, insts, items, n_mfma,
+                           n_items, counter + 1, part);
+    }
     hipLaunchKernelGGL(k_batch_reduce_ranges, dim3(P.n_inst), dim3(256), 0, st, (const double*)(P.base + P.off_part),
                        (const int32_t*)(P.base + P.off_range), (const BatchInst*)(P.base + P.off_insts), out);
     return hipGetLastError();
