@@ -1,0 +1,118 @@
+"""Parity at the full size of the 8-D workload (M = 2048 two-shell format,
+16 SNR points x 1e7 samples, generated on the device), in the launch
+configuration the benchmark times.
+
+The oracle cannot evaluate 3.3e11 pairs, so the full-size results are tied
+to it through outputs it can compute one by one and through properties that
+hold at any size:
+* LLR mode over all 1e7 samples of every SNR point; 384 seeded random rows
+  per point against the FP64 oracle on the very same (device) inputs, bar
+  |d lambda| <= 1e-3 * max(|lambda|, 1) nats;
+* the GMI-mode result of the timed launch equals m - mean of the bit costs
+  formed from those full LLR arrays (same samples), within 1e-4 bit;
+* additivity of the reduction: the full-size sums equal the sample-weighted
+  sums of two halves run separately (1e-9 relative);
+* the full-size MI agrees with the oracle's MI of the sampled rows within
+  Monte-Carlo error, and MI >= GMI within 3 standard errors.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2011_13695_amd import mdgmi  # noqa: E402
+
+LLR_RTOL = 1e-3
+GMI_TOL32 = 1e-4
+ROWS = 384
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def full():
+    wl = w.workload_8d2048()
+    f = wl.fmt
+    gf = mdgmi.Format.of(f)
+    say(f"[full] generating {len(wl.snr_db)} x {wl.n} samples of {f.name}")
+    y, tx = mdgmi.mdgmi_generate(gf, wl.seed, wl.sigma2, wl.n, dtype=torch.float32)
+    out = mdgmi.mdgmi_gmi(gf, y, tx, wl.sigma2, path="mfma").cpu().numpy()
+    torch.cuda.synchronize()
+    return wl, f, gf, y, tx, out
+
+
+def test_counts_and_finiteness(full):
+    wl, f, gf, y, tx, out = full
+    assert np.all(out[:, 4] == wl.n) and np.all(out[:, 5] == 0)
+    assert np.all(np.isfinite(out[:, :4]))
+
+
+def test_sampled_llrs_and_gmi_formula_at_full_size(full, orc):
+    wl, f, gf, y, tx, out = full
+    rng = np.random.default_rng(2048)
+    ws = mdgmi.workspace(mdgmi.mdgmi_llr_workspace_size(gf, wl.n, "mfma"))
+    lab = torch.from_numpy(f.labels.astype(np.int64)).cuda()
+    bits = torch.arange(f.m, device="cuda", dtype=torch.int64)
+    worst = 0.0
+    for q, s2 in enumerate(wl.sigma2):
+        say(f"[full] SNR {wl.snr_db[q]} dB: LLRs of {wl.n} samples")
+        lam = mdgmi.mdgmi_llr(gf, y[q], float(s2), path="mfma", ws=ws)
+        rows = np.sort(rng.choice(wl.n, size=ROWS, replace=False))
+        ri = torch.from_numpy(rows).cuda()
+        yr = y[q].index_select(0, ri).cpu().numpy().astype(np.float64)
+        ref = orc.llr(yr, f.X, f.labels, float(s2))
+        got = lam.index_select(0, ri).cpu().numpy().astype(np.float64)
+        ratio = float(np.max(np.abs(got - ref) / (LLR_RTOL * np.maximum(np.abs(ref), 1.0))))
+        worst = max(worst, ratio)
+        assert ratio <= 1.0, (q, ratio)
+        # GMI of the timed launch vs the bit costs of the full LLR arrays
+        b = ((lab[tx[q].long()].unsqueeze(1) >> bits) & 1).double()
+        u = -(2.0 * b - 1.0) * lam.double()
+        cg = (torch.clamp(u, min=0.0) + torch.log1p(torch.exp(-u.abs()))).sum(dim=1) / math.log(2.0)
+        gmi = f.m - float(cg.mean())
+        assert abs(gmi - out[q, 0]) <= GMI_TOL32, (q, gmi, out[q, 0])
+        del lam, b, u, cg
+    say(f"[full] worst sampled LLR error / bar = {worst:.3f}")
+
+
+def test_reduction_is_additive_over_halves(full):
+    wl, f, gf, y, tx, out = full
+    h = wl.n // 2
+    parts = []
+    for sl in (slice(0, h), slice(h, wl.n)):
+        ys = y[:, sl].contiguous()
+        ts = tx[:, sl].contiguous()
+        parts.append(mdgmi.mdgmi_gmi(gf, ys, ts, wl.sigma2, path="mfma").cpu().numpy())
+        del ys, ts
+    n1, n2 = h, wl.n - h
+    for col in (0, 1):
+        comb = (n1 * parts[0][:, col] + n2 * parts[1][:, col]) / wl.n
+        np.testing.assert_allclose(comb, out[:, col], rtol=1e-9, atol=1e-9)
+
+
+def test_mi_against_sampled_oracle(full, orc):
+    wl, f, gf, y, tx, out = full
+    rng = np.random.default_rng(4096)
+    for q in (0, 7, 15):
+        s2 = float(wl.sigma2[q])
+        rows = np.sort(rng.choice(wl.n, size=2000, replace=False))
+        ri = torch.from_numpy(rows).cuda()
+        yr = y[q].index_select(0, ri).cpu().numpy().astype(np.float64)
+        tr = tx[q].index_select(0, ri).cpu().numpy().view(np.uint32)
+        r = orc.gmi(yr, tr, f.X, f.labels, s2)
+        say(f"[full] q={q}: MI full {out[q, 1]:.5f} vs sample {r[1]:.5f} +- {r[3]:.5f}")
+        assert abs(out[q, 1] - r[1]) <= 5.0 * r[3] + 1e-6
+        assert abs(out[q, 0] - r[0]) <= 5.0 * r[2] + 1e-6
+        assert out[q, 1] >= out[q, 0] - 3.0 * math.hypot(out[q, 2], out[q, 3])
