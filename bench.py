@@ -74,6 +74,7 @@ def parse():
                     help="training samples of the learned demapper (0 skips the learned leg)")
     ap.add_argument("--learned-eval", type=float, default=1e8, help="held-out samples over the 16 SNR points")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch leg")
+    ap.add_argument("--no-llr", action="store_true", help="skip timing the LLR-output mode")
     ap.add_argument("--ragged-scale", type=float, default=1.0, help="scale of the ragged sample counts")
     ap.add_argument("--copy-probe", type=float, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration) and exit")
@@ -308,7 +309,27 @@ def main():
         dwall, dms, dout = run_path("direct", max(2, args.steps // 3), 1)
         extra["direct_fp32"] = {"value": pairs / (dwall / max(2, args.steps // 3)),
                                 "ms_per_step": dwall / max(2, args.steps // 3) * 1e3,
-                                "max_abs_dgmi_vs_timed_path": float(np.abs(dout[:, :2] - out[:, :2]).max())}
+                                "max_abs_dgmi_vs_timed_path": float(np.abs(dout[:, :2] - out[:, :2]).max()),
+                                "speedup_timed_path_vs_direct": dwall / max(2, args.steps // 3) / (wall / args.steps)}
+    if not args.no_llr:
+        # LLR output of every sample (11 FP32 per sample written to HBM)
+        lam = torch.empty((wl.n, f.m), dtype=torch.float32, device="cuda")
+        lws = mdgmi.workspace(mdgmi.mdgmi_llr_workspace_size(gf, wl.n, args.path))
+        stream = torch.cuda.current_stream()
+        for q in range(min(2, n_snr)):
+            mdgmi.mdgmi_llr(gf, y[q], float(s2[q]), path=args.path, llr=lam, ws=lws)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for q in range(n_snr):
+            mdgmi.mdgmi_llr(gf, y[q], float(s2[q]), path=args.path, llr=lam, ws=lws)
+        b.record(stream)
+        torch.cuda.synchronize()
+        lms = a.elapsed_time(b)
+        extra["llr_mode"] = {"value": pairs / (lms * 1e-3), "ms_all_snr": lms,
+                             "bytes_written": n_snr * wl.n * f.m * 4,
+                             "note": "mdgmi_llr over every SNR point, one call each, LLRs of all samples written"}
+        del lam, lws
     achieved = pairs / (kernel_ms * 1e-3)
     line = {
         "metric": METRIC,

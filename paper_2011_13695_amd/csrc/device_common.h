@@ -29,6 +29,38 @@ __device__ __forceinline__ float log2_ratio(float Sa, float Sb, float lsa, float
     return d;
 }
 
+// log2(Sa / Sb) from the ratio alone while it stays within 2^+-60 (the
+// usual case: one reciprocal and one logarithm), else as a difference of
+// logarithms. Sb = 0 gives +inf, Sa = 0 gives -inf, NaN propagates.
+// The rare branch is entered only when one of the wave's active lanes needs
+// it (a wave vote), so the common case issues one reciprocal and one
+// logarithm.
+__device__ __forceinline__ float log2_ratio_fast(float Sa, float Sb) {
+    const float r = Sa * __builtin_amdgcn_rcpf(Sb);
+    const bool ok = r > 0x1p-60f && r < 0x1p60f;
+    float v = lg2(r);
+    if (__ballot(!ok) != 0ull) {
+        asm volatile("" ::: "memory");  // keeps the rare path a real branch
+        if (!ok) v = lg2(Sa) - lg2(Sb);
+    }
+    return v;
+}
+
+// Base-2 GMI cost of one bit from the class sums: log2(1 + S_other / S_sent)
+// = log2(tot / S_sent) with tot = S_sent + S_other >= S_sent; the ratio form
+// keeps full FP32 accuracy near zero cost, the difference of logarithms
+// takes over for costs beyond 60 bits (and propagates NaN).
+__device__ __forceinline__ float bit_cost_sum2(float tot, float Ssent) {
+    const float r = tot * __builtin_amdgcn_rcpf(Ssent);
+    const bool ok = r < 0x1p60f;
+    float v = fmaxf(lg2(r), 0.0f);
+    if (__ballot(!ok) != 0ull) {
+        asm volatile("" ::: "memory");  // keeps the rare path a real branch
+        if (!ok) v = lg2(tot) - lg2(Ssent);
+    }
+    return v;
+}
+
 // MI cost log2(sum_j 2^(u_j - u_i)) = log2(tot * 2^-u_i) without the
 // cancellation of log2(tot) - u_i: the integer part of u_i is removed exactly
 // with ldexp first. tot >= 2^u_i always (the sent point is in the sum).

@@ -423,12 +423,12 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
                 const int k = ke + h;
                 const float s0 = h ? S0o : S0e, s1 = h ? S1o : S1e;
                 if (k < m) {
-                    const float lz = lg2(s0), lo = lg2(s1);
                     if (LLR) {
-                        if (!slow && i < n) llr[i * m + k] = log2_ratio(s1, s0, lo, lz) * (float)kLn2;
+                        if (!slow && i < n) llr[i * m + k] = log2_ratio_fast(s1, s0) * (float)kLn2;
                     } else {
+                        // log2(1 + S_other / S_sent) = log2((S0 + S1) / S_sent)
                         const bool bk = (slot >> k) & 1;
-                        cg += bit_cost2(bk ? log2_ratio(s0, s1, lz, lo) : log2_ratio(s1, s0, lo, lz));
+                        cg += bit_cost_sum2(s0 + s1, bk ? s1 : s0);
                     }
                 }
             }
