@@ -230,51 +230,30 @@ __device__ __forceinline__ f32x16 tile_mfma(const half8* a, const half8* b) {
     return u;
 }
 
-// One column tile: NCOL x 32 samples starting at sample ct * NCOL * 32 of one
-// (format, SNR) instance, against all points of its A image. Costs go to
-// acc (GMI mode) or LLRs to llr (LLR mode). All 64 lanes of the wave must
-// call it together (the MFMA and the half-wave shuffles need every lane).
-template <int DIM, int NCOL, int G, bool LLR>
-__device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const float* __restrict__ ys,
-                                             const uint32_t* __restrict__ txs, int64_t n, int64_t ct, int M,
-                                             int m, int ntiles, float s, const float* __restrict__ X32,
-                                             const uint32_t* __restrict__ labels, float* __restrict__ llr,
-                                             CostAcc& acc) {
+// Exponentials of one or more sample columns against every tile of the A
+// image, folded into a per-register bank (label bits in the register index)
+// and per-group class sums of the tile-index bits (HiAcc).
+//
+// Software pipeline: the MFMA of tile t+1 is in flight while the
+// exponentials of tile t issue, and the operands of tile t+2 are loaded
+// meanwhile. Tile indices wrap (ntiles is a power of two and a multiple of
+// G), so the last steps compute unused tiles instead of branching; the wrap
+// is applied once per group through two base pointers (for G >= 2, tiles
+// t + 2 past the group are the first two of the next group). CLAMP caps each
+// exponent at 110 so that sums of up to 2^12 terms stay finite when the
+// offset has been raised for far classes (only those classes are read then).
+template <int DIM, int NCOL, int G, bool CLAMP, int MAXHI>
+__device__ __forceinline__ void tile_loop(const uint4* __restrict__ A, int ntiles, int h, int col,
+                                          const half8 (&bop)[NCOL][Blk<DIM>::value], float (&bank)[NCOL][16],
+                                          HiAcc<G, MAXHI> (&hi)[NCOL]) {
     constexpr int NB = Blk<DIM>::value;
-    constexpr int MAXHI = MDGMI_MAX_BITS - 5;
-    const int lane = threadIdx.x & 63;
-    const int h = lane >> 5, col = lane & 31;
-    half8 bop[NCOL][NB];
-    float yv[NCOL][DIM];
-    int64_t idx[NCOL];
-#pragma unroll
-    for (int c = 0; c < NCOL; c++) {
-        idx[c] = (ct * NCOL + c) * 32 + col;
-        const bool valid = idx[c] < n;
-        float ys2 = 0.0f;
-#pragma unroll
-        for (int d = 0; d < DIM; d++) {
-            yv[c][d] = valid ? ys[idx[c] * DIM + d] : 0.0f;
-            ys2 = fmaf(yv[c][d], yv[c][d], ys2);
-        }
-        const float K = fmaf(-s, ys2, kBias);
-        make_b<DIM>(yv[c], K, h, bop[c]);
-    }
-    float bank[NCOL][16];
-    HiAcc<G, MAXHI> hi[NCOL];
+    constexpr int TS = NB * 64;  // uint4 per tile of the image
 #pragma unroll
     for (int c = 0; c < NCOL; c++) {
 #pragma unroll
         for (int r = 0; r < 16; r++) bank[c][r] = 0.0f;
         hi[c].zero();
     }
-    // Software pipeline: the MFMA of tile t+1 is in flight while the
-    // exponentials of tile t issue, and the operands of tile t+2 are loaded
-    // meanwhile. Tile indices wrap (ntiles is a power of two and a multiple
-    // of G), so the last steps compute unused tiles instead of branching; the
-    // wrap is applied once per group through two base pointers (for G >= 2,
-    // tiles t + 2 past the group are the first two of the next group).
-    constexpr int TS = NB * 64;  // uint4 per tile of the image
     const int tmask = ntiles - 1;
     const uint4* __restrict__ Al = A + h * 32 + col;
     half8 a_nxt[NB];
@@ -306,7 +285,7 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
                 float ev[16];
 #pragma unroll
                 for (int r = 0; r < 16; r++) {
-                    ev[r] = ex2(u_cur[c][r]);
+                    ev[r] = ex2(CLAMP ? fminf(u_cur[c][r], 110.0f) : u_cur[c][r]);
                     bank[c][r] += ev[r];
                 }
                 if (G > 1) {
@@ -325,6 +304,171 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
 #pragma unroll
         for (int c = 0; c < NCOL; c++) hi[c].add_group(g0 / G, T[c]);
     }
+}
+
+// This lane's partial class sums p0[k], p1[k] (its 16 rows of every tile)
+// from its bank and tile-bit sums. Label bits 0, 1, 3, 4 are bits 0..3 of
+// the register index (folded by a register tree), bit 2 is the lane half
+// (p0[2] = p1[2] = this half's total), bits 5.. come from the tile index.
+// The bank is consumed.
+template <int MAXHI, int G>
+__device__ __forceinline__ void half_partials(float* b, const HiAcc<G, MAXHI>& hi, int m, float* p0, float* p1) {
+    p0[0] = ((b[0] + b[2]) + (b[4] + b[6])) + ((b[8] + b[10]) + (b[12] + b[14]));
+    p1[0] = ((b[1] + b[3]) + (b[5] + b[7])) + ((b[9] + b[11]) + (b[13] + b[15]));
+#pragma unroll
+    for (int j = 0; j < 8; j++) b[j] = b[2 * j] + b[2 * j + 1];
+    p0[1] = (b[0] + b[2]) + (b[4] + b[6]);
+    p1[1] = (b[1] + b[3]) + (b[5] + b[7]);
+#pragma unroll
+    for (int j = 0; j < 4; j++) b[j] = b[2 * j] + b[2 * j + 1];
+    p0[3] = b[0] + b[2];
+    p1[3] = b[1] + b[3];
+    p0[4] = b[0] + b[1];
+    p1[4] = b[2] + b[3];
+    p0[2] = p1[2] = p0[4] + p1[4];
+#pragma unroll
+    for (int k = 5; k < MDGMI_MAX_BITS; k++) {
+        p0[k] = k < m ? hi.R0[k - 5] : 1.0f;
+        p1[k] = k < m ? hi.R1[k - 5] : 1.0f;
+    }
+}
+
+// Full class sums of label bit k from both halves' partials, identical in
+// every lane (all 64 lanes must take part).
+__device__ __forceinline__ void full_sums(const float* p0, const float* p1, int k, float& S0k, float& S1k) {
+    if (k == 2) {
+        const Halves t = halves(p0[2]);
+        S0k = t.lo;
+        S1k = t.hi;
+    } else {
+        S0k = half_sum(p0[k]);
+        S1k = half_sum(p1[k]);
+    }
+}
+
+// LLR mode, a column tile where some sample has a class too far for the
+// common offset (its sum below 2^kFarLog2): classes that were in range keep
+// their first-pass sums; the far ones are summed again with the offset
+// raised by 100 (the same fold, the exponents of the near points capped);
+// classes still out of range, or non-finite inputs, take the exact
+// per-class path. p0/p1 are the first pass's partials of this lane.
+template <int DIM, int G, int MAXHI>
+__device__ __forceinline__ void llr_far_pass(const uint4* __restrict__ A, const float* __restrict__ ys, int64_t n,
+                                          int64_t i, int M, int m, int ntiles, float s,
+                                          const float* __restrict__ X32, float* __restrict__ llr, const float* p0,
+                                          const float* p1) {
+    constexpr int NB = Blk<DIM>::value;
+    const int lane = threadIdx.x & 63;
+    const int h = lane >> 5, col = lane & 31;
+    const float thr = ex2(kFarLog2);
+    // first pass: this half's bits, near classes' log2 sums
+    constexpr int NJ = (MDGMI_MAX_BITS + 1) / 2;
+    float lnear0[NJ], lnear1[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        lnear0[j] = lnear1[j] = 0.0f;
+        if (2 * j < m) {
+            const int ke = 2 * j, ko = ke + 1 < MDGMI_MAX_BITS ? ke + 1 : ke;
+            float S0e, S1e, S0o = 1.0f, S1o = 1.0f;
+            full_sums(p0, p1, ke, S0e, S1e);
+            if (ko < m) full_sums(p0, p1, ko, S0o, S1o);
+            const float s0 = h ? S0o : S0e, s1 = h ? S1o : S1e;
+            lnear0[j] = s0 >= thr ? lg2(s0) : NAN;   // NaN marks a far (or non-finite) class
+            lnear1[j] = s1 >= thr ? lg2(s1) : NAN;
+        }
+    }
+    // second pass with the offset raised by 100
+    half8 bop[1][NB];
+    float yv[DIM];
+    const bool valid = i < n;
+    float ys2 = 0.0f;
+#pragma unroll
+    for (int d = 0; d < DIM; d++) {
+        yv[d] = valid ? ys[i * DIM + d] : 0.0f;
+        ys2 = fmaf(yv[d], yv[d], ys2);
+    }
+    make_b<DIM>(yv, fmaf(-s, ys2, kBias + 100.0f), h, bop[0]);
+    float bank[1][16];
+    HiAcc<G, MAXHI> hi[1];
+    tile_loop<DIM, 1, G, true, MAXHI>(A, ntiles, h, col, bop, bank, hi);
+    float q0[MDGMI_MAX_BITS], q1[MDGMI_MAX_BITS];
+    half_partials<MAXHI, G>(bank[0], hi[0], m, q0, q1);
+    float out[NJ];
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        out[j] = 0.0f;
+        if (2 * j < m) {
+            const int ke = 2 * j, ko = ke + 1 < MDGMI_MAX_BITS ? ke + 1 : ke;
+            float S0e, S1e, S0o = 1.0f, S1o = 1.0f;
+            full_sums(q0, q1, ke, S0e, S1e);
+            if (ko < m) full_sums(q0, q1, ko, S0o, S1o);
+            const int k = ke + h;
+            if (k < m) {
+                const float f0 = h ? S0o : S0e, f1 = h ? S1o : S1e;
+                // log2 of each class sum at the common offset
+                const float l0 = lnear0[j] == lnear0[j] ? lnear0[j] : lg2(f0) - 100.0f;
+                const float l1 = lnear1[j] == lnear1[j] ? lnear1[j] : lg2(f1) - 100.0f;
+                const bool r0 = lnear0[j] == lnear0[j] || f0 >= thr;
+                const bool r1 = lnear1[j] == lnear1[j] || f1 >= thr;
+                bad = bad || !(r0 && r1);
+                out[j] = l1 - l0;
+            }
+        }
+    }
+    const Halves hb = halves(bad ? 1.0f : 0.0f);
+    const bool any_bad = hb.lo + hb.hi > 0.0f;  // for this sample, over both halves
+    if (!valid) return;
+    if (!any_bad) {
+#pragma unroll
+        for (int j = 0; j < NJ; j++) {
+            const int k = 2 * j + h;
+            if (k < m) llr[i * m + k] = out[j] * (float)kLn2;
+        }
+    } else if (h == 0) {
+        float yc[DIM], ls0[MDGMI_MAX_BITS], ls1[MDGMI_MAX_BITS], ltot, ti;
+#pragma unroll
+        for (int d = 0; d < DIM; d++) yc[d] = ys[i * DIM + d];
+        exact_classes_f32<DIM>(yc, X32, M, m, s, -1, ls0, ls1, ltot, ti);
+#pragma unroll
+        for (int k = 0; k < MDGMI_MAX_BITS; k++)
+            if (k < m) llr[i * m + k] = (ls1[k] - ls0[k]) * (float)kLn2;
+    }
+}
+
+// One column tile: NCOL x 32 samples starting at sample ct * NCOL * 32 of one
+// (format, SNR) instance, against all points of its A image. Costs go to
+// acc (GMI mode) or LLRs to llr (LLR mode). All 64 lanes of the wave must
+// call it together (the MFMA and the half-wave swaps need every lane).
+template <int DIM, int NCOL, int G, bool LLR>
+__device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const float* __restrict__ ys,
+                                             const uint32_t* __restrict__ txs, int64_t n, int64_t ct, int M,
+                                             int m, int ntiles, float s, const float* __restrict__ X32,
+                                             const uint32_t* __restrict__ labels, float* __restrict__ llr,
+                                             CostAcc& acc) {
+    constexpr int NB = Blk<DIM>::value;
+    constexpr int MAXHI = MDGMI_MAX_BITS - 5;
+    constexpr int TS = NB * 64;
+    const int lane = threadIdx.x & 63;
+    const int h = lane >> 5, col = lane & 31;
+    half8 bop[NCOL][NB];
+    int64_t idx[NCOL];
+#pragma unroll
+    for (int c = 0; c < NCOL; c++) {
+        idx[c] = (ct * NCOL + c) * 32 + col;
+        const bool valid = idx[c] < n;
+        float yv[DIM], ys2 = 0.0f;
+#pragma unroll
+        for (int d = 0; d < DIM; d++) {
+            yv[d] = valid ? ys[idx[c] * DIM + d] : 0.0f;
+            ys2 = fmaf(yv[d], yv[d], ys2);
+        }
+        const float K = fmaf(-s, ys2, kBias);
+        make_b<DIM>(yv, K, h, bop[c]);
+    }
+    float bank[NCOL][16];
+    HiAcc<G, MAXHI> hi[NCOL];
+    tile_loop<DIM, NCOL, G, false, MAXHI>(A, ntiles, h, col, bop, bank, hi);
     // ---- epilogue ----
     // Each lane folds its own 16 rows into per-bit partial class sums; the
     // two lane halves (rows differing in label bit 2) are combined with one
@@ -335,78 +479,65 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
 #pragma unroll
     for (int c = 0; c < NCOL; c++) {
         const int64_t i = idx[c];
-        float* b = bank[c];
         float p0[MDGMI_MAX_BITS], p1[MDGMI_MAX_BITS];  // this half's partial class sums
-        // label bits 0, 1, 3, 4 are bits 0..3 of the register index
-        p0[0] = ((b[0] + b[2]) + (b[4] + b[6])) + ((b[8] + b[10]) + (b[12] + b[14]));
-        p1[0] = ((b[1] + b[3]) + (b[5] + b[7])) + ((b[9] + b[11]) + (b[13] + b[15]));
-#pragma unroll
-        for (int j = 0; j < 8; j++) b[j] = b[2 * j] + b[2 * j + 1];
-        p0[1] = (b[0] + b[2]) + (b[4] + b[6]);
-        p1[1] = (b[1] + b[3]) + (b[5] + b[7]);
-#pragma unroll
-        for (int j = 0; j < 4; j++) b[j] = b[2 * j] + b[2 * j + 1];
-        p0[3] = b[0] + b[2];
-        p1[3] = b[1] + b[3];
-        p0[4] = b[0] + b[1];
-        p1[4] = b[2] + b[3];
-        p0[2] = p1[2] = p0[4] + p1[4];  // this half's total; label bit 2 is the lane half
-#pragma unroll
-        for (int k = 5; k < MDGMI_MAX_BITS; k++) {  // tile-index bits
-            p0[k] = k < m ? hi[c].R0[k - 5] : 1.0f;
-            p1[k] = k < m ? hi[c].R1[k - 5] : 1.0f;
-        }
-        // full class sums of bit k, identical in both halves
-        auto sums = [&](int k, float& S0k, float& S1k) {
-            if (k == 2) {
-                const Halves t = halves(p0[2]);
-                S0k = t.lo;
-                S1k = t.hi;
-            } else {
-                S0k = half_sum(p0[k]);
-                S1k = half_sum(p1[k]);
-            }
-        };
+        half_partials<MAXHI, G>(bank[c], hi[c], m, p0, p1);
         float S0t, S1t;
-        sums(2, S0t, S1t);
+        full_sums(p0, p1, 2, S0t, S1t);
         const float tot = S0t + S1t;
-        bool slow = false;
         if (LLR) {
             float smin = INFINITY;
 #pragma unroll
             for (int k = 0; k < MDGMI_MAX_BITS; k++) {
                 if (k < m) {
                     float S0k, S1k;
-                    sums(k, S0k, S1k);
+                    full_sums(p0, p1, k, S0k, S1k);
                     smin = fminf(smin, fminf(S0k, S1k));
                 }
             }
-            slow = !(smin >= ex2(kFarLog2));
-        }
-        uint32_t slot = 0;
-        bool row_ok = true;
-        float ui = 0.0f;
-        if (!LLR) {
-            // a sent row outside [0, M) gives a NaN cost instead of a stray read
-            const uint32_t row = i < n ? txs[i] : 0u;
-            row_ok = row < (uint32_t)M;
-            slot = labels[row_ok ? row : 0u];
-            // u of the sent point by the matrix cores themselves: one more MFMA
-            // whose row r is the sent point of sample r puts u_i(y) on the
-            // diagonal, bit-identical to the value inside the class sums, so
-            // the MI cost log2 sum_j 2^(u_j - u_i) carries no recomputation
-            // error. Diagonal element r sits in lane half (r >> 2) & 1,
-            // register ((r >> 3) << 2) | (r & 3).
-            half8 ad[NB];
-            load_a_at<NB>(A + (int)(slot >> 5) * TS + h * 32 + (int)(slot & 31), ad);
-            const f32x16 ud = tile_mfma<NB>(ad, bop[c]);
-            const int q = ((col >> 3) << 2) | (col & 3);
-            float dv = 0.0f;
+            // a class of some sample of this column lies too far for the
+            // common offset (or y is not finite): second pass for the column
+            if (__ballot(!(smin >= ex2(kFarLog2))) != 0ull) {
+                llr_far_pass<DIM, G, MAXHI>(A, ys, n, i, M, m, ntiles, s, X32, llr, p0, p1);
+                continue;
+            }
 #pragma unroll
-            for (int r = 0; r < 16; r++) dv = (r == q) ? ud[r] : dv;
-            const Halves d = halves(dv);
-            ui = ((col >> 2) & 1) ? d.hi : d.lo;
+            for (int j = 0; j < (MDGMI_MAX_BITS + 1) / 2; j++) {
+                if (2 * j < m) {  // uniform
+                    const int ke = 2 * j, ko = ke + 1 < MDGMI_MAX_BITS ? ke + 1 : ke;
+                    float S0e, S1e, S0o = 1.0f, S1o = 1.0f;
+                    if (ke == 2) {
+                        S0e = S0t;
+                        S1e = S1t;
+                    } else {
+                        full_sums(p0, p1, ke, S0e, S1e);
+                    }
+                    if (ko < m) full_sums(p0, p1, ko, S0o, S1o);
+                    const int k = ke + h;
+                    const float s0 = h ? S0o : S0e, s1 = h ? S1o : S1e;
+                    if (k < m && i < n) llr[i * m + k] = log2_ratio_fast(s1, s0) * (float)kLn2;
+                }
+            }
+            continue;
         }
+        // a sent row outside [0, M) gives a NaN cost instead of a stray read
+        const uint32_t row = i < n ? txs[i] : 0u;
+        const bool row_ok = row < (uint32_t)M;
+        const uint32_t slot = labels[row_ok ? row : 0u];
+        // u of the sent point by the matrix cores themselves: one more MFMA
+        // whose row r is the sent point of sample r puts u_i(y) on the
+        // diagonal, bit-identical to the value inside the class sums, so the
+        // MI cost log2 sum_j 2^(u_j - u_i) carries no recomputation error.
+        // Diagonal element r sits in lane half (r >> 2) & 1, register
+        // ((r >> 3) << 2) | (r & 3).
+        half8 ad[NB];
+        load_a_at<NB>(A + (int)(slot >> 5) * TS + h * 32 + (int)(slot & 31), ad);
+        const f32x16 ud = tile_mfma<NB>(ad, bop[c]);
+        const int q = ((col >> 3) << 2) | (col & 3);
+        float dv = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 16; r++) dv = (r == q) ? ud[r] : dv;
+        const Halves d = halves(dv);
+        const float ui = ((col >> 2) & 1) ? d.hi : d.lo;
         float cg = 0.0f;
 #pragma unroll
         for (int j = 0; j < (MDGMI_MAX_BITS + 1) / 2; j++) {
@@ -417,58 +548,41 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
                     S0e = S0t;
                     S1e = S1t;
                 } else {
-                    sums(ke, S0e, S1e);
+                    full_sums(p0, p1, ke, S0e, S1e);
                 }
-                if (ko < m) sums(ko, S0o, S1o);
+                if (ko < m) full_sums(p0, p1, ko, S0o, S1o);
                 const int k = ke + h;
                 const float s0 = h ? S0o : S0e, s1 = h ? S1o : S1e;
                 if (k < m) {
-                    if (LLR) {
-                        if (!slow && i < n) llr[i * m + k] = log2_ratio_fast(s1, s0) * (float)kLn2;
-                    } else {
-                        // log2(1 + S_other / S_sent) = log2((S0 + S1) / S_sent)
-                        const bool bk = (slot >> k) & 1;
-                        cg += bit_cost_sum2(s0 + s1, bk ? s1 : s0);
-                    }
+                    // log2(1 + S_other / S_sent) = log2((S0 + S1) / S_sent)
+                    const bool bk = (slot >> k) & 1;
+                    cg += bit_cost_sum2(s0 + s1, bk ? s1 : s0);
                 }
             }
         }
-        if (LLR) {
-            if (slow && h == 0 && i < n) {
-                // a class lies too far for the common offset: exact per-class path
-                float yc[DIM], ls0[MDGMI_MAX_BITS], ls1[MDGMI_MAX_BITS], ltot, ti;
-#pragma unroll
-                for (int d = 0; d < DIM; d++) yc[d] = ys[i * DIM + d];
-                exact_classes_f32<DIM>(yc, X32, M, m, s, -1, ls0, ls1, ltot, ti);
-#pragma unroll
-                for (int k = 0; k < MDGMI_MAX_BITS; k++)
-                    if (k < m) llr[i * m + k] = (ls1[k] - ls0[k]) * (float)kLn2;
-            }
+        cg = half_sum(cg);
+        if (h != 0 || i >= n) continue;
+        float cm;
+        if (ui >= kFarLog2) {
+            cm = mi_cost2(tot, ui);
         } else {
-            cg = half_sum(cg);
-            if (h != 0 || i >= n) continue;
-            float cm;
-            if (ui >= kFarLog2) {
-                cm = mi_cost2(tot, ui);
-            } else {
-                // the sent point itself is far from y (or y is not finite)
-                float yc[DIM], ls0[MDGMI_MAX_BITS], ls1[MDGMI_MAX_BITS], ltot, ti = 0.0f;
+            // the sent point itself is far from y (or y is not finite)
+            float yc[DIM], ls0[MDGMI_MAX_BITS], ls1[MDGMI_MAX_BITS], ltot, ti = 0.0f;
 #pragma unroll
-                for (int d = 0; d < DIM; d++) yc[d] = ys[i * DIM + d];
-                exact_classes_f32<DIM>(yc, X32, M, m, s, (int)slot, ls0, ls1, ltot, ti);
-                cg = 0.0f;
+            for (int dd = 0; dd < DIM; dd++) yc[dd] = ys[i * DIM + dd];
+            exact_classes_f32<DIM>(yc, X32, M, m, s, (int)slot, ls0, ls1, ltot, ti);
+            cg = 0.0f;
 #pragma unroll
-                for (int k = 0; k < MDGMI_MAX_BITS; k++) {
-                    if (k < m) {
-                        const bool bk = (slot >> k) & 1;
-                        cg += bit_cost2(bk ? ls0[k] - ls1[k] : ls1[k] - ls0[k]);
-                    }
+            for (int k = 0; k < MDGMI_MAX_BITS; k++) {
+                if (k < m) {
+                    const bool bk = (slot >> k) & 1;
+                    cg += bit_cost2(bk ? ls0[k] - ls1[k] : ls1[k] - ls0[k]);
                 }
-                cm = ltot + ti;
             }
-            if (!row_ok) cg = cm = NAN;
-            acc.add((double)cg, (double)cm);
+            cm = ltot + ti;
         }
+        if (!row_ok) cg = cm = NAN;
+        acc.add((double)cg, (double)cm);
     }
 }
 

@@ -209,6 +209,32 @@ def test_far_samples_take_the_exact_per_class_path(orc, path):
     assert abs(out[0, 1] - r[1]) <= 1e-4 * max(1.0, abs(r[1]))
 
 
+@pytest.mark.parametrize("path", F32_PATHS)
+def test_far_class_windows(orc, path):
+    """LLRs of samples whose farthest class lies inside the common exponent
+    window, in the window of the raised offset (the second pass of the MFMA
+    path) and beyond both (exact per-class path), all against the oracle.
+    The regimes are counted on the host from the class distances."""
+    f, gf = gfmt("16qam")
+    s2 = float(w.sigma2_from_snr_db(20, 2))
+    s = 1.0 / (math.log(2.0) * 2.0 * s2)
+    rng = np.random.default_rng(11)
+    r = rng.uniform(0.3, 2.0, size=3000)
+    th = rng.uniform(0.0, 2.0 * np.pi, size=3000)
+    y = np.stack([r * np.cos(th), r * np.sin(th)], axis=1).astype(np.float32)
+    d = s * ((y.astype(np.float64)[:, None, :] - f.X[None]) ** 2).sum(-1)   # s |y - x|^2, log2 units
+    far = np.zeros(len(y))           # distance of the farthest class (its nearest point)
+    for k in range(f.m):
+        b = (f.labels >> k) & 1
+        far = np.maximum(far, np.maximum(d[:, b == 0].min(1), d[:, b == 1].min(1)))
+    assert (far < 180).sum() > 100 and ((far > 220) & (far < 280)).sum() > 100 and (far > 320).sum() > 100
+    say(f"[far windows] path={path}")
+    lam = mdgmi.mdgmi_llr(gf, dev(y, torch.float32), s2, path=path).cpu().numpy().astype(np.float64)
+    ref = orc.llr(y.astype(np.float64), f.X, f.labels, s2)
+    ratio, _ = llr_bar(lam, ref, LLR_RTOL)
+    assert ratio <= 1.0, ratio
+
+
 @pytest.mark.parametrize("path", ["f64"] + F32_PATHS)
 def test_nonfinite_input_is_flagged(orc, path):
     f, gf = gfmt("4d64")
