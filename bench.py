@@ -257,8 +257,8 @@ def ragged_leg(args, log, scale=None):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build measures one GPU: the exact GMI/MI path has no "
-                                   "multi-GPU mode here (shards would all-reduce 5 doubles per SNR)",
+        print(json.dumps({"error": "single-GPU benchmark: the GMI/MI engine runs on one GPU and has no "
+                                   "multi-GPU mode (shards would all-reduce 5 doubles per SNR point)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np

@@ -241,9 +241,9 @@ int mdgmi_mlp_gmi(const mdgmi_mlp* net, const mdgmi_format* fmt, const float* y,
                   const double* snr_db_host, int32_t n_snr, int64_t chunk, double* out, void* ws, size_t ws_bytes,
                   void* stream);
 /* Inference kernel choice of mdgmi_mlp_gmi for networks of shape
- * [<=16, 256, 256, 256, <=32]: waves = 4 or 8 per block for the fused
- * kernel (activations in registers, weights staged in LDS), 0 for the
- * layer-by-layer GEMM path. Process-wide. */
+ * [<=16, 256, 256, 256, <=32]: waves = 8 (default) or 4 per block for the
+ * fused kernel (activations in registers, weights staged in LDS), 0 for the
+ * layer-by-layer GEMM path. Process-wide; returns MDGMI_E_ARG otherwise. */
 int mdgmi_mlp_set_fused(int waves);
 /* Checkpoint: widths, step, masters and both Adam moments (binary). */
 int mdgmi_mlp_save(const mdgmi_mlp* net, const char* path);

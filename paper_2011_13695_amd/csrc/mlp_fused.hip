@@ -11,8 +11,9 @@
 // {4h..4h+3, 8+4h..8+4h+3}. Activations never leave registers.
 //
 // LDS: W_1 (8 KiB), W_4 (16 KiB) and all biases stay resident; W_2 and W_3
-// (128 KiB each) are staged in turn into one buffer, once per block of 256
-// samples (8 waves x 32). The logits are turned into the per-sample GMI cost
+// (128 KiB each) are staged in turn into one buffer, once per block of
+// 32 samples per wave (8 waves by default: two per SIMD, so one wave's
+// GELUs overlap the other's MFMAs). The logits are turned into the per-sample GMI cost
 // in the kernel; only FP64 block partials are written.
 #include <algorithm>
 #include <cmath>
@@ -79,17 +80,18 @@ __global__ void k_fused_weights(const float* __restrict__ W, int out, int in, in
 
 // One hidden layer: in activations act_in [kTiles][2] (bf16x8 per lane),
 // weights in LDS (fused layout), out activations gelu(W h + b) into act_out.
-// Output tiles go in two halves of four: per half, K-major order with four
-// independent accumulation chains, so the live set is 4 x 16 accumulators,
-// the resident input activations, one K-block of weight operands and the
-// output half done so far.
+// Output tiles go in groups of kGroup: per group, K-major order with kGroup
+// independent accumulation chains, so the live set is kGroup x 16
+// accumulators, the resident input activations, one K-block of weight
+// operands and the output tiles done so far.
+template <int kGroup>
 __device__ __forceinline__ void hidden_layer(const uint4* __restrict__ Wl, const float* __restrict__ bias,
                                              const bf16x8 (&act_in)[kTiles][2], bf16x8 (&act_out)[kTiles][2],
                                              int lane) {
     const int h = lane >> 5;
-    constexpr int kHalf = kTiles / 2;
+    constexpr int kHalf = kGroup;
 #pragma unroll
-    for (int half = 0; half < 2; half++) {
+    for (int half = 0; half < kTiles / kGroup; half++) {
         f32x16 acc[kHalf];
 #pragma unroll
         for (int j = 0; j < kHalf; j++) acc[j] = bias_acc(bias, half * kHalf + j, h);
@@ -118,6 +120,8 @@ __device__ __forceinline__ void hidden_layer(const uint4* __restrict__ Wl, const
             }
             act_out[ot][0] = o0.v;
             act_out[ot][1] = o1.v;
+            // one tile's GELUs at a time keeps their temporaries few
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 }
@@ -194,14 +198,16 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp_gmi_fused(
             __builtin_amdgcn_sched_barrier(0);
         }
         // ---- layer 2
+#pragma unroll 4
         for (int k = threadIdx.x; k < kWHU; k += kThreads) sWH[k] = w2f[k];
         __syncthreads();
-        hidden_layer(sWH, sB + kH, actA, actB, lane);
+        hidden_layer<kWaves == 4 ? 4 : 2>(sWH, sB + kH, actA, actB, lane);
         __syncthreads();
         // ---- layer 3
+#pragma unroll 4
         for (int k = threadIdx.x; k < kWHU; k += kThreads) sWH[k] = w3f[k];
         __syncthreads();
-        hidden_layer(sWH, sB + 2 * kH, actB, actA, lane);
+        hidden_layer<kWaves == 4 ? 4 : 2>(sWH, sB + 2 * kH, actB, actA, lane);
         // ---- layer 4: logits, one output tile of 32 rows
         f32x16 zo = bias_acc(sB + 3 * kH, 0, h);
 #pragma unroll
@@ -258,7 +264,7 @@ hipError_t build_fused_weights(const float* W, int out, int in, int layer, __bf1
 
 int fused_grid() { return device_cu_count(); }
 
-int g_fused_waves = 4;  // 4: one wave per SIMD with the whole register file; 8: two, tighter registers
+int g_fused_waves = 8;  // 8: two waves per SIMD (256 VGPRs, output tiles in pairs); 4: one, whole register file
 
 template <int W>
 hipError_t launch_fused_w(__bf16* const* wf, const float* const* bias, int in_dim, int out_dim, const float* y, int dim,

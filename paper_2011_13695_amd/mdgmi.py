@@ -496,5 +496,5 @@ def mdgmi_mlp_gmi(net: "MLP", fmt: Format, y, tx_idx, snr_db, chunk: int = 1 << 
 
 
 def mdgmi_mlp_set_fused(waves: int) -> None:
-    """Inference kernel of mdgmi_mlp_gmi: 4 or 8 waves fused, 0 layer by layer."""
+    """Inference kernel of mdgmi_mlp_gmi: 8 (default) or 4 waves fused, 0 layer by layer."""
     _check("mdgmi_mlp_set_fused", lib().mdgmi_mlp_set_fused(int(waves)))

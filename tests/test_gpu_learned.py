@@ -95,7 +95,7 @@ def test_fused_inference_matches_layered_path(waves, orc):
         mdgmi.mdgmi_mlp_set_fused(waves)
         out = mdgmi.mdgmi_mlp_gmi(net, gf, y, tx, snr).cpu().numpy()
     finally:
-        mdgmi.mdgmi_mlp_set_fused(4)
+        mdgmi.mdgmi_mlp_set_fused(8)
     np.testing.assert_array_equal(out[:, 4], ref[:, 4])
     assert np.max(np.abs(out[:, 0] - ref[:, 0])) <= 1e-3, (out[:, 0], ref[:, 0])
     x = mdgmi.mdgmi_mlp_features(y[0].contiguous(), float(snr[0]))
