@@ -1,6 +1,7 @@
 """Parity at the full size of the 8-D workload (M = 2048 two-shell format,
 16 SNR points x 1e7 samples, generated on the device), in the launch
-configuration the benchmark times.
+configuration the benchmark times, and of the 4-D workload (M = 64
+two-ring product, 21 SNR points x 1e7 samples) on its default path.
 
 The oracle cannot evaluate 3.3e11 pairs, so the full-size results are tied
 to it through outputs it can compute one by one and through properties that
@@ -116,3 +117,39 @@ def test_mi_against_sampled_oracle(full, orc):
         assert abs(out[q, 1] - r[1]) <= 5.0 * r[3] + 1e-6
         assert abs(out[q, 0] - r[0]) <= 5.0 * r[2] + 1e-6
         assert out[q, 1] >= out[q, 0] - 3.0 * math.hypot(out[q, 2], out[q, 3])
+
+
+def test_4d64_workload_full_size(orc):
+    """21 SNR points x 1e7 samples of the 4-D M = 64 format on the default
+    (autotuned or untuned) path: sampled LLR rows against the oracle, the
+    GMI of the one launch against the bit costs of the full LLR arrays, and
+    the sampled GMI/MI within Monte-Carlo error."""
+    wl = w.workload_4d64()
+    f = wl.fmt
+    gf = mdgmi.Format.of(f)
+    say(f"[full] generating {len(wl.snr_db)} x {wl.n} samples of {f.name}")
+    y, tx = mdgmi.mdgmi_generate(gf, wl.seed, wl.sigma2, wl.n, dtype=torch.float32)
+    out = mdgmi.mdgmi_gmi(gf, y, tx, wl.sigma2, path="auto").cpu().numpy()
+    assert np.all(out[:, 4] == wl.n) and np.all(out[:, 5] == 0)
+    rng = np.random.default_rng(64)
+    ws = mdgmi.workspace(mdgmi.mdgmi_llr_workspace_size(gf, wl.n, "auto"))
+    lab = torch.from_numpy(f.labels.astype(np.int64)).cuda()
+    bits = torch.arange(f.m, device="cuda", dtype=torch.int64)
+    for q in range(0, len(wl.snr_db), 4):
+        s2 = float(wl.sigma2[q])
+        lam = mdgmi.mdgmi_llr(gf, y[q], s2, path="auto", ws=ws)
+        rows = np.sort(rng.choice(wl.n, size=2000, replace=False))
+        ri = torch.from_numpy(rows).cuda()
+        yr = y[q].index_select(0, ri).cpu().numpy().astype(np.float64)
+        ref = orc.llr(yr, f.X, f.labels, s2)
+        got = lam.index_select(0, ri).cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(got - ref) / (LLR_RTOL * np.maximum(np.abs(ref), 1.0))) <= 1.0, q
+        b = ((lab[tx[q].long()].unsqueeze(1) >> bits) & 1).double()
+        u = -(2.0 * b - 1.0) * lam.double()
+        cg = (torch.clamp(u, min=0.0) + torch.log1p(torch.exp(-u.abs()))).sum(dim=1) / math.log(2.0)
+        assert abs(f.m - float(cg.mean()) - out[q, 0]) <= GMI_TOL32, q
+        tr = tx[q].index_select(0, ri).cpu().numpy().view(np.uint32)
+        r = orc.gmi(yr, tr, f.X, f.labels, s2)
+        assert abs(out[q, 1] - r[1]) <= 5.0 * r[3] + 1e-6
+        say(f"[full] 4D q={q}: GMI {out[q, 0]:.5f} MI {out[q, 1]:.5f}")
+        del lam, b, u, cg
