@@ -61,7 +61,9 @@ typedef enum {
     MDGMI_PATH_F32_DIRECT = 1,       /* FP32 distances on the vector ALUs         */
     MDGMI_PATH_F32_MFMA_F16SPLIT = 2,/* distance term on MFMA, fp16 hi+lo split,  */
                                      /* FP32 accumulate; log-sum-exp in FP32      */
-    MDGMI_PATH_AUTO = 5              /* fastest FP32 exact path for the shape     */
+    MDGMI_PATH_AUTO = 5              /* fastest FP32 exact path for the shape:    */
+                                     /* the autotuner's choice for (dim, M), else */
+                                     /* MFMA from M = 128 and direct below        */
 } mdgmi_path;
 
 /* Fields of one GMI/MI result row (doubles). */

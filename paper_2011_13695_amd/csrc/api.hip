@@ -55,8 +55,8 @@ int resolve_path(const mdgmi_format* f, int path, double max_s, int* out) {
             const int t = tuned_path(f->dim, f->M);
             if (t == MDGMI_PATH_F32_DIRECT || (t == MDGMI_PATH_F32_MFMA_F16SPLIT && mfma_ok))
                 *out = t;
-            else
-                *out = mfma_ok ? MDGMI_PATH_F32_MFMA_F16SPLIT : MDGMI_PATH_F32_DIRECT;
+            else  // untuned: below 128 points the per-sample work of the MFMA path dominates
+                *out = mfma_ok && f->M >= 128 ? MDGMI_PATH_F32_MFMA_F16SPLIT : MDGMI_PATH_F32_DIRECT;
             return MDGMI_OK;
         }
         default:
