@@ -45,6 +45,7 @@ def lib():
                                    ctypes.c_double, P, P]
         L.oracle_gmi.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, P, P, ctypes.c_int,
                                  ctypes.c_double, P]
+        L.oracle_hd.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_double, P]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -120,6 +121,21 @@ def gmi(y, tx_idx, X, labels, sigma2):
 def gmi_per_snr(y, tx_idx, X, labels, sigma2s):
     """Rows of gmi() for y (n_snr, n, N), tx (n_snr, n) and one sigma2 per SNR."""
     return np.stack([gmi(y[s], tx_idx[s], X, labels, s2) for s, s2 in enumerate(sigma2s)])
+
+
+def hd(y, tx_idx, X, labels, sigma2):
+    """Hard decisions: (BER of the bitwise MAP decisions, SER of the
+    nearest-point decisions, n, non-finite count)."""
+    X = _c(X, np.float64)
+    M, dim = X.shape
+    y = _c(np.reshape(y, (-1, dim)), np.float64)
+    tx = _c(tx_idx, np.uint32)
+    lab = _c(labels, np.uint32)
+    out = np.empty(4)
+    rc = lib().oracle_hd(_ptr(y), _ptr(tx), y.shape[0], dim, _ptr(X), _ptr(lab), M, float(sigma2), _ptr(out))
+    if rc != 0:
+        raise RuntimeError(f"oracle_hd failed ({rc})")
+    return out
 
 
 # ---------------------------------------------------------------- MLP demapper

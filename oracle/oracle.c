@@ -225,6 +225,76 @@ int oracle_gmi(const double* y, const uint32_t* tx_idx, int64_t n, int dim, cons
 }
 
 /* ------------------------------------------------------------------------
+ * Hard decisions (FP64). Two decisions per received sample:
+ *   bitwise MAP   b_hat_k = 1 if lambda_k > 0, else 0   (the sign of the
+ *                 exact LLR: the hard decision of bit-metric decoding)
+ *   nearest point j_hat = argmin_j ||y - x_j||^2, ties to the lowest row
+ * Per sample: errs[s] = number of k with b_hat_k != b_k(i) (0..m) and
+ * sym[s] = 1 if j_hat != i else 0. The estimates are
+ *   BER = sum errs / (n m),  SER = sum sym / n.
+ * Non-finite samples count as errors and are reported separately.
+ * ---------------------------------------------------------------------- */
+static void hd_one(const double* y, int dim, const double* X, const uint32_t* labels, int M, double sigma2,
+                   uint32_t row, double* t, int* errs, int* sym) {
+    int m = log2_exact(M);
+    metrics(y, X, M, dim, sigma2, t);
+    int e = 0;
+    uint32_t lab = labels[row];
+    for (int k = 0; k < m; k++) {
+        double lam = class_lse(t, labels, M, k, 1) - class_lse(t, labels, M, k, 0);
+        int bhat = lam > 0.0 ? 1 : 0;
+        if (!(lam == lam)) bhat = -1; /* NaN: an error for either bit value */
+        if (bhat != (int)((lab >> k) & 1u)) e++;
+    }
+    int best = 0;
+    for (int j = 1; j < M; j++)
+        if (t[j] < t[best]) best = j;
+    *errs = e;
+    *sym = (best != (int)row || !(t[best] == t[best])) ? 1 : 0;
+}
+
+/* out[0] = BER, out[1] = SER, out[2] = n, out[3] = non-finite samples. */
+int oracle_hd(const double* y, const uint32_t* tx_idx, int64_t n, int dim, const double* X,
+              const uint32_t* labels, int M, double sigma2, double* out) {
+    if (n < 1) return -2;
+    int m = log2_exact(M);
+    int64_t bit_err = 0, sym_err = 0, bad = 0;
+    int err = 0;
+#pragma omp parallel reduction(+ : bit_err, sym_err, bad)
+    {
+        double* t = (double*)malloc(sizeof(double) * (size_t)M);
+        if (!t) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t s = 0; s < n; s++) {
+                int e, q;
+                const double* ys = y + s * dim;
+                int finite = 1;
+                for (int d = 0; d < dim; d++)
+                    if (!isfinite(ys[d])) finite = 0;
+                hd_one(ys, dim, X, labels, M, sigma2, tx_idx[s], t, &e, &q);
+                if (!finite) {
+                    e = m;
+                    q = 1;
+                    bad++;
+                }
+                bit_err += e;
+                sym_err += q;
+            }
+            free(t);
+        }
+    }
+    if (err) return -1;
+    out[0] = (double)bit_err / ((double)n * (double)m);
+    out[1] = (double)sym_err / (double)n;
+    out[2] = (double)n;
+    out[3] = (double)bad;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
  * MLP demapper oracle (FP64). A fully connected network maps the input
  * features x (the received sample and an SNR feature) to m logits that are
  * read as LLRs in nats:
