@@ -75,6 +75,7 @@ def parse():
     ap.add_argument("--learned-eval", type=float, default=1e8, help="held-out samples over the 16 SNR points")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch leg")
     ap.add_argument("--no-llr", action="store_true", help="skip timing the LLR-output mode")
+    ap.add_argument("--no-hd", action="store_true", help="skip the hard-decision (BER/SER/Q) leg")
     ap.add_argument("--ragged-scale", type=float, default=1.0, help="scale of the ragged sample counts")
     ap.add_argument("--copy-probe", type=float, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration) and exit")
@@ -181,6 +182,48 @@ def learned_leg(gf, wl, args, log):
         "note": "learned value counts n*M sample*points per sample demapped by the network; mixed routes "
                 "each SNR point to the learned kernel where its paired GMI loss <= 0.01 bit, else exact",
     }
+
+
+def q_crossing(snr_db, q_db, q_ref):
+    """SNR (dB) at which the Q-factor curve first reaches q_ref, by linear
+    interpolation between the bracketing SNR points (None if it never does)."""
+    for k in range(len(snr_db) - 1):
+        a, b = q_db[k], q_db[k + 1]
+        if a is not None and a < q_ref and (b is None or b >= q_ref):
+            if b is None:
+                return float(snr_db[k + 1])
+            return float(snr_db[k] + (q_ref - a) / (b - a) * (snr_db[k + 1] - snr_db[k]))
+    return None
+
+
+def hd_leg(gf, wl, y, tx, path, gmi_out, reps=3):
+    """Hard decisions on the timed workload: bit error rate of the bitwise MAP
+    decision, symbol error rate of the nearest-point decision and the Q-factor
+    per SNR point, with the SNR at which Q reaches the HD-FEC thresholds the
+    paper quotes (8.4 dB at 6.7 % overhead, 5.7 dB at 20 %)."""
+    import numpy as np
+    import torch
+    from paper_2011_13695_amd import mdgmi
+
+    n_snr = len(wl.sigma2)
+    ws = mdgmi.workspace(mdgmi.mdgmi_gmi_hd_workspace_size(gf, wl.n, n_snr, path))
+    out = torch.empty((n_snr, mdgmi.MDGMI_NFIELDS_HD), dtype=torch.float64, device="cuda")
+    mdgmi.mdgmi_gmi_hd(gf, y, tx, wl.sigma2, path=path, out=out, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        mdgmi.mdgmi_gmi_hd(gf, y, tx, wl.sigma2, path=path, out=out, ws=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    h = out.cpu().numpy()
+    q_db = [mdgmi.mdgmi_q_factor_db(float(b)) for b in h[:, 6]]
+    q_db = [None if not np.isfinite(v) else float(v) for v in q_db]   # BER 0: Q unbounded
+    snr = [float(v) for v in wl.snr_db]
+    return {"ms_per_call": ms, "value": n_snr * wl.n * gf.M / (ms * 1e-3),
+            "ber": [float(v) for v in h[:, 6]], "ser": [float(v) for v in h[:, 7]], "q_db": q_db,
+            "snr_db_at_q_8.4dB": q_crossing(snr, q_db, 8.4), "snr_db_at_q_5.7dB": q_crossing(snr, q_db, 5.7),
+            "max_abs_dgmi_vs_timed_path": float(np.abs(h[:, :2] - gmi_out[:, :2]).max()),
+            "note": "mdgmi_gmi_hd: GMI/MI plus BER/SER in one pass; Q = 20 log10(sqrt(2) erfc^-1(2 BER))"}
 
 
 def ragged_leg(args, log, scale=None):
@@ -330,6 +373,8 @@ def main():
                              "bytes_written": n_snr * wl.n * f.m * 4,
                              "note": "mdgmi_llr over every SNR point, one call each, LLRs of all samples written"}
         del lam, lws
+    if not args.no_hd:
+        extra["hard_decisions"] = hd_leg(gf, wl, y, tx, args.path, out)
     achieved = pairs / (kernel_ms * 1e-3)
     line = {
         "metric": METRIC,

@@ -74,7 +74,12 @@ enum {
     MDGMI_F_SE_MI = 3,     /* standard error of the MI estimate             */
     MDGMI_F_N = 4,         /* number of samples                              */
     MDGMI_F_NONFINITE = 5, /* samples whose GMI or MI cost is NaN or inf    */
-    MDGMI_NFIELDS = 6
+    MDGMI_NFIELDS = 6,
+    MDGMI_F_BER = 6,       /* mdgmi_gmi_hd: bit error rate of the bitwise   */
+                           /* MAP decisions (the signs of the exact LLRs)   */
+    MDGMI_F_SER = 7,       /* mdgmi_gmi_hd: symbol error rate of the        */
+                           /* nearest-point decisions                        */
+    MDGMI_NFIELDS_HD = 8
 };
 
 #define MDGMI_MAX_BITS 12   /* M <= 4096 */
@@ -139,6 +144,31 @@ int mdgmi_gmi_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, 
 int mdgmi_gmi(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int64_t n,
               const double* sigma2_host, int32_t n_snr, int32_t path, double* out, void* ws,
               size_t ws_bytes, void* stream);
+
+/* Hard decisions on the same pass. The paper's figure of merit is the
+ * Q-factor estimated from the bit error rate (continuous real-time
+ * transmission subsection), compared with HD-FEC thresholds (experimental
+ * results subsections of the IM/DD and KK chains). Everything mdgmi_gmi
+ * computes, plus per SNR point:
+ *   MDGMI_F_BER  fraction of (sample, bit) pairs whose bitwise MAP decision
+ *                (bit k = 1 iff lambda_k > 0) differs from the sent bit;
+ *   MDGMI_F_SER  fraction of samples for which some other point is strictly
+ *                nearer to y than the sent one (nearest-point decision;
+ *                an exact tie with the sent point counts as correct).
+ * A sample with non-finite y counts m bit errors and one symbol error.
+ *   out  device [n_snr][MDGMI_NFIELDS_HD] double.
+ * Paths as for mdgmi_gmi (the MFMA path runs its 16-wave single-column
+ * shape here whatever the tuning). */
+int mdgmi_gmi_hd_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, int32_t path,
+                                size_t* bytes);
+int mdgmi_gmi_hd(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int64_t n,
+                 const double* sigma2_host, int32_t n_snr, int32_t path, double* out, void* ws,
+                 size_t ws_bytes, void* stream);
+
+/* Q-factor in dB of a bit error rate, 20 log10(sqrt(2) erfc^-1(2 ber)) (the
+ * Gaussian-noise conversion; the paper states no formula). Host-only, no
+ * GPU needed; +inf for ber = 0, -inf for ber = 0.5, NaN outside [0, 0.5]. */
+double mdgmi_q_factor_db(double ber);
 
 /* ---- ragged batches ------------------------------------------------------
  * Many (format, SNR, sample count) instances evaluated by one persistent

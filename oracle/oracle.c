@@ -228,9 +228,11 @@ int oracle_gmi(const double* y, const uint32_t* tx_idx, int64_t n, int dim, cons
  * Hard decisions (FP64). Two decisions per received sample:
  *   bitwise MAP   b_hat_k = 1 if lambda_k > 0, else 0   (the sign of the
  *                 exact LLR: the hard decision of bit-metric decoding)
- *   nearest point j_hat = argmin_j ||y - x_j||^2, ties to the lowest row
+ *   nearest point j_hat = argmin_j ||y - x_j||^2; a tie that includes the
+ *                 sent point i is decided for i (measure zero for continuous
+ *                 noise; the choice fixes coincident-point formats)
  * Per sample: errs[s] = number of k with b_hat_k != b_k(i) (0..m) and
- * sym[s] = 1 if j_hat != i else 0. The estimates are
+ * sym[s] = 1 if some j has ||y - x_j|| < ||y - x_i||, else 0. The estimates are
  *   BER = sum errs / (n m),  SER = sum sym / n.
  * Non-finite samples count as errors and are reported separately.
  * ---------------------------------------------------------------------- */
@@ -246,11 +248,13 @@ static void hd_one(const double* y, int dim, const double* X, const uint32_t* la
         if (!(lam == lam)) bhat = -1; /* NaN: an error for either bit value */
         if (bhat != (int)((lab >> k) & 1u)) e++;
     }
-    int best = 0;
-    for (int j = 1; j < M; j++)
-        if (t[j] < t[best]) best = j;
+    /* nearest-point decision: wrong iff some other point is strictly nearer
+     * than the sent one (an exact tie is decided in favour of the sent point) */
+    int wrong = !(t[row] == t[row]);
+    for (int j = 0; j < M; j++)
+        if (t[j] < t[row]) wrong = 1;
     *errs = e;
-    *sym = (best != (int)row || !(t[best] == t[best])) ? 1 : 0;
+    *sym = wrong;
 }
 
 /* out[0] = BER, out[1] = SER, out[2] = n, out[3] = non-finite samples. */

@@ -1,6 +1,7 @@
 // C ABI of libmdgmi: argument checks on the host, format staging, workspace
 // carving and kernel dispatch. Every check happens before the first launch.
 #include <algorithm>
+#include <limits>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -66,13 +67,15 @@ int resolve_path(const mdgmi_format* f, int path, double max_s, int* out) {
 
 double s_of(double sigma2) { return kLog2e / (2.0 * sigma2); }
 
+int part_stride(int mode) { return mode == kModeHd ? kNPartHd : kNPart; }
+
 struct GmiPlan {
     int path;
     LaunchCfg cfg;
     size_t part_bytes, image_bytes, total;
 };
 
-GmiPlan plan_gmi(const mdgmi_format* f, int64_t n, int n_snr, int path) {
+GmiPlan plan_gmi(const mdgmi_format* f, int64_t n, int n_snr, int path, int mode = kModeGmi) {
     GmiPlan p{};
     p.path = path;
     const int per_launch = std::min(n_snr, kMaxSnrPerLaunch);
@@ -83,10 +86,10 @@ GmiPlan plan_gmi(const mdgmi_format* f, int64_t n, int n_snr, int path) {
         p.cfg = direct_cfg(f, n);
         p.image_bytes = direct_image_bytes(f, per_launch);
     } else {
-        p.cfg = mfma_cfg(f, n, n_snr);
+        p.cfg = mfma_cfg(f, n, n_snr, mode);
         p.image_bytes = mfma_image_bytes(f, per_launch);
     }
-    p.part_bytes = (size_t)n_snr * p.cfg.blocks_per_snr * kNPart * sizeof(double);
+    p.part_bytes = (size_t)n_snr * p.cfg.blocks_per_snr * part_stride(mode) * sizeof(double);
     p.total = align_up(p.part_bytes) + align_up(p.image_bytes);
     return p;
 }
@@ -102,6 +105,60 @@ SnrArgs snr_args(const double* sigma2, int q0, int cnt) {
         sa.inv2s2[q] = 1.0 / (2.0 * s2);
     }
     return sa;
+}
+
+
+int gmi_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, int32_t path, int mode, size_t* bytes) {
+    if (!fmt || !bytes) return MDGMI_E_NULL;
+    if (n < 1 || n_snr < 1) return MDGMI_E_SHAPE;
+    int p = path;
+    if (p == MDGMI_PATH_AUTO) p = MDGMI_PATH_F32_MFMA_F16SPLIT;
+    if (p != MDGMI_PATH_F64 && p != MDGMI_PATH_F32_DIRECT && p != MDGMI_PATH_F32_MFMA_F16SPLIT) return MDGMI_E_ARG;
+    GmiPlan pl = plan_gmi(fmt, n, n_snr, p, mode);
+    // AUTO resolves per call (format size, tuning, fp16 range); size for
+    // whichever of the two FP32 paths it may take.
+    if (path == MDGMI_PATH_AUTO)
+        pl.total = std::max(pl.total, plan_gmi(fmt, n, n_snr, MDGMI_PATH_F32_DIRECT, mode).total);
+    *bytes = pl.total;
+    return MDGMI_OK;
+}
+
+// One pass over n samples at n_snr noise levels: per-block partial sums
+// (launches of at most kMaxSnrPerLaunch SNR points), then the FP64 reduce.
+int run_gmi(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int64_t n, const double* sigma2_host,
+            int32_t n_snr, int32_t path, int mode, double* out, void* ws, size_t ws_bytes, void* stream) {
+    if (!fmt || !y || !tx_idx || !sigma2_host || !out) return MDGMI_E_NULL;
+    if (n < 1 || n_snr < 1) return MDGMI_E_SHAPE;
+    double max_s = 0.0;
+    for (int q = 0; q < n_snr; q++) {
+        if (!finite_pos(sigma2_host[q])) return MDGMI_E_SIGMA2;
+        max_s = std::max(max_s, s_of(sigma2_host[q]));
+    }
+    int p = 0;
+    int rc = resolve_path(fmt, path, max_s, &p);
+    if (rc != MDGMI_OK) return rc;
+    GmiPlan pl = plan_gmi(fmt, n, n_snr, p, mode);
+    if (!ws || ws_bytes < pl.total) return MDGMI_E_WORKSPACE;
+    rc = check_device(fmt);
+    if (rc != MDGMI_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    double* part = (double*)ws;
+    void* image = (char*)ws + align_up(pl.part_bytes);
+    for (int q0 = 0; q0 < n_snr; q0 += kMaxSnrPerLaunch) {
+        const int cnt = std::min(kMaxSnrPerLaunch, n_snr - q0);
+        SnrArgs sa = snr_args(sigma2_host, q0, cnt);
+        double* pq = part + (size_t)q0 * pl.cfg.blocks_per_snr * part_stride(mode);
+        hipError_t e;
+        if (p == MDGMI_PATH_F64)
+            e = launch_f64(fmt, (const double*)y, tx_idx, n, sa, mode, nullptr, pq, pl.cfg, st);
+        else if (p == MDGMI_PATH_F32_DIRECT)
+            e = launch_direct(fmt, (const float*)y, tx_idx, n, sa, mode, nullptr, pq, (float*)image, pl.cfg, st);
+        else
+            e = launch_mfma(fmt, (const float*)y, tx_idx, n, sa, mode, nullptr, pq, image, pl.cfg, st);
+        if (e != hipSuccess) return MDGMI_E_HIP;
+    }
+    hipError_t e = launch_reduce(part, n_snr, pl.cfg.blocks_per_snr, n, fmt->m, out, st, mode == kModeHd);
+    return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
 }
 
 }  // namespace
@@ -249,64 +306,53 @@ int mdgmi_llr(const mdgmi_format* fmt, const void* y, int64_t n, double sigma2, 
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     if (p == MDGMI_PATH_F64) {
-        e = launch_f64(fmt, (const double*)y, nullptr, n, sa, true, (double*)llr, nullptr, f64_cfg(fmt, n), st);
+        e = launch_f64(fmt, (const double*)y, nullptr, n, sa, kModeLlr, (double*)llr, nullptr, f64_cfg(fmt, n), st);
     } else if (p == MDGMI_PATH_F32_DIRECT) {
-        e = launch_direct(fmt, (const float*)y, nullptr, n, sa, true, (float*)llr, nullptr, (float*)ws,
+        e = launch_direct(fmt, (const float*)y, nullptr, n, sa, kModeLlr, (float*)llr, nullptr, (float*)ws,
                           direct_cfg(fmt, n), st);
     } else {
-        e = launch_mfma(fmt, (const float*)y, nullptr, n, sa, true, (float*)llr, nullptr, ws, mfma_cfg(fmt, n, 1),
+        e = launch_mfma(fmt, (const float*)y, nullptr, n, sa, kModeLlr, (float*)llr, nullptr, ws, mfma_cfg(fmt, n, 1),
                         st);
     }
     return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
 }
 
 int mdgmi_gmi_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, int32_t path, size_t* bytes) {
-    if (!fmt || !bytes) return MDGMI_E_NULL;
-    if (n < 1 || n_snr < 1) return MDGMI_E_SHAPE;
-    int p = path;
-    if (p == MDGMI_PATH_AUTO) p = fmt->M >= 32 ? MDGMI_PATH_F32_MFMA_F16SPLIT : MDGMI_PATH_F32_DIRECT;
-    if (p != MDGMI_PATH_F64 && p != MDGMI_PATH_F32_DIRECT && p != MDGMI_PATH_F32_MFMA_F16SPLIT) return MDGMI_E_ARG;
-    GmiPlan pl = plan_gmi(fmt, n, n_snr, p);
-    // AUTO may fall back to the direct path at run time; size for the larger.
-    if (path == MDGMI_PATH_AUTO) pl.total = std::max(pl.total, plan_gmi(fmt, n, n_snr, MDGMI_PATH_F32_DIRECT).total);
-    *bytes = pl.total;
-    return MDGMI_OK;
+    return gmi_workspace_size(fmt, n, n_snr, path, kModeGmi, bytes);
 }
 
 int mdgmi_gmi(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int64_t n, const double* sigma2_host,
               int32_t n_snr, int32_t path, double* out, void* ws, size_t ws_bytes, void* stream) {
-    if (!fmt || !y || !tx_idx || !sigma2_host || !out) return MDGMI_E_NULL;
-    if (n < 1 || n_snr < 1) return MDGMI_E_SHAPE;
-    double max_s = 0.0;
-    for (int q = 0; q < n_snr; q++) {
-        if (!finite_pos(sigma2_host[q])) return MDGMI_E_SIGMA2;
-        max_s = std::max(max_s, s_of(sigma2_host[q]));
-    }
-    int p = 0;
-    int rc = resolve_path(fmt, path, max_s, &p);
-    if (rc != MDGMI_OK) return rc;
-    GmiPlan pl = plan_gmi(fmt, n, n_snr, p);
-    if (!ws || ws_bytes < pl.total) return MDGMI_E_WORKSPACE;
-    rc = check_device(fmt);
-    if (rc != MDGMI_OK) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    double* part = (double*)ws;
-    void* image = (char*)ws + align_up(pl.part_bytes);
-    for (int q0 = 0; q0 < n_snr; q0 += kMaxSnrPerLaunch) {
-        const int cnt = std::min(kMaxSnrPerLaunch, n_snr - q0);
-        SnrArgs sa = snr_args(sigma2_host, q0, cnt);
-        double* pq = part + (size_t)q0 * pl.cfg.blocks_per_snr * kNPart;
-        hipError_t e;
-        if (p == MDGMI_PATH_F64)
-            e = launch_f64(fmt, (const double*)y, tx_idx, n, sa, false, nullptr, pq, pl.cfg, st);
-        else if (p == MDGMI_PATH_F32_DIRECT)
-            e = launch_direct(fmt, (const float*)y, tx_idx, n, sa, false, nullptr, pq, (float*)image, pl.cfg, st);
+    return run_gmi(fmt, y, tx_idx, n, sigma2_host, n_snr, path, kModeGmi, out, ws, ws_bytes, stream);
+}
+
+int mdgmi_gmi_hd_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, int32_t path, size_t* bytes) {
+    return gmi_workspace_size(fmt, n, n_snr, path, kModeHd, bytes);
+}
+
+int mdgmi_gmi_hd(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int64_t n,
+                 const double* sigma2_host, int32_t n_snr, int32_t path, double* out, void* ws, size_t ws_bytes,
+                 void* stream) {
+    return run_gmi(fmt, y, tx_idx, n, sigma2_host, n_snr, path, kModeHd, out, ws, ws_bytes, stream);
+}
+
+double mdgmi_q_factor_db(double ber) {
+    if (!(ber >= 0.0 && ber <= 0.5)) return std::numeric_limits<double>::quiet_NaN();
+    if (ber == 0.0) return std::numeric_limits<double>::infinity();
+    if (ber == 0.5) return -std::numeric_limits<double>::infinity();
+    // erfc^-1(2 ber) by bisection on the decreasing erfc over [0, 28]
+    // (erfc(28) is below the smallest positive double)
+    const double target = 2.0 * ber;
+    double lo = 0.0, hi = 28.0;
+    for (int it = 0; it < 200; it++) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (std::erfc(mid) > target)
+            lo = mid;
         else
-            e = launch_mfma(fmt, (const float*)y, tx_idx, n, sa, false, nullptr, pq, image, pl.cfg, st);
-        if (e != hipSuccess) return MDGMI_E_HIP;
+            hi = mid;
     }
-    hipError_t e = launch_reduce(part, n_snr, pl.cfg.blocks_per_snr, n, fmt->m, out, st);
-    return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+    return 20.0 * std::log10(std::sqrt(2.0) * 0.5 * (lo + hi));
 }
 
 }  // extern "C"

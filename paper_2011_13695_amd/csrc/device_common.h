@@ -137,36 +137,53 @@ struct CostAcc {
         sg2 += cg * cg;
         sm += cm;
         sm2 += cm * cm;
-        bool fin = (cg - cg == 0.0) && (cm - cm == 0.0);  // false for NaN and inf
+        // a class test, not x - x == 0: contraction may turn x - x into
+        // fma(a, b, -x) when x = a * b, which is the product's rounding error
+        const bool fin = __builtin_isfinite(cg) && __builtin_isfinite(cm);
         bad += fin ? 0.0 : 1.0;
     }
 };
 
-// Fixed-order reduction of the five partials over a block; thread 0 writes
-// them to dst[0..4]. The shuffle tree and the per-wave order are fixed, so
-// the result does not depend on scheduling.
-__device__ inline void block_reduce_store(CostAcc a, double* dst) {
-    __shared__ double red[16][kNPart];
-    double v[kNPart] = {a.sg, a.sg2, a.sm, a.sm2, a.bad};
+// Per-lane hard-decision error counts (bits, symbols), kept as doubles.
+struct HdAcc {
+    double be = 0.0, se = 0.0;
+};
+
+// Fixed-order reduction of NP partials over a block; thread 0 writes them to
+// dst[0..NP-1]. The shuffle tree and the per-wave order are fixed, so the
+// result does not depend on scheduling.
+template <int NP>
+__device__ inline void block_reduce_vals(double (&v)[NP], double* dst) {
+    __shared__ double red[16][NP];
 #pragma unroll
-    for (int q = 0; q < kNPart; q++) {
+    for (int q = 0; q < NP; q++) {
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
     }
     int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
 #pragma unroll
-        for (int q = 0; q < kNPart; q++) red[wave][q] = v[q];
+        for (int q = 0; q < NP; q++) red[wave][q] = v[q];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         int nw = (blockDim.x + 63) >> 6;
-        for (int q = 0; q < kNPart; q++) {
+        for (int q = 0; q < NP; q++) {
             double s = 0.0;
             for (int w = 0; w < nw; w++) s += red[w][q];
             dst[q] = s;
         }
     }
+}
+
+__device__ inline void block_reduce_store(CostAcc a, double* dst) {
+    double v[kNPart] = {a.sg, a.sg2, a.sm, a.sm2, a.bad};
+    block_reduce_vals<kNPart>(v, dst);
+}
+
+__device__ inline void block_reduce_store_hd(CostAcc a, HdAcc h, double* dst) {
+    double v[kNPartHd] = {a.sg, a.sg2, a.sm, a.sm2, a.bad, h.be, h.se};
+    block_reduce_vals<kNPartHd>(v, dst);
 }
 
 // Exact per-class evaluation of one sample in FP32, used when a class sum
@@ -178,7 +195,8 @@ __device__ inline void block_reduce_store(CostAcc a, double* dst) {
 //          ltot = log2 sum_j 2^-t_j,  ti = t of slot `sent` (if sent >= 0).
 template <int DIM>
 __device__ inline void exact_classes_f32(const float* yv, const float* __restrict__ X32, int M, int m,
-                                         float s, int sent, float* ls0, float* ls1, float& ltot, float& ti) {
+                                         float s, int sent, float* ls0, float* ls1, float& ltot, float& ti,
+                                         float* tmin_out = nullptr) {
     float cmin0[MDGMI_MAX_BITS], cmin1[MDGMI_MAX_BITS];
     float tmin = INFINITY;
 #pragma unroll
@@ -234,6 +252,7 @@ __device__ inline void exact_classes_f32(const float* yv, const float* __restric
         }
     }
     ltot = lg2(tot) - tmin;
+    if (tmin_out) *tmin_out = tmin;
 }
 
 }  // namespace mdgmi

@@ -42,12 +42,15 @@ __device__ inline void direct_record(const double* __restrict__ X64, int dim, in
 
 // One sample (index i of one (format, SNR) instance) against all M points of
 // the instance's direct image im (records {2 s x_j, s ||x_j||^2}).
-template <int DIM, int CHB, int G, bool LLR>
+// MODE: kModeGmi (costs into acc), kModeLlr (LLRs into llr) or kModeHd
+// (costs and hard-decision error counts into hd).
+template <int DIM, int CHB, int G, int MODE>
 __device__ __forceinline__ void direct_sample(const float* __restrict__ im, const float* __restrict__ ys,
                                               const uint32_t* __restrict__ txs, int64_t i, int M, int m,
                                               float s, const float* __restrict__ X32,
                                               const uint32_t* __restrict__ labels, float* __restrict__ llr,
-                                              CostAcc& acc) {
+                                              CostAcc& acc, HdAcc* hd = nullptr) {
+    constexpr bool LLR = MODE == kModeLlr;
     constexpr int CH = 1 << CHB;
     constexpr int REC = DirectRec<DIM>::value;
     constexpr int MAXHI = MDGMI_MAX_BITS - CHB;
@@ -65,6 +68,7 @@ __device__ __forceinline__ void direct_sample(const float* __restrict__ im, cons
     for (int r = 0; r < CH; r++) bank[r] = 0.0f;
     HiAcc<G, MAXHI> hi;
     hi.zero();
+    float umax = -INFINITY;  // nearest point (hard decisions only)
     for (int c0 = 0; c0 < nchunk; c0 += G) {
         float T[G];
 #pragma unroll
@@ -76,6 +80,7 @@ __device__ __forceinline__ void direct_sample(const float* __restrict__ im, cons
                 float u = K - rc[r * REC + DIM];
 #pragma unroll
                 for (int q = 0; q < DIM; q++) u = fmaf(rc[r * REC + q], yv[q], u);
+                if (MODE == kModeHd) umax = fmaxf(umax, u);
                 ev[r] = ex2(u);
                 bank[r] += ev[r];
             }
@@ -169,9 +174,26 @@ __device__ __forceinline__ void direct_sample(const float* __restrict__ im, cons
                 }
             }
             cm = ltot + ti;
+            // decisions below from the exact per-class logarithms
+#pragma unroll
+            for (int k = 0; k < MDGMI_MAX_BITS; k++) {
+                S0[k] = ls0[k];
+                S1[k] = ls1[k];
+            }
         }
         if (!row_ok) cg = cm = NAN;
         acc.add((double)cg, (double)cm);
+        if (MODE == kModeHd) {
+            // bitwise MAP decisions (S1 > S0 decides 1; log2 sums on the
+            // exact path, same order) and the nearest point
+            int be = 0;
+#pragma unroll
+            for (int k = 0; k < MDGMI_MAX_BITS; k++)
+                if (k < m) be += (S1[k] > S0[k] ? 1 : 0) != (int)((slot >> k) & 1u);
+            const bool finite = cg == cg && cm == cm && ui == ui;
+            hd->be += finite ? (double)be : (double)m;
+            hd->se += (finite && !(umax > ui)) ? 0.0 : 1.0;
+        }
     }
 }
 

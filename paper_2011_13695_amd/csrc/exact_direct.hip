@@ -10,7 +10,7 @@ using namespace direct;
 
 constexpr int kDirectThreads = 256;
 
-template <int DIM, int CHB, int G, bool LLR>
+template <int DIM, int CHB, int G, int MODE>
 __global__ __launch_bounds__(kDirectThreads) void k_direct(
     const float* __restrict__ y, const uint32_t* __restrict__ tx, const float* __restrict__ img,
     const float* __restrict__ X32, const uint32_t* __restrict__ labels, int64_t n, int M, int m, SnrArgs sa,
@@ -21,12 +21,15 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(
     const int64_t snr = sa.snr0 + q_snr;
     const float* __restrict__ im = img + (size_t)q_snr * M * REC;
     const float* ys = y + snr * n * DIM;
-    const uint32_t* txs = LLR ? nullptr : tx + snr * n;
+    const uint32_t* txs = MODE == kModeLlr ? nullptr : tx + snr * n;
     CostAcc acc;
+    HdAcc hd;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        direct_sample<DIM, CHB, G, LLR>(im, ys, txs, i, M, m, s, X32, labels, llr, acc);
-    if (!LLR) block_reduce_store(acc, part + ((int64_t)q_snr * gridDim.x + blockIdx.x) * kNPart);
+        direct_sample<DIM, CHB, G, MODE>(im, ys, txs, i, M, m, s, X32, labels, llr, acc, &hd);
+    double* dst = part + ((int64_t)q_snr * gridDim.x + blockIdx.x) * (MODE == kModeHd ? kNPartHd : kNPart);
+    if (MODE == kModeGmi) block_reduce_store(acc, dst);
+    if (MODE == kModeHd) block_reduce_store_hd(acc, hd, dst);
 }
 
 __global__ void k_direct_image(const double* __restrict__ X64, int M, int dim, int rec, SnrArgs sa,
@@ -40,35 +43,38 @@ __global__ void k_direct_image(const double* __restrict__ X64, int M, int dim, i
 
 template <int DIM, int CHB, int G>
 hipError_t launch_direct_t(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
-                           const SnrArgs& sa, bool llr_mode, float* llr, double* part, float* image,
+                           const SnrArgs& sa, int mode, float* llr, double* part, float* image,
                            LaunchCfg cfg, hipStream_t st) {
     dim3 grid(cfg.blocks_per_snr, sa.n_snr), block(cfg.threads);
-    if (llr_mode)
-        hipLaunchKernelGGL((k_direct<DIM, CHB, G, true>), grid, block, 0, st, y, tx, image, f->d_X32,
+    if (mode == kModeLlr)
+        hipLaunchKernelGGL((k_direct<DIM, CHB, G, kModeLlr>), grid, block, 0, st, y, tx, image, f->d_X32,
+                           f->d_labels, n, f->M, f->m, sa, llr, part);
+    else if (mode == kModeHd)
+        hipLaunchKernelGGL((k_direct<DIM, CHB, G, kModeHd>), grid, block, 0, st, y, tx, image, f->d_X32,
                            f->d_labels, n, f->M, f->m, sa, llr, part);
     else
-        hipLaunchKernelGGL((k_direct<DIM, CHB, G, false>), grid, block, 0, st, y, tx, image, f->d_X32,
+        hipLaunchKernelGGL((k_direct<DIM, CHB, G, kModeGmi>), grid, block, 0, st, y, tx, image, f->d_X32,
                            f->d_labels, n, f->M, f->m, sa, llr, part);
     return hipGetLastError();
 }
 
 template <int DIM>
 hipError_t launch_direct_d(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
-                           const SnrArgs& sa, bool llr_mode, float* llr, double* part, float* image,
+                           const SnrArgs& sa, int mode, float* llr, double* part, float* image,
                            LaunchCfg cfg, hipStream_t st) {
     switch (f->m) {
         case 1:
-            return launch_direct_t<DIM, 1, 1>(f, y, tx, n, sa, llr_mode, llr, part, image, cfg, st);
+            return launch_direct_t<DIM, 1, 1>(f, y, tx, n, sa, mode, llr, part, image, cfg, st);
         case 2:
-            return launch_direct_t<DIM, 2, 1>(f, y, tx, n, sa, llr_mode, llr, part, image, cfg, st);
+            return launch_direct_t<DIM, 2, 1>(f, y, tx, n, sa, mode, llr, part, image, cfg, st);
         case 3:
-            return launch_direct_t<DIM, 3, 1>(f, y, tx, n, sa, llr_mode, llr, part, image, cfg, st);
+            return launch_direct_t<DIM, 3, 1>(f, y, tx, n, sa, mode, llr, part, image, cfg, st);
         case 4:
-            return launch_direct_t<DIM, 4, 1>(f, y, tx, n, sa, llr_mode, llr, part, image, cfg, st);
+            return launch_direct_t<DIM, 4, 1>(f, y, tx, n, sa, mode, llr, part, image, cfg, st);
         case 5:
-            return launch_direct_t<DIM, 4, 2>(f, y, tx, n, sa, llr_mode, llr, part, image, cfg, st);
+            return launch_direct_t<DIM, 4, 2>(f, y, tx, n, sa, mode, llr, part, image, cfg, st);
         default:
-            return launch_direct_t<DIM, 4, 4>(f, y, tx, n, sa, llr_mode, llr, part, image, cfg, st);
+            return launch_direct_t<DIM, 4, 4>(f, y, tx, n, sa, mode, llr, part, image, cfg, st);
     }
 }
 
@@ -90,7 +96,7 @@ LaunchCfg direct_cfg(const mdgmi_format* f, int64_t n) {
 }
 
 hipError_t launch_direct(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
-                         const SnrArgs& sa, bool llr_mode, float* llr, double* part, float* image,
+                         const SnrArgs& sa, int mode, float* llr, double* part, float* image,
                          LaunchCfg cfg, hipStream_t st) {
     int rec = ((f->dim + 1 + 3) / 4) * 4;
     dim3 g((f->M + 255) / 256, sa.n_snr);
@@ -99,11 +105,11 @@ hipError_t launch_direct(const mdgmi_format* f, const float* y, const uint32_t* 
     if (e != hipSuccess) return e;
     switch (f->dim) {
         case 2:
-            return launch_direct_d<2>(f, y, tx, n, sa, llr_mode, llr, part, image, cfg, st);
+            return launch_direct_d<2>(f, y, tx, n, sa, mode, llr, part, image, cfg, st);
         case 4:
-            return launch_direct_d<4>(f, y, tx, n, sa, llr_mode, llr, part, image, cfg, st);
+            return launch_direct_d<4>(f, y, tx, n, sa, mode, llr, part, image, cfg, st);
         case 8:
-            return launch_direct_d<8>(f, y, tx, n, sa, llr_mode, llr, part, image, cfg, st);
+            return launch_direct_d<8>(f, y, tx, n, sa, mode, llr, part, image, cfg, st);
         default:
             return hipErrorInvalidValue;
     }

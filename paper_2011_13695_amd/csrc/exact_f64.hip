@@ -24,7 +24,7 @@ __device__ __forceinline__ double dist2(const double* yv, const double* __restri
     return d;
 }
 
-template <int DIM, bool LLR>
+template <int DIM, int MODE>
 __global__ __launch_bounds__(kF64Threads) void k_exact_f64(const double* __restrict__ y,
                                                            const uint32_t* __restrict__ tx,
                                                            const double* __restrict__ X,
@@ -35,8 +35,10 @@ __global__ __launch_bounds__(kF64Threads) void k_exact_f64(const double* __restr
     const double inv2s2 = sa.inv2s2[q_snr];
     const int64_t snr = sa.snr0 + q_snr;
     const double* ys = y + snr * n * DIM;
+    constexpr bool LLR = MODE == kModeLlr;
     const uint32_t* txs = LLR ? nullptr : tx + snr * n;
     CostAcc acc;
+    HdAcc hd;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         double yv[DIM];
@@ -103,9 +105,27 @@ __global__ __launch_bounds__(kF64Threads) void k_exact_f64(const double* __restr
             double cm = ti - tmin + log(tot);
             if (!row_ok) cg = cm = NAN;
             acc.add(cg * kLog2e, cm * kLog2e);
+            if (MODE == kModeHd) {
+                // bitwise MAP decisions (sign of the LLR) and the nearest
+                // point (some other point strictly nearer than the sent one)
+                int be = 0;
+#pragma unroll
+                for (int k = 0; k < MDGMI_MAX_BITS; k++) {
+                    if (k < m) {
+                        const double lam = (log(S1[k]) - cmin1[k]) - (log(S0[k]) - cmin0[k]);
+                        const int bk = (int)((slot >> k) & 1u);
+                        be += (lam == lam) ? ((lam > 0.0 ? 1 : 0) != bk) : 1;
+                    }
+                }
+                const bool finite = cg == cg && cm == cm;
+                hd.be += finite ? (double)be : (double)m;
+                hd.se += (finite && !(tmin < ti)) ? 0.0 : 1.0;
+            }
         }
     }
-    if (!LLR) block_reduce_store(acc, part + ((int64_t)q_snr * gridDim.x + blockIdx.x) * kNPart);
+    double* dst = part + ((int64_t)q_snr * gridDim.x + blockIdx.x) * (MODE == kModeHd ? kNPartHd : kNPart);
+    if (MODE == kModeGmi) block_reduce_store(acc, dst);
+    if (MODE == kModeHd) block_reduce_store_hd(acc, hd, dst);
 }
 
 }  // namespace
@@ -121,17 +141,20 @@ LaunchCfg f64_cfg(const mdgmi_format* f, int64_t n) {
 }
 
 hipError_t launch_f64(const mdgmi_format* f, const double* y, const uint32_t* tx, int64_t n,
-                      const SnrArgs& sa, bool llr_mode, double* llr, double* part, LaunchCfg cfg,
+                      const SnrArgs& sa, int mode, double* llr, double* part, LaunchCfg cfg,
                       hipStream_t st) {
     dim3 grid(cfg.blocks_per_snr, sa.n_snr), block(cfg.threads);
     // part points at the first block row of this launch's first SNR.
 #define MDGMI_F64_CASE(D)                                                                              \
     case D:                                                                                            \
-        if (llr_mode)                                                                                  \
-            hipLaunchKernelGGL((k_exact_f64<D, true>), grid, block, 0, st, y, tx, f->d_X64,           \
+        if (mode == kModeLlr)                                                                          \
+            hipLaunchKernelGGL((k_exact_f64<D, kModeLlr>), grid, block, 0, st, y, tx, f->d_X64,       \
+                               f->d_labels, n, f->M, f->m, sa, llr, part);                             \
+        else if (mode == kModeHd)                                                                      \
+            hipLaunchKernelGGL((k_exact_f64<D, kModeHd>), grid, block, 0, st, y, tx, f->d_X64,        \
                                f->d_labels, n, f->M, f->m, sa, llr, part);                             \
         else                                                                                           \
-            hipLaunchKernelGGL((k_exact_f64<D, false>), grid, block, 0, st, y, tx, f->d_X64,          \
+            hipLaunchKernelGGL((k_exact_f64<D, kModeGmi>), grid, block, 0, st, y, tx, f->d_X64,       \
                                f->d_labels, n, f->M, f->m, sa, llr, part);                             \
         break;
     switch (f->dim) {

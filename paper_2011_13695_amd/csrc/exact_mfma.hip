@@ -21,7 +21,7 @@ __global__ void k_mfma_image(const double* __restrict__ X64, int M, int ntiles, 
     image_slot<DIM>(X64, M, ntiles, sa.s64[q], slot, img + (size_t)q * ntiles * NB * 64);
 }
 
-template <int DIM, int NCOL, int WAVES, int G, bool LDS_IMG, bool LLR>
+template <int DIM, int NCOL, int WAVES, int G, bool LDS_IMG, int MODE>
 __global__ __launch_bounds__(WAVES * 64) void k_mfma(
     const float* __restrict__ y, const uint32_t* __restrict__ tx, const uint4* __restrict__ img,
     const float* __restrict__ X32, const float* __restrict__ n32, const uint32_t* __restrict__ labels,
@@ -40,13 +40,16 @@ __global__ __launch_bounds__(WAVES * 64) void k_mfma(
     const uint4* A = LDS_IMG ? lds_img : gimg;
     const int wave = threadIdx.x >> 6;
     const float* ys = y + snr * n * DIM;
-    const uint32_t* txs = LLR ? nullptr : tx + snr * n;
+    const uint32_t* txs = MODE == kModeLlr ? nullptr : tx + snr * n;
     CostAcc acc;
+    HdAcc hd;
     const int64_t ncoltiles = (n + 32 * NCOL - 1) / (32 * NCOL);
     for (int64_t ct = (int64_t)blockIdx.x * WAVES + wave; ct < ncoltiles; ct += (int64_t)gridDim.x * WAVES)
-        mfma_coltile<DIM, NCOL, G, LLR>(A, ys, txs, n, ct, M, m, ntiles, s, X32, labels, llr, acc);
+        mfma_coltile<DIM, NCOL, G, MODE>(A, ys, txs, n, ct, M, m, ntiles, s, X32, labels, llr, acc, &hd);
     (void)n32;
-    if (!LLR) block_reduce_store(acc, part + ((int64_t)q_snr * gridDim.x + blockIdx.x) * kNPart);
+    double* dst = part + ((int64_t)q_snr * gridDim.x + blockIdx.x) * (MODE == kModeHd ? kNPartHd : kNPart);
+    if (MODE == kModeGmi) block_reduce_store(acc, dst);
+    if (MODE == kModeHd) block_reduce_store_hd(acc, hd, dst);
 }
 
 
@@ -57,26 +60,50 @@ struct MfmaVariant {
 
 int g_variant_override = -1;  // set through mdgmi_set_tuning for sweeps
 
-template <int DIM, int NCOL, int WAVES, int G, bool LDS>
-hipError_t launch_v(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n, const SnrArgs& sa,
-                    bool llr_mode, float* llr, double* part, const uint4* img, int ntiles, int blocks,
-                    hipStream_t st) {
+template <int DIM, int NCOL, int WAVES, int G, bool LDS, int MODE>
+hipError_t launch_vm(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n, const SnrArgs& sa,
+                     float* llr, double* part, const uint4* img, int ntiles, int blocks, hipStream_t st) {
     constexpr int NB = Blk<DIM>::value;
     dim3 grid(blocks, sa.n_snr), block(WAVES * 64);
     size_t lds = LDS ? (size_t)ntiles * NB * 64 * sizeof(uint4) : 0;
     if (LDS) {
-        auto kfn = llr_mode ? (const void*)k_mfma<DIM, NCOL, WAVES, G, true, true>
-                            : (const void*)k_mfma<DIM, NCOL, WAVES, G, true, false>;
-        hipError_t e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute((const void*)k_mfma<DIM, NCOL, WAVES, G, true, MODE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    if (llr_mode)
-        hipLaunchKernelGGL((k_mfma<DIM, NCOL, WAVES, G, LDS, true>), grid, block, lds, st, y, tx, img, f->d_X32,
-                           f->d_n32, f->d_labels, n, f->M, f->m, ntiles, sa, llr, part);
-    else
-        hipLaunchKernelGGL((k_mfma<DIM, NCOL, WAVES, G, LDS, false>), grid, block, lds, st, y, tx, img, f->d_X32,
-                           f->d_n32, f->d_labels, n, f->M, f->m, ntiles, sa, llr, part);
+    hipLaunchKernelGGL((k_mfma<DIM, NCOL, WAVES, G, LDS, MODE>), grid, block, lds, st, y, tx, img, f->d_X32,
+                       f->d_n32, f->d_labels, n, f->M, f->m, ntiles, sa, llr, part);
     return hipGetLastError();
+}
+
+// GMI and LLR modes in every launch shape; hard decisions only in the
+// 1-column, 16-wave shape (launch_hd).
+template <int DIM, int NCOL, int WAVES, int G, bool LDS>
+hipError_t launch_v(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n, const SnrArgs& sa,
+                    int mode, float* llr, double* part, const uint4* img, int ntiles, int blocks,
+                    hipStream_t st) {
+    if (mode == kModeLlr)
+        return launch_vm<DIM, NCOL, WAVES, G, LDS, kModeLlr>(f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
+    return launch_vm<DIM, NCOL, WAVES, G, LDS, kModeGmi>(f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
+}
+
+template <int DIM>
+hipError_t launch_hd(bool lds, const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
+                     const SnrArgs& sa, double* part, const uint4* img, int ntiles, int blocks, hipStream_t st) {
+#define MDGMI_HD_G(G)                                                                                        \
+    return lds ? launch_vm<DIM, 1, 16, G, true, kModeHd>(f, y, tx, n, sa, nullptr, part, img, ntiles, blocks, \
+                                                          st)                                                 \
+               : launch_vm<DIM, 1, 16, G, false, kModeHd>(f, y, tx, n, sa, nullptr, part, img, ntiles, blocks, st);
+    if (ntiles >= 8) {
+        MDGMI_HD_G(8)
+    } else if (ntiles == 4) {
+        MDGMI_HD_G(4)
+    } else if (ntiles == 2) {
+        MDGMI_HD_G(2)
+    } else {
+        MDGMI_HD_G(1)
+    }
+#undef MDGMI_HD_G
 }
 
 // Variants (sample columns per wave, waves per block, A image in LDS):
@@ -85,11 +112,11 @@ hipError_t launch_v(const mdgmi_format* f, const float* y, const uint32_t* tx, i
 // L2.
 template <int DIM>
 hipError_t launch_d(int var, bool lds, const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
-                    const SnrArgs& sa, bool llr_mode, float* llr, double* part, const uint4* img, int ntiles,
+                    const SnrArgs& sa, int mode, float* llr, double* part, const uint4* img, int ntiles,
                     int blocks, hipStream_t st) {
 #define MDGMI_VG(NC, W, G)                                                                                  \
-    return lds ? launch_v<DIM, NC, W, G, true>(f, y, tx, n, sa, llr_mode, llr, part, img, ntiles, blocks, st) \
-               : launch_v<DIM, NC, W, G, false>(f, y, tx, n, sa, llr_mode, llr, part, img, ntiles, blocks, st);
+    return lds ? launch_v<DIM, NC, W, G, true>(f, y, tx, n, sa, mode, llr, part, img, ntiles, blocks, st) \
+               : launch_v<DIM, NC, W, G, false>(f, y, tx, n, sa, mode, llr, part, img, ntiles, blocks, st);
 #define MDGMI_V(NC, W)             \
     if (ntiles >= 8) {             \
         MDGMI_VG(NC, W, 8)         \
@@ -150,8 +177,10 @@ bool mfma_supported(const mdgmi_format* f, double max_s) {
 
 size_t mfma_image_bytes(const mdgmi_format* f, int n_snr) { return (size_t)n_snr * image_bytes_per_snr(f); }
 
-LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr) {
-    const MfmaVariant& v = kVariants[pick_variant(f)];
+LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr, int mode) {
+    // hard decisions run the 1-column, 16-wave shape only (LDS image if it fits)
+    const int var = mode == kModeHd ? (image_bytes_per_snr(f) <= 128 * 1024 ? 4 : 6) : pick_variant(f);
+    const MfmaVariant& v = kVariants[var];
     const int64_t cols = 32 * v.ncol;
     const int64_t tiles = (n + cols - 1) / cols;
     const int64_t want = (tiles + v.waves - 1) / v.waves;
@@ -172,7 +201,7 @@ LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr) {
 }
 
 hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
-                       const SnrArgs& sa, bool llr_mode, float* llr, double* part, void* image,
+                       const SnrArgs& sa, int mode, float* llr, double* part, void* image,
                        LaunchCfg cfg, hipStream_t st) {
     const int ntiles = (f->M + 31) / 32;
     uint4* img = (uint4*)image;
@@ -194,13 +223,24 @@ hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx
     if (e != hipSuccess) return e;
     const int var = pick_variant(f);
     const bool lds = kVariants[var].lds && image_bytes_per_snr(f) <= 128 * 1024;
+    if (mode == kModeHd) {
+        const bool hd_lds = image_bytes_per_snr(f) <= 128 * 1024;
+        switch (f->dim) {
+            case 2:
+                return launch_hd<2>(hd_lds, f, y, tx, n, sa, part, img, ntiles, cfg.blocks_per_snr, st);
+            case 4:
+                return launch_hd<4>(hd_lds, f, y, tx, n, sa, part, img, ntiles, cfg.blocks_per_snr, st);
+            default:
+                return launch_hd<8>(hd_lds, f, y, tx, n, sa, part, img, ntiles, cfg.blocks_per_snr, st);
+        }
+    }
     switch (f->dim) {
         case 2:
-            return launch_d<2>(var, lds, f, y, tx, n, sa, llr_mode, llr, part, img, ntiles, cfg.blocks_per_snr, st);
+            return launch_d<2>(var, lds, f, y, tx, n, sa, mode, llr, part, img, ntiles, cfg.blocks_per_snr, st);
         case 4:
-            return launch_d<4>(var, lds, f, y, tx, n, sa, llr_mode, llr, part, img, ntiles, cfg.blocks_per_snr, st);
+            return launch_d<4>(var, lds, f, y, tx, n, sa, mode, llr, part, img, ntiles, cfg.blocks_per_snr, st);
         default:
-            return launch_d<8>(var, lds, f, y, tx, n, sa, llr_mode, llr, part, img, ntiles, cfg.blocks_per_snr, st);
+            return launch_d<8>(var, lds, f, y, tx, n, sa, mode, llr, part, img, ntiles, cfg.blocks_per_snr, st);
     }
 }
 

@@ -26,6 +26,10 @@ namespace mdgmi {
 
 constexpr int kMfmaVariants = 8;     // MFMA launch shapes (see mdgmi_set_tuning)
 constexpr int kNPart = 5;           // per-block FP64 partials: sum cG, sum cG^2, sum cM, sum cM^2, nonfinite
+constexpr int kNPartHd = kNPart + 2; // ... and, with hard decisions, bit errors and symbol errors
+// What a demapper launch produces: GMI/MI partials, LLRs, or GMI/MI partials
+// with hard-decision error counts.
+constexpr int kModeGmi = 0, kModeLlr = 1, kModeHd = 2;
 constexpr int kMaxSnrPerLaunch = 32;
 // Exponents are taken relative to a fixed offset: e_j = 2^(kBias - t_j) with
 // t_j = ||y - x_j||^2 / (2 sigma2) * log2(e) >= 0, so no term can overflow
@@ -55,24 +59,24 @@ hipError_t launch_generate(const mdgmi_format* f, uint64_t seed, const double* s
 
 LaunchCfg f64_cfg(const mdgmi_format* f, int64_t n);
 hipError_t launch_f64(const mdgmi_format* f, const double* y, const uint32_t* tx, int64_t n,
-                      const SnrArgs& sa, bool llr_mode, double* llr, double* part, LaunchCfg cfg,
+                      const SnrArgs& sa, int mode, double* llr, double* part, LaunchCfg cfg,
                       hipStream_t st);
 
 LaunchCfg direct_cfg(const mdgmi_format* f, int64_t n);
 size_t direct_image_bytes(const mdgmi_format* f, int n_snr);
 hipError_t launch_direct(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
-                         const SnrArgs& sa, bool llr_mode, float* llr, double* part, float* image,
+                         const SnrArgs& sa, int mode, float* llr, double* part, float* image,
                          LaunchCfg cfg, hipStream_t st);
 
 bool mfma_supported(const mdgmi_format* f, double max_s);
-LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr);
+LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr, int mode = kModeGmi);
 size_t mfma_image_bytes(const mdgmi_format* f, int n_snr);
 hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
-                       const SnrArgs& sa, bool llr_mode, float* llr, double* part, void* image,
+                       const SnrArgs& sa, int mode, float* llr, double* part, void* image,
                        LaunchCfg cfg, hipStream_t st);
 
 hipError_t launch_reduce(const double* part, int n_snr, int blocks_per_snr, int64_t n, int m,
-                         double* out, hipStream_t st);
+                         double* out, hipStream_t st, bool hd = false);
 
 int device_cu_count();
 

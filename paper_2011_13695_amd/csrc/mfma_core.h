@@ -242,10 +242,10 @@ __device__ __forceinline__ f32x16 tile_mfma(const half8* a, const half8* b) {
 // t + 2 past the group are the first two of the next group). CLAMP caps each
 // exponent at 110 so that sums of up to 2^12 terms stay finite when the
 // offset has been raised for far classes (only those classes are read then).
-template <int DIM, int NCOL, int G, bool CLAMP, int MAXHI>
+template <int DIM, int NCOL, int G, bool CLAMP, int MAXHI, bool TRACK = false>
 __device__ __forceinline__ void tile_loop(const uint4* __restrict__ A, int ntiles, int h, int col,
                                           const half8 (&bop)[NCOL][Blk<DIM>::value], float (&bank)[NCOL][16],
-                                          HiAcc<G, MAXHI> (&hi)[NCOL]) {
+                                          HiAcc<G, MAXHI> (&hi)[NCOL], float* umax = nullptr) {
     constexpr int NB = Blk<DIM>::value;
     constexpr int TS = NB * 64;  // uint4 per tile of the image
 #pragma unroll
@@ -253,6 +253,7 @@ __device__ __forceinline__ void tile_loop(const uint4* __restrict__ A, int ntile
 #pragma unroll
         for (int r = 0; r < 16; r++) bank[c][r] = 0.0f;
         hi[c].zero();
+        if (TRACK) umax[c] = -INFINITY;
     }
     const int tmask = ntiles - 1;
     const uint4* __restrict__ Al = A + h * 32 + col;
@@ -282,6 +283,14 @@ __device__ __forceinline__ void tile_loop(const uint4* __restrict__ A, int ntile
                 load_a_at<NB>(Anxt + (i + 2 - G) * TS, a_nxt);
 #pragma unroll
             for (int c = 0; c < NCOL; c++) {
+                if (TRACK) {
+                    // largest u of the tile (nearest point), a tree of 3-input maxima
+                    const f32x16& u = u_cur[c];
+                    const float a = fmaxf(fmaxf(u[0], u[1]), u[2]), b = fmaxf(fmaxf(u[3], u[4]), u[5]);
+                    const float d = fmaxf(fmaxf(u[6], u[7]), u[8]), e = fmaxf(fmaxf(u[9], u[10]), u[11]);
+                    const float g = fmaxf(fmaxf(u[12], u[13]), u[14]), q = fmaxf(fmaxf(u[15], a), b);
+                    umax[c] = fmaxf(fmaxf(umax[c], q), fmaxf(fmaxf(d, e), g));
+                }
                 float ev[16];
 #pragma unroll
                 for (int r = 0; r < 16; r++) {
@@ -440,12 +449,14 @@ __device__ __forceinline__ void llr_far_pass(const uint4* __restrict__ A, const 
 // (format, SNR) instance, against all points of its A image. Costs go to
 // acc (GMI mode) or LLRs to llr (LLR mode). All 64 lanes of the wave must
 // call it together (the MFMA and the half-wave swaps need every lane).
-template <int DIM, int NCOL, int G, bool LLR>
+template <int DIM, int NCOL, int G, int MODE>
 __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const float* __restrict__ ys,
                                              const uint32_t* __restrict__ txs, int64_t n, int64_t ct, int M,
                                              int m, int ntiles, float s, const float* __restrict__ X32,
                                              const uint32_t* __restrict__ labels, float* __restrict__ llr,
-                                             CostAcc& acc) {
+                                             CostAcc& acc, HdAcc* hd = nullptr) {
+    constexpr bool LLR = MODE == kModeLlr;
+    constexpr bool HD = MODE == kModeHd;
     constexpr int NB = Blk<DIM>::value;
     constexpr int MAXHI = MDGMI_MAX_BITS - 5;
     constexpr int TS = NB * 64;
@@ -468,7 +479,8 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
     }
     float bank[NCOL][16];
     HiAcc<G, MAXHI> hi[NCOL];
-    tile_loop<DIM, NCOL, G, false, MAXHI>(A, ntiles, h, col, bop, bank, hi);
+    float umax[NCOL];
+    tile_loop<DIM, NCOL, G, false, MAXHI, HD>(A, ntiles, h, col, bop, bank, hi, umax);
     // ---- epilogue ----
     // Each lane folds its own 16 rows into per-bit partial class sums; the
     // two lane halves (rows differing in label bit 2) are combined with one
@@ -538,7 +550,7 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
         for (int r = 0; r < 16; r++) dv = (r == q) ? ud[r] : dv;
         const Halves d = halves(dv);
         const float ui = ((col >> 2) & 1) ? d.hi : d.lo;
-        float cg = 0.0f;
+        float cg = 0.0f, be = 0.0f;
 #pragma unroll
         for (int j = 0; j < (MDGMI_MAX_BITS + 1) / 2; j++) {
             if (2 * j < m) {  // uniform
@@ -557,32 +569,49 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
                     // log2(1 + S_other / S_sent) = log2((S0 + S1) / S_sent)
                     const bool bk = (slot >> k) & 1;
                     cg += bit_cost_sum2(s0 + s1, bk ? s1 : s0);
+                    if (HD) be += (s1 > s0) != bk ? 1.0f : 0.0f;  // bitwise MAP decision
                 }
             }
         }
         cg = half_sum(cg);
+        float sym = 0.0f;
+        if (HD) {
+            be = half_sum(be);
+            const Halves um = halves(umax[c]);
+            sym = fmaxf(um.lo, um.hi) > ui ? 1.0f : 0.0f;  // another point strictly nearer
+        }
         if (h != 0 || i >= n) continue;
         float cm;
         if (ui >= kFarLog2) {
             cm = mi_cost2(tot, ui);
         } else {
             // the sent point itself is far from y (or y is not finite)
-            float yc[DIM], ls0[MDGMI_MAX_BITS], ls1[MDGMI_MAX_BITS], ltot, ti = 0.0f;
+            float yc[DIM], ls0[MDGMI_MAX_BITS], ls1[MDGMI_MAX_BITS], ltot, ti = 0.0f, tmin = 0.0f;
 #pragma unroll
             for (int dd = 0; dd < DIM; dd++) yc[dd] = ys[i * DIM + dd];
-            exact_classes_f32<DIM>(yc, X32, M, m, s, (int)slot, ls0, ls1, ltot, ti);
+            exact_classes_f32<DIM>(yc, X32, M, m, s, (int)slot, ls0, ls1, ltot, ti, HD ? &tmin : nullptr);
             cg = 0.0f;
+            be = 0.0f;
+            // the split factors may be out of range here: decide the symbol
+            // from the FP32 distances as well
+            if (HD) sym = tmin < ti ? 1.0f : 0.0f;
 #pragma unroll
             for (int k = 0; k < MDGMI_MAX_BITS; k++) {
                 if (k < m) {
                     const bool bk = (slot >> k) & 1;
                     cg += bit_cost2(bk ? ls0[k] - ls1[k] : ls1[k] - ls0[k]);
+                    if (HD) be += (ls1[k] > ls0[k]) != bk ? 1.0f : 0.0f;  // from the exact logarithms
                 }
             }
             cm = ltot + ti;
         }
         if (!row_ok) cg = cm = NAN;
         acc.add((double)cg, (double)cm);
+        if (HD) {
+            const bool finite = cg == cg && cm == cm && ui == ui;
+            hd->be += finite ? (double)be : (double)m;
+            hd->se += finite ? (double)sym : 1.0;
+        }
     }
 }
 

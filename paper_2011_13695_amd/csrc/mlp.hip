@@ -551,7 +551,7 @@ __global__ __launch_bounds__(256) void k_learned_cost(const float* __restrict__ 
         const double d = (double)c;
         s += d;
         s2 += d * d;
-        bad += (d - d == 0.0) ? 0.0 : 1.0;
+        bad += __builtin_isfinite(d) ? 0.0 : 1.0;
     }
     CostAcc a;
     a.sg = s;

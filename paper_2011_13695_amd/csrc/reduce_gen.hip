@@ -8,27 +8,23 @@ namespace {
 
 // One block per SNR point; every thread sums a fixed strided subset of the
 // block partials, then a fixed shuffle tree and a fixed per-wave order.
+template <bool HD>
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part, int blocks_per_snr, int64_t n,
                                                 int m, double* __restrict__ out) {
+    constexpr int NP = HD ? kNPartHd : kNPart;
     const int q = blockIdx.x;
-    const double* p = part + (size_t)q * blocks_per_snr * kNPart;
-    double v[kNPart] = {0, 0, 0, 0, 0};
+    const double* p = part + (size_t)q * blocks_per_snr * NP;
+    double v[NP] = {};
     for (int b = threadIdx.x; b < blocks_per_snr; b += blockDim.x) {
 #pragma unroll
-        for (int k = 0; k < kNPart; k++) v[k] += p[(size_t)b * kNPart + k];
+        for (int k = 0; k < NP; k++) v[k] += p[(size_t)b * NP + k];
     }
-    CostAcc a;
-    a.sg = v[0];
-    a.sg2 = v[1];
-    a.sm = v[2];
-    a.sm2 = v[3];
-    a.bad = v[4];
-    __shared__ double tot[kNPart];
-    block_reduce_store(a, tot);
+    __shared__ double tot[NP];
+    block_reduce_vals<NP>(v, tot);
     __syncthreads();
     if (threadIdx.x == 0) {
         const double N = (double)n;
-        double* o = out + (size_t)q * MDGMI_NFIELDS;
+        double* o = out + (size_t)q * (HD ? MDGMI_NFIELDS_HD : MDGMI_NFIELDS);
         o[MDGMI_F_GMI] = m - tot[0] / N;
         o[MDGMI_F_MI] = m - tot[2] / N;
         double vg = n > 1 ? (tot[1] - tot[0] * tot[0] / N) / (N - 1.0) : 0.0;
@@ -37,6 +33,10 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part,
         o[MDGMI_F_SE_MI] = sqrt(fmax(vm, 0.0) / N);
         o[MDGMI_F_N] = N;
         o[MDGMI_F_NONFINITE] = tot[4];
+        if (HD) {
+            o[MDGMI_F_BER] = tot[5] / (N * m);
+            o[MDGMI_F_SER] = tot[6] / N;
+        }
     }
 }
 
@@ -111,8 +111,11 @@ __global__ __launch_bounds__(256) void k_generate(const double* __restrict__ X64
 }  // namespace
 
 hipError_t launch_reduce(const double* part, int n_snr, int blocks_per_snr, int64_t n, int m, double* out,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce, dim3(n_snr), dim3(256), 0, st, part, blocks_per_snr, n, m, out);
+                         hipStream_t st, bool hd) {
+    if (hd)
+        hipLaunchKernelGGL(k_reduce<true>, dim3(n_snr), dim3(256), 0, st, part, blocks_per_snr, n, m, out);
+    else
+        hipLaunchKernelGGL(k_reduce<false>, dim3(n_snr), dim3(256), 0, st, part, blocks_per_snr, n, m, out);
     return hipGetLastError();
 }
 

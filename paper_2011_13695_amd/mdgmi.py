@@ -36,6 +36,8 @@ PATHS = {"f64": MDGMI_PATH_F64, "direct": MDGMI_PATH_F32_DIRECT,
 
 MDGMI_NFIELDS = 6
 FIELDS = ("gmi", "mi", "se_gmi", "se_mi", "n", "n_nonfinite")
+MDGMI_NFIELDS_HD = 8
+FIELDS_HD = FIELDS + ("ber", "ser")
 
 
 class MdgmiError(RuntimeError):
@@ -68,6 +70,10 @@ def lib():
                                                ctypes.POINTER(ctypes.c_size_t)]
         L.mdgmi_gmi.argtypes = [_P, _P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int32, _P, _P,
                                 ctypes.c_size_t, _P]
+        L.mdgmi_gmi_hd_workspace_size.argtypes = L.mdgmi_gmi_workspace_size.argtypes
+        L.mdgmi_gmi_hd.argtypes = L.mdgmi_gmi.argtypes
+        L.mdgmi_q_factor_db.restype = ctypes.c_double
+        L.mdgmi_q_factor_db.argtypes = [ctypes.c_double]
         L.mdgmi_set_tuning.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
@@ -211,6 +217,36 @@ def mdgmi_gmi(fmt: Format, y, tx_idx, sigma2, path="auto", out=None, ws=None, st
     _check("mdgmi_gmi", lib().mdgmi_gmi(fmt.handle, _dptr(y), _dptr(tx_idx), n, s2.ctypes.data_as(_P), n_snr, p,
                                         _dptr(out), _dptr(ws), ws.numel(), _stream(stream)))
     return out
+
+
+def mdgmi_gmi_hd_workspace_size(fmt: Format, n: int, n_snr: int, path="auto") -> int:
+    b = ctypes.c_size_t()
+    _check("mdgmi_gmi_hd_workspace_size",
+           lib().mdgmi_gmi_hd_workspace_size(fmt.handle, n, n_snr, _path(path), ctypes.byref(b)))
+    return int(b.value)
+
+
+def mdgmi_gmi_hd(fmt: Format, y, tx_idx, sigma2, path="auto", out=None, ws=None, stream=None):
+    """GMI/MI plus hard-decision BER and SER per SNR -> out [n_snr, 8] (double)."""
+    import torch
+    s2 = np.ascontiguousarray(np.atleast_1d(sigma2), dtype=np.float64)
+    n_snr = s2.size
+    assert y.is_cuda and y.is_contiguous() and tx_idx.is_contiguous()
+    n = y.numel() // (fmt.dim * n_snr)
+    assert y.numel() == n_snr * n * fmt.dim and tx_idx.numel() == n_snr * n
+    p = _path(path)
+    if out is None:
+        out = torch.empty((n_snr, MDGMI_NFIELDS_HD), dtype=torch.float64, device=y.device)
+    if ws is None:
+        ws = workspace(mdgmi_gmi_hd_workspace_size(fmt, n, n_snr, p))
+    _check("mdgmi_gmi_hd", lib().mdgmi_gmi_hd(fmt.handle, _dptr(y), _dptr(tx_idx), n, s2.ctypes.data_as(_P), n_snr,
+                                              p, _dptr(out), _dptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def mdgmi_q_factor_db(ber: float) -> float:
+    """Q-factor (dB) of a bit error rate under the Gaussian-noise conversion."""
+    return float(lib().mdgmi_q_factor_db(float(ber)))
 
 
 # ------------------------------------------------------------------ batches
