@@ -10,6 +10,7 @@ GMI, MI and LLR only in its glossary): see the header of oracle.c.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from pathlib import Path
@@ -46,6 +47,7 @@ def lib():
         L.oracle_gmi.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, P, P, ctypes.c_int,
                                  ctypes.c_double, P]
         L.oracle_hd.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_double, P]
+        L.oracle_llr_maxlog.argtypes = [P, ctypes.c_int64, ctypes.c_int, P, P, ctypes.c_int, ctypes.c_double, P]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -206,3 +208,68 @@ def gmi_cost_from_llr(llr, sent_label):
     out = np.empty(llr.shape[0])
     _mlp_sigs().oracle_gmi_cost_from_llr(_ptr(llr), _ptr(lab), llr.shape[0], llr.shape[1], _ptr(out))
     return out
+
+
+# ------------------------------------------------- max-log LLRs, GMI(s), s-opt
+def llr_maxlog(y, X, labels, sigma2):
+    """Max-log LLRs in nats, shape (n, m): per bit, the squared distance to
+    the nearest point labelled 0 minus that to the nearest point labelled 1,
+    over 2 sigma2."""
+    X = _c(X, np.float64)
+    M, dim = X.shape
+    m = int(M).bit_length() - 1
+    y = _c(np.reshape(y, (-1, dim)), np.float64)
+    lab = _c(labels, np.uint32)
+    out = np.empty((y.shape[0], m), dtype=np.float64)
+    rc = lib().oracle_llr_maxlog(_ptr(y), y.shape[0], dim, _ptr(X), _ptr(lab), M, float(sigma2), _ptr(out))
+    if rc != 0:
+        raise RuntimeError(f"oracle_llr_maxlog failed ({rc})")
+    return out
+
+
+def gmi_s(llr, sent_label, s):
+    """(GMI(s), its standard error) in bits of a bit-metric decoder that uses
+    the given LLRs scaled by s >= 0:
+        GMI(s) = m - mean_i sum_k log2(1 + exp(-s (2 b_k(i) - 1) lambda_k(i))).
+    s = 1 is the GMI of the LLRs as they are; for the exact LLRs of the
+    channel it is also the maximum over s."""
+    llr = _c(llr, np.float64)
+    n, m = llr.shape
+    c = gmi_cost_from_llr(float(s) * llr, sent_label)
+    se = float(np.std(c, ddof=1) / np.sqrt(n)) if n > 1 else 0.0
+    return float(m - np.mean(c)), se
+
+
+GOLDEN = (math.sqrt(5.0) - 1.0) / 2.0
+
+
+def gmi_sopt(llr, sent_label, iters=120):
+    """(s*, GMI(s*), SE at s*): the s-optimised GMI, max over s >= 0 of
+    gmi_s. Every cost term log(1 + e^{-s v}) is convex in s, so GMI(s) is
+    concave and a golden-section search finds the maximum: first an upper
+    end s_hi, doubled from 1 until GMI(s_hi) no longer exceeds GMI(s_hi / 2),
+    then the search on [0, s_hi]."""
+    f = lambda s: gmi_s(llr, sent_label, s)[0]   # noqa: E731
+    hi = 1.0
+    while f(2.0 * hi) > f(hi) and hi < 2.0 ** 40:
+        hi *= 2.0
+    hi *= 2.0
+    lo = 0.0
+    a = hi - GOLDEN * (hi - lo)
+    b = lo + GOLDEN * (hi - lo)
+    fa, fb = f(a), f(b)
+    for _ in range(iters):
+        if fa < fb:
+            lo, a, fa = a, b, fb
+            b = lo + GOLDEN * (hi - lo)
+            fb = f(b)
+        else:
+            hi, b, fb = b, a, fa
+            a = hi - GOLDEN * (hi - lo)
+            fa = f(a)
+    s = 0.5 * (lo + hi)
+    g, se = gmi_s(llr, sent_label, s)
+    if f(0.0) >= g:       # non-informative LLRs: the maximum is at s = 0
+        s = 0.0
+        g, se = gmi_s(llr, sent_label, 0.0)
+    return s, g, se

@@ -225,6 +225,44 @@ int oracle_gmi(const double* y, const uint32_t* tx_idx, int64_t n, int dim, cons
 }
 
 /* ------------------------------------------------------------------------
+ * Max-log LLRs (FP64). Each class log-sum-exp is replaced by its largest
+ * term, ln sum_{j in C} e^{-t_j} ~ -min_{j in C} t_j (the error lies in
+ * [0, ln |C|]):
+ *   lambda_k^ML(y) = min_{j: b_k(j)=0} t_j - min_{j: b_k(j)=1} t_j   (nats)
+ * i.e. the difference of the squared distances from y to the nearest point
+ * of each class, over 2 sigma2.
+ * ---------------------------------------------------------------------- */
+static double class_min(const double* t, const uint32_t* labels, int M, int k, int b) {
+    double mn = INFINITY;
+    for (int j = 0; j < M; j++)
+        if ((int)((labels[j] >> k) & 1u) == b && t[j] < mn) mn = t[j];
+    return mn;
+}
+
+int oracle_llr_maxlog(const double* y, int64_t n, int dim, const double* X, const uint32_t* labels,
+                      int M, double sigma2, double* llr) {
+    int m = log2_exact(M);
+    int err = 0;
+#pragma omp parallel
+    {
+        double* t = (double*)malloc(sizeof(double) * (size_t)M);
+        if (!t) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+#pragma omp for schedule(static)
+            for (int64_t s = 0; s < n; s++) {
+                metrics(y + s * dim, X, M, dim, sigma2, t);
+                for (int k = 0; k < m; k++)
+                    llr[s * m + k] = class_min(t, labels, M, k, 0) - class_min(t, labels, M, k, 1);
+            }
+            free(t);
+        }
+    }
+    return err ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------
  * Hard decisions (FP64). Two decisions per received sample:
  *   bitwise MAP   b_hat_k = 1 if lambda_k > 0, else 0   (the sign of the
  *                 exact LLR: the hard decision of bit-metric decoding)
