@@ -76,6 +76,7 @@ def parse():
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch leg")
     ap.add_argument("--no-llr", action="store_true", help="skip timing the LLR-output mode")
     ap.add_argument("--no-hd", action="store_true", help="skip the hard-decision (BER/SER/Q) leg")
+    ap.add_argument("--no-maxlog", action="store_true", help="skip the max-log / s-optimised GMI leg")
     ap.add_argument("--ragged-scale", type=float, default=1.0, help="scale of the ragged sample counts")
     ap.add_argument("--copy-probe", type=float, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration) and exit")
@@ -224,6 +225,60 @@ def hd_leg(gf, wl, y, tx, path, gmi_out, reps=3):
             "snr_db_at_q_8.4dB": q_crossing(snr, q_db, 8.4), "snr_db_at_q_5.7dB": q_crossing(snr, q_db, 5.7),
             "max_abs_dgmi_vs_timed_path": float(np.abs(h[:, :2] - gmi_out[:, :2]).max()),
             "note": "mdgmi_gmi_hd: GMI/MI plus BER/SER in one pass; Q = 20 log10(sqrt(2) erfc^-1(2 BER))"}
+
+
+def maxlog_leg(gf, wl, y, tx, path, gmi_out, exact_ms, reps=3):
+    """Max-log metrics on the timed workload: the GMI of max-log LLRs in one
+    launch (timed), and per SNR point the s-optimised GMI of the exact and of
+    the max-log LLRs (mdgmi_llr / mdgmi_llr_maxlog, then mdgmi_gmi_sopt)."""
+    import numpy as np
+    import torch
+    from paper_2011_13695_amd import mdgmi
+
+    n_snr = len(wl.sigma2)
+    pairs = n_snr * wl.n * gf.M
+    ws = mdgmi.workspace(mdgmi.mdgmi_gmi_workspace_size(gf, wl.n, n_snr, path))
+    out = torch.empty((n_snr, mdgmi.MDGMI_NFIELDS), dtype=torch.float64, device="cuda")
+    mdgmi.mdgmi_gmi_maxlog(gf, y, tx, wl.sigma2, path=path, out=out, ws=ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        mdgmi.mdgmi_gmi_maxlog(gf, y, tx, wl.sigma2, path=path, out=out, ws=ws)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    ml = out.cpu().numpy()
+    del ws
+    lam = torch.empty((wl.n, gf.m), dtype=torch.float32, device="cuda")
+    lws = mdgmi.workspace(mdgmi.mdgmi_llr_workspace_size(gf, wl.n, path))
+    sws = mdgmi.workspace(mdgmi.mdgmi_gmi_sopt_workspace_size(wl.n))
+    sout = torch.empty(mdgmi.MDGMI_NFIELDS_S, dtype=torch.float64, device="cuda")
+    rows = {"exact": [], "maxlog": []}
+    sopt_ms = []
+    for q in range(n_snr):
+        for name, fn in (("exact", mdgmi.mdgmi_llr), ("maxlog", mdgmi.mdgmi_llr_maxlog)):
+            fn(gf, y[q], float(wl.sigma2[q]), path=path, llr=lam, ws=lws)
+            a.record(stream)
+            mdgmi.mdgmi_gmi_sopt(gf, lam, tx[q], out=sout, ws=sws)
+            b.record(stream)
+            torch.cuda.synchronize()
+            sopt_ms.append(a.elapsed_time(b))
+            rows[name].append(sout.cpu().numpy().copy())
+    del lam, lws, sws
+    ex = np.array(rows["exact"])
+    mx = np.array(rows["maxlog"])
+    return {"ms_per_call": ms, "value": pairs / (ms * 1e-3), "speedup_vs_exact_gmi": exact_ms / ms,
+            "gmi_maxlog_s1": [float(v) for v in ml[:, 0]],
+            "gmi_exact_minus_maxlog_s1": [float(v) for v in gmi_out[:, 0] - ml[:, 0]],
+            "s_opt_exact": [float(v) for v in ex[:, 2]], "gmi_sopt_exact": [float(v) for v in ex[:, 3]],
+            "s_opt_maxlog": [float(v) for v in mx[:, 2]], "gmi_sopt_maxlog": [float(v) for v in mx[:, 3]],
+            "ngmi_sopt_exact": [float(v) for v in ex[:, 5]],
+            "sopt_passes_max": int(max(ex[:, 8].max(), mx[:, 8].max())),
+            "sopt_ms_per_snr_point": float(np.mean(sopt_ms)),
+            "note": "mdgmi_gmi_maxlog over all SNR points in one launch (timed); s-optimised GMI of the exact "
+                    "and max-log LLRs per SNR point via mdgmi_gmi_sopt (1e7 x 11 LLRs each)"}
 
 
 def ragged_leg(args, log, scale=None):
@@ -375,6 +430,8 @@ def main():
         del lam, lws
     if not args.no_hd:
         extra["hard_decisions"] = hd_leg(gf, wl, y, tx, args.path, out)
+    if not args.no_maxlog:
+        extra["maxlog_sopt"] = maxlog_leg(gf, wl, y, tx, args.path, out, ms_per_step)
     achieved = pairs / (kernel_ms * 1e-3)
     line = {
         "metric": METRIC,

@@ -165,6 +165,55 @@ int mdgmi_gmi_hd(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx,
                  const double* sigma2_host, int32_t n_snr, int32_t path, double* out, void* ws,
                  size_t ws_bytes, void* stream);
 
+/* Max-log metrics. Each class log-sum-exp in the LLR is replaced by its
+ * largest term (the usual low-complexity demapper; the paper names GMI and
+ * LLRs only in its glossary, so this is the standard approximation):
+ *   lambda_k^ML(y) = (min_{j: b_k(j)=0} ||y - x_j||^2
+ *                     - min_{j: b_k(j)=1} ||y - x_j||^2) / (2 sigma2)  (nats)
+ * mdgmi_llr_maxlog: as mdgmi_llr (same layout, paths, workspace size from
+ *   mdgmi_llr_workspace_size), max-log LLRs instead of exact ones.
+ * mdgmi_gmi_maxlog: as mdgmi_gmi (same workspace size), the GMI of the
+ *   max-log LLRs at s = 1 with its standard error; MDGMI_F_MI and
+ *   MDGMI_F_SE_MI are NaN (max-log metrics define no MI).
+ * A sample whose nearest point is far outside the common exponent window
+ * (or whose y is not finite) is evaluated from FP32 distances; non-finite
+ * samples give NaN LLRs / are counted in MDGMI_F_NONFINITE. */
+int mdgmi_llr_maxlog(const mdgmi_format* fmt, const void* y, int64_t n, double sigma2, void* llr,
+                     int32_t path, void* ws, size_t ws_bytes, void* stream);
+int mdgmi_gmi_maxlog(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int64_t n,
+                     const double* sigma2_host, int32_t n_snr, int32_t path, double* out, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* s-optimised GMI and NGMI of given LLRs (any demapper: exact, max-log or
+ * learned). With v_ik = (2 b_k(i) - 1) lambda_ik for the sent bits,
+ *   GMI(s) = m - (1/n) sum_i sum_k log2(1 + exp(-s v_ik)),   s >= 0,
+ * is the GMI of a bit-metric decoder using the LLRs scaled by s; the
+ * s-optimised GMI is max_s GMI(s) (concave in s; found on the device by
+ * safeguarded Newton steps, no host synchronisation). NGMI = GMI / m, the
+ * normalised GMI for uniform priors (glossary entry NGMI of the paper).
+ *   llr      device [n][m] FP32 (llr_is_f64 = 0) or FP64 (1), nats
+ *   tx_idx   device [n] uint32 rows of the format that were sent
+ *   out      device [MDGMI_NFIELDS_S] double, fields below
+ *   ws       device workspace of mdgmi_gmi_sopt_workspace_size bytes
+ * A non-finite LLR or a sent row outside [0, M) makes every estimate NaN
+ * (counted in MDGMI_S_NONFINITE). LLRs that favour the wrong bit on average
+ * give s* = 0 and GMI = 0. */
+enum {
+    MDGMI_S_GMI1 = 0,      /* GMI at s = 1 (the LLRs as given)            */
+    MDGMI_S_SE1 = 1,       /* its standard error                          */
+    MDGMI_S_S = 2,         /* s* maximising GMI(s)                         */
+    MDGMI_S_GMI = 3,       /* GMI(s*), the s-optimised GMI                 */
+    MDGMI_S_SE = 4,        /* standard error of GMI(s*)                    */
+    MDGMI_S_NGMI = 5,      /* GMI(s*) / m                                  */
+    MDGMI_S_N = 6,         /* number of samples                            */
+    MDGMI_S_NONFINITE = 7, /* samples with a non-finite cost               */
+    MDGMI_S_ITERS = 8,     /* evaluation passes used                       */
+    MDGMI_NFIELDS_S = 9
+};
+int mdgmi_gmi_sopt_workspace_size(int64_t n, size_t* bytes);
+int mdgmi_gmi_sopt(const mdgmi_format* fmt, const void* llr, int32_t llr_is_f64, const uint32_t* tx_idx,
+                   int64_t n, double* out, void* ws, size_t ws_bytes, void* stream);
+
 /* Q-factor in dB of a bit error rate, 20 log10(sqrt(2) erfc^-1(2 ber)) (the
  * Gaussian-noise conversion; the paper states no formula). Host-only, no
  * GPU needed; +inf for ber = 0, -inf for ber = 0.5, NaN outside [0, 0.5]. */

@@ -157,10 +157,40 @@ int run_gmi(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int6
             e = launch_mfma(fmt, (const float*)y, tx_idx, n, sa, mode, nullptr, pq, image, pl.cfg, st);
         if (e != hipSuccess) return MDGMI_E_HIP;
     }
-    hipError_t e = launch_reduce(part, n_snr, pl.cfg.blocks_per_snr, n, fmt->m, out, st, mode == kModeHd);
+    const int kind = mode == kModeHd ? kReduceHd : (mode == kModeMlGmi ? kReduceMl : kReduceGmi);
+    hipError_t e = launch_reduce(part, n_snr, pl.cfg.blocks_per_snr, n, fmt->m, out, st, kind);
     return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
 }
 
+
+// Per-bit LLRs of n samples at one noise level (exact or max-log metrics).
+int run_llr(const mdgmi_format* fmt, const void* y, int64_t n, double sigma2, void* llr, int32_t path, int mode,
+            void* ws, size_t ws_bytes, void* stream) {
+    if (!fmt || !y || !llr) return MDGMI_E_NULL;
+    if (n < 1) return MDGMI_E_SHAPE;
+    if (!finite_pos(sigma2)) return MDGMI_E_SIGMA2;
+    int p = 0;
+    int rc = resolve_path(fmt, path, s_of(sigma2), &p);
+    if (rc != MDGMI_OK) return rc;
+    size_t need = 0;
+    rc = mdgmi_llr_workspace_size(fmt, n, p, &need);
+    if (rc != MDGMI_OK) return rc;
+    if (need > 0 && (!ws || ws_bytes < need)) return MDGMI_E_WORKSPACE;
+    rc = check_device(fmt);
+    if (rc != MDGMI_OK) return rc;
+    SnrArgs sa = snr_args(&sigma2, 0, 1);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (p == MDGMI_PATH_F64)
+        e = launch_f64(fmt, (const double*)y, nullptr, n, sa, mode, (double*)llr, nullptr, f64_cfg(fmt, n), st);
+    else if (p == MDGMI_PATH_F32_DIRECT)
+        e = launch_direct(fmt, (const float*)y, nullptr, n, sa, mode, (float*)llr, nullptr, (float*)ws,
+                          direct_cfg(fmt, n), st);
+    else
+        e = launch_mfma(fmt, (const float*)y, nullptr, n, sa, mode, (float*)llr, nullptr, ws,
+                        mfma_cfg(fmt, n, 1, mode), st);
+    return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+}
 }  // namespace
 }  // namespace mdgmi
 
@@ -290,31 +320,12 @@ int mdgmi_llr_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t path, s
 
 int mdgmi_llr(const mdgmi_format* fmt, const void* y, int64_t n, double sigma2, void* llr, int32_t path, void* ws,
               size_t ws_bytes, void* stream) {
-    if (!fmt || !y || !llr) return MDGMI_E_NULL;
-    if (n < 1) return MDGMI_E_SHAPE;
-    if (!finite_pos(sigma2)) return MDGMI_E_SIGMA2;
-    int p = 0;
-    int rc = resolve_path(fmt, path, s_of(sigma2), &p);
-    if (rc != MDGMI_OK) return rc;
-    size_t need = 0;
-    rc = mdgmi_llr_workspace_size(fmt, n, p, &need);
-    if (rc != MDGMI_OK) return rc;
-    if (need > 0 && (!ws || ws_bytes < need)) return MDGMI_E_WORKSPACE;
-    rc = check_device(fmt);
-    if (rc != MDGMI_OK) return rc;
-    SnrArgs sa = snr_args(&sigma2, 0, 1);
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e;
-    if (p == MDGMI_PATH_F64) {
-        e = launch_f64(fmt, (const double*)y, nullptr, n, sa, kModeLlr, (double*)llr, nullptr, f64_cfg(fmt, n), st);
-    } else if (p == MDGMI_PATH_F32_DIRECT) {
-        e = launch_direct(fmt, (const float*)y, nullptr, n, sa, kModeLlr, (float*)llr, nullptr, (float*)ws,
-                          direct_cfg(fmt, n), st);
-    } else {
-        e = launch_mfma(fmt, (const float*)y, nullptr, n, sa, kModeLlr, (float*)llr, nullptr, ws, mfma_cfg(fmt, n, 1),
-                        st);
-    }
-    return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+    return run_llr(fmt, y, n, sigma2, llr, path, kModeLlr, ws, ws_bytes, stream);
+}
+
+int mdgmi_llr_maxlog(const mdgmi_format* fmt, const void* y, int64_t n, double sigma2, void* llr, int32_t path,
+                     void* ws, size_t ws_bytes, void* stream) {
+    return run_llr(fmt, y, n, sigma2, llr, path, kModeMlLlr, ws, ws_bytes, stream);
 }
 
 int mdgmi_gmi_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, int32_t path, size_t* bytes) {
@@ -334,6 +345,31 @@ int mdgmi_gmi_hd(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx,
                  const double* sigma2_host, int32_t n_snr, int32_t path, double* out, void* ws, size_t ws_bytes,
                  void* stream) {
     return run_gmi(fmt, y, tx_idx, n, sigma2_host, n_snr, path, kModeHd, out, ws, ws_bytes, stream);
+}
+
+int mdgmi_gmi_maxlog(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int64_t n,
+                     const double* sigma2_host, int32_t n_snr, int32_t path, double* out, void* ws, size_t ws_bytes,
+                     void* stream) {
+    return run_gmi(fmt, y, tx_idx, n, sigma2_host, n_snr, path, kModeMlGmi, out, ws, ws_bytes, stream);
+}
+
+int mdgmi_gmi_sopt_workspace_size(int64_t n, size_t* bytes) {
+    if (!bytes) return MDGMI_E_NULL;
+    if (n < 1) return MDGMI_E_SHAPE;
+    *bytes = sopt_workspace_bytes(n);
+    return MDGMI_OK;
+}
+
+int mdgmi_gmi_sopt(const mdgmi_format* fmt, const void* llr, int32_t llr_is_f64, const uint32_t* tx_idx, int64_t n,
+                   double* out, void* ws, size_t ws_bytes, void* stream) {
+    if (!fmt || !llr || !tx_idx || !out) return MDGMI_E_NULL;
+    if (n < 1) return MDGMI_E_SHAPE;
+    if (llr_is_f64 != 0 && llr_is_f64 != 1) return MDGMI_E_ARG;
+    if (!ws || ws_bytes < sopt_workspace_bytes(n)) return MDGMI_E_WORKSPACE;
+    int rc = check_device(fmt);
+    if (rc != MDGMI_OK) return rc;
+    hipError_t e = launch_sopt(fmt, llr, llr_is_f64 == 1, tx_idx, n, out, ws, (hipStream_t)stream);
+    return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
 }
 
 double mdgmi_q_factor_db(double ber) {

@@ -129,6 +129,55 @@ struct HiAcc {
     }
 };
 
+// The max counterpart of HiAcc for max-log metrics: per tile-index bit l,
+// R0[l] / R1[l] = largest u over the tiles whose bit l is 0 / 1, from the
+// tile maxima T of G consecutive tiles at a time. Max is exact, so the
+// grouping does not change any value.
+template <int G, int MAXHI>
+struct HiMax {
+    static constexpr int GB = G == 8 ? 3 : (G == 4 ? 2 : (G == 2 ? 1 : 0));
+    float R0[MAXHI > 0 ? MAXHI : 1], R1[MAXHI > 0 ? MAXHI : 1];
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int l = 0; l < (MAXHI > 0 ? MAXHI : 1); l++) R0[l] = R1[l] = -INFINITY;
+    }
+    __device__ __forceinline__ void add_group(int grp, const float* T) {
+        if (G == 1 || MAXHI == 0) return;
+        float GT;
+        if (G == 2) {
+            R0[0] = fmaxf(R0[0], T[0]);
+            R1[0] = fmaxf(R1[0], T[1]);
+            GT = fmaxf(T[0], T[1]);
+        } else if (G == 4) {
+            R0[0] = fmaxf(R0[0], fmaxf(T[0], T[2]));
+            R1[0] = fmaxf(R1[0], fmaxf(T[1], T[3]));
+            const float a = fmaxf(T[0], T[1]), b = fmaxf(T[2], T[3]);
+            R0[1] = fmaxf(R0[1], a);
+            R1[1] = fmaxf(R1[1], b);
+            GT = fmaxf(a, b);
+        } else {
+            R0[0] = fmaxf(R0[0], fmaxf(fmaxf(T[0], T[2]), fmaxf(T[4], T[6])));
+            R1[0] = fmaxf(R1[0], fmaxf(fmaxf(T[1], T[3]), fmaxf(T[5], T[7])));
+            const float a0 = fmaxf(T[0], T[1]), a1 = fmaxf(T[2], T[3]);
+            const float a2 = fmaxf(T[4], T[5]), a3 = fmaxf(T[6], T[7]);
+            R0[1] = fmaxf(R0[1], fmaxf(a0, a2));
+            R1[1] = fmaxf(R1[1], fmaxf(a1, a3));
+            const float q0 = fmaxf(a0, a1), q1 = fmaxf(a2, a3);
+            R0[2] = fmaxf(R0[2], q0);
+            R1[2] = fmaxf(R1[2], q1);
+            GT = fmaxf(q0, q1);
+        }
+#pragma unroll
+        for (int l = GB; l < MAXHI; l++) {
+            // grp is uniform over the wave: a scalar branch
+            if (((uint32_t)grp >> (l - GB)) & 1u)
+                R1[l] = fmaxf(R1[l], GT);
+            else
+                R0[l] = fmaxf(R0[l], GT);
+        }
+    }
+};
+
 // Per-lane FP64 accumulators of the Monte-Carlo sums.
 struct CostAcc {
     double sg = 0.0, sg2 = 0.0, sm = 0.0, sm2 = 0.0, bad = 0.0;
@@ -253,6 +302,35 @@ __device__ inline void exact_classes_f32(const float* yv, const float* __restric
     }
     ltot = lg2(tot) - tmin;
     if (tmin_out) *tmin_out = tmin;
+}
+
+// Max-log fallback in FP32 for one sample: per bit, the log2 metric of the
+// nearest point of each class, u0[k] = -min_{j: bit k = 0} t_j and
+// u1[k] = -min_{j: bit k = 1} t_j with t_j = s ||y - x_j||^2 from the
+// differences (exact at any distance; X32 in label order).
+template <int DIM>
+__device__ inline void class_max_u_f32(const float* yv, const float* __restrict__ X32, int M, int m, float s,
+                                       float* u0, float* u1) {
+#pragma unroll
+    for (int k = 0; k < MDGMI_MAX_BITS; k++) u0[k] = u1[k] = -INFINITY;
+    for (int j = 0; j < M; j++) {
+        float d = 0.0f;
+#pragma unroll
+        for (int q = 0; q < DIM; q++) {
+            const float e = yv[q] - X32[j * DIM + q];
+            d = fmaf(e, e, d);
+        }
+        const float u = -(s * d);
+#pragma unroll
+        for (int k = 0; k < MDGMI_MAX_BITS; k++) {
+            if (k < m) {
+                if ((j >> k) & 1)
+                    u1[k] = fmaxf(u1[k], u);
+                else
+                    u0[k] = fmaxf(u0[k], u);
+            }
+        }
+    }
 }
 
 }  // namespace mdgmi

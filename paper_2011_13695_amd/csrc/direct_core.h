@@ -197,5 +197,115 @@ __device__ __forceinline__ void direct_sample(const float* __restrict__ im, cons
     }
 }
 
+// Max-log metrics of one sample (MODE kModeMlLlr: LLRs into llr; kModeMlGmi:
+// the GMI cost of those LLRs into acc, no MI). The same walk as
+// direct_sample with maxima instead of exponentials and sums: bank[r] keeps
+// the largest u of chunk position r, HiMax the largest u per class of the
+// chunk-index bits. A sample whose nearest point lies outside the exponent
+// window (or whose y is not finite) takes the FP32 per-class path.
+template <int DIM, int CHB, int G, int MODE>
+__device__ __forceinline__ void direct_sample_ml(const float* __restrict__ im, const float* __restrict__ ys,
+                                                 const uint32_t* __restrict__ txs, int64_t i, int M, int m,
+                                                 float s, const float* __restrict__ X32,
+                                                 const uint32_t* __restrict__ labels, float* __restrict__ llr,
+                                                 CostAcc& acc) {
+    constexpr int CH = 1 << CHB;
+    constexpr int REC = DirectRec<DIM>::value;
+    constexpr int MAXHI = MDGMI_MAX_BITS - CHB;
+    const int nchunk = M >> CHB;
+    float yv[DIM];
+    float ys2 = 0.0f;
+#pragma unroll
+    for (int q = 0; q < DIM; q++) {
+        yv[q] = ys[i * DIM + q];
+        ys2 = fmaf(yv[q], yv[q], ys2);
+    }
+    const float K = kBias - s * ys2;
+    float bank[CH];
+#pragma unroll
+    for (int r = 0; r < CH; r++) bank[r] = -INFINITY;
+    HiMax<G, MAXHI> hi;
+    hi.zero();
+    for (int c0 = 0; c0 < nchunk; c0 += G) {
+        float T[G];
+#pragma unroll
+        for (int g = 0; g < G; g++) {
+            const float* __restrict__ rc = im + (size_t)(c0 + g) * CH * REC;
+            float uv[CH];
+#pragma unroll
+            for (int r = 0; r < CH; r++) {
+                float u = K - rc[r * REC + DIM];
+#pragma unroll
+                for (int q = 0; q < DIM; q++) u = fmaf(rc[r * REC + q], yv[q], u);
+                uv[r] = u;
+                bank[r] = fmaxf(bank[r], u);
+            }
+            if (G > 1) {
+#pragma unroll
+                for (int w = 1; w < CH; w <<= 1) {
+#pragma unroll
+                    for (int r = 0; r < CH; r += 2 * w) uv[r] = fmaxf(uv[r], uv[r + w]);
+                }
+                T[g] = uv[0];
+            }
+        }
+        hi.add_group(c0 / G, T);
+    }
+    float u0[MDGMI_MAX_BITS], u1[MDGMI_MAX_BITS];
+    float best = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < CH; r++) best = fmaxf(best, bank[r]);
+#pragma unroll
+    for (int k = 0; k < MDGMI_MAX_BITS; k++) {
+        u0[k] = u1[k] = 0.0f;
+        if (k < m) {
+            float a0 = -INFINITY, a1 = -INFINITY;
+            if (k < CHB) {
+#pragma unroll
+                for (int r = 0; r < CH; r++) {
+                    if ((r >> k) & 1)
+                        a1 = fmaxf(a1, bank[r]);
+                    else
+                        a0 = fmaxf(a0, bank[r]);
+                }
+            } else {
+#pragma unroll
+                for (int l = 0; l < (MAXHI > 0 ? MAXHI : 1); l++) {
+                    if (l == k - CHB) {
+                        a0 = hi.R0[l];
+                        a1 = hi.R1[l];
+                    }
+                }
+            }
+            u0[k] = a0;
+            u1[k] = a1;
+        }
+    }
+    // fmaxf drops NaN: a non-finite y shows as best = -inf or as y itself
+    bool finite = true;
+#pragma unroll
+    for (int q = 0; q < DIM; q++) finite = finite && __builtin_isfinite(yv[q]);
+    if (!(best >= kFarLog2) || !finite) class_max_u_f32<DIM>(yv, X32, M, m, s, u0, u1);
+    if (MODE == kModeMlLlr) {
+#pragma unroll
+        for (int k = 0; k < MDGMI_MAX_BITS; k++)
+            if (k < m) llr[i * m + k] = finite ? (u1[k] - u0[k]) * (float)kLn2 : NAN;
+    } else {
+        const uint32_t row = txs[i];
+        const bool row_ok = row < (uint32_t)M;
+        const uint32_t slot = labels[row_ok ? row : 0u];
+        float cg = 0.0f;
+#pragma unroll
+        for (int k = 0; k < MDGMI_MAX_BITS; k++) {
+            if (k < m) {
+                const bool b = (slot >> k) & 1;
+                cg += bit_cost2(b ? u0[k] - u1[k] : u1[k] - u0[k]);
+            }
+        }
+        if (!row_ok || !finite) cg = NAN;
+        acc.add((double)cg, 0.0);
+    }
+}
+
 }  // namespace direct
 }  // namespace mdgmi

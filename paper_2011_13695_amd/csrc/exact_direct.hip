@@ -21,14 +21,18 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(
     const int64_t snr = sa.snr0 + q_snr;
     const float* __restrict__ im = img + (size_t)q_snr * M * REC;
     const float* ys = y + snr * n * DIM;
-    const uint32_t* txs = MODE == kModeLlr ? nullptr : tx + snr * n;
+    const uint32_t* txs = mode_is_llr(MODE) ? nullptr : tx + snr * n;
     CostAcc acc;
     HdAcc hd;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        direct_sample<DIM, CHB, G, MODE>(im, ys, txs, i, M, m, s, X32, labels, llr, acc, &hd);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if constexpr (mode_is_ml(MODE))
+            direct_sample_ml<DIM, CHB, G, MODE>(im, ys, txs, i, M, m, s, X32, labels, llr, acc);
+        else
+            direct_sample<DIM, CHB, G, MODE>(im, ys, txs, i, M, m, s, X32, labels, llr, acc, &hd);
+    }
     double* dst = part + ((int64_t)q_snr * gridDim.x + blockIdx.x) * (MODE == kModeHd ? kNPartHd : kNPart);
-    if (MODE == kModeGmi) block_reduce_store(acc, dst);
+    if (MODE == kModeGmi || MODE == kModeMlGmi) block_reduce_store(acc, dst);
     if (MODE == kModeHd) block_reduce_store_hd(acc, hd, dst);
 }
 
@@ -48,6 +52,12 @@ hipError_t launch_direct_t(const mdgmi_format* f, const float* y, const uint32_t
     dim3 grid(cfg.blocks_per_snr, sa.n_snr), block(cfg.threads);
     if (mode == kModeLlr)
         hipLaunchKernelGGL((k_direct<DIM, CHB, G, kModeLlr>), grid, block, 0, st, y, tx, image, f->d_X32,
+                           f->d_labels, n, f->M, f->m, sa, llr, part);
+    else if (mode == kModeMlLlr)
+        hipLaunchKernelGGL((k_direct<DIM, CHB, G, kModeMlLlr>), grid, block, 0, st, y, tx, image, f->d_X32,
+                           f->d_labels, n, f->M, f->m, sa, llr, part);
+    else if (mode == kModeMlGmi)
+        hipLaunchKernelGGL((k_direct<DIM, CHB, G, kModeMlGmi>), grid, block, 0, st, y, tx, image, f->d_X32,
                            f->d_labels, n, f->M, f->m, sa, llr, part);
     else if (mode == kModeHd)
         hipLaunchKernelGGL((k_direct<DIM, CHB, G, kModeHd>), grid, block, 0, st, y, tx, image, f->d_X32,

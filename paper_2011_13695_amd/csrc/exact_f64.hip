@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kF64Threads) void k_exact_f64(const double* __restr
     const int64_t snr = sa.snr0 + q_snr;
     const double* ys = y + snr * n * DIM;
     constexpr bool LLR = MODE == kModeLlr;
-    const uint32_t* txs = LLR ? nullptr : tx + snr * n;
+    const uint32_t* txs = mode_is_llr(MODE) ? nullptr : tx + snr * n;
     CostAcc acc;
     HdAcc hd;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -62,6 +62,30 @@ __global__ __launch_bounds__(kF64Threads) void k_exact_f64(const double* __restr
                         cmin0[k] = fmin(cmin0[k], t);
                 }
             }
+        }
+        if (mode_is_ml(MODE)) {
+            // max-log: lambda_k = min over class 0 of t - min over class 1 of t
+            if (MODE == kModeMlLlr) {
+#pragma unroll
+                for (int k = 0; k < MDGMI_MAX_BITS; k++)
+                    if (k < m) llr[i * m + k] = cmin0[k] - cmin1[k];
+            } else {
+                const uint32_t row = txs[i];
+                const bool row_ok = row < (uint32_t)M;
+                const uint32_t slot = labels[row_ok ? row : 0u];
+                double cg = 0.0;
+#pragma unroll
+                for (int k = 0; k < MDGMI_MAX_BITS; k++) {
+                    if (k < m) {
+                        const double lam = cmin0[k] - cmin1[k];
+                        const double u = ((slot >> k) & 1) ? -lam : lam;
+                        cg += fmax(u, 0.0) + log1p(exp(-fabs(u)));
+                    }
+                }
+                if (!row_ok) cg = NAN;
+                acc.add(cg * kLog2e, 0.0);
+            }
+            continue;
         }
         double S0[MDGMI_MAX_BITS], S1[MDGMI_MAX_BITS];
 #pragma unroll
@@ -124,7 +148,7 @@ __global__ __launch_bounds__(kF64Threads) void k_exact_f64(const double* __restr
         }
     }
     double* dst = part + ((int64_t)q_snr * gridDim.x + blockIdx.x) * (MODE == kModeHd ? kNPartHd : kNPart);
-    if (MODE == kModeGmi) block_reduce_store(acc, dst);
+    if (MODE == kModeGmi || MODE == kModeMlGmi) block_reduce_store(acc, dst);
     if (MODE == kModeHd) block_reduce_store_hd(acc, hd, dst);
 }
 
@@ -152,6 +176,12 @@ hipError_t launch_f64(const mdgmi_format* f, const double* y, const uint32_t* tx
                                f->d_labels, n, f->M, f->m, sa, llr, part);                             \
         else if (mode == kModeHd)                                                                      \
             hipLaunchKernelGGL((k_exact_f64<D, kModeHd>), grid, block, 0, st, y, tx, f->d_X64,        \
+                               f->d_labels, n, f->M, f->m, sa, llr, part);                             \
+        else if (mode == kModeMlLlr)                                                                   \
+            hipLaunchKernelGGL((k_exact_f64<D, kModeMlLlr>), grid, block, 0, st, y, tx, f->d_X64,     \
+                               f->d_labels, n, f->M, f->m, sa, llr, part);                             \
+        else if (mode == kModeMlGmi)                                                                   \
+            hipLaunchKernelGGL((k_exact_f64<D, kModeMlGmi>), grid, block, 0, st, y, tx, f->d_X64,     \
                                f->d_labels, n, f->M, f->m, sa, llr, part);                             \
         else                                                                                           \
             hipLaunchKernelGGL((k_exact_f64<D, kModeGmi>), grid, block, 0, st, y, tx, f->d_X64,       \

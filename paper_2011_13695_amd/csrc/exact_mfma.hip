@@ -40,15 +40,19 @@ __global__ __launch_bounds__(WAVES * 64) void k_mfma(
     const uint4* A = LDS_IMG ? lds_img : gimg;
     const int wave = threadIdx.x >> 6;
     const float* ys = y + snr * n * DIM;
-    const uint32_t* txs = MODE == kModeLlr ? nullptr : tx + snr * n;
+    const uint32_t* txs = mode_is_llr(MODE) ? nullptr : tx + snr * n;
     CostAcc acc;
     HdAcc hd;
     const int64_t ncoltiles = (n + 32 * NCOL - 1) / (32 * NCOL);
-    for (int64_t ct = (int64_t)blockIdx.x * WAVES + wave; ct < ncoltiles; ct += (int64_t)gridDim.x * WAVES)
-        mfma_coltile<DIM, NCOL, G, MODE>(A, ys, txs, n, ct, M, m, ntiles, s, X32, labels, llr, acc, &hd);
+    for (int64_t ct = (int64_t)blockIdx.x * WAVES + wave; ct < ncoltiles; ct += (int64_t)gridDim.x * WAVES) {
+        if constexpr (mode_is_ml(MODE))
+            mfma_coltile_ml<DIM, NCOL, G, MODE>(A, ys, txs, n, ct, M, m, ntiles, s, X32, labels, llr, acc);
+        else
+            mfma_coltile<DIM, NCOL, G, MODE>(A, ys, txs, n, ct, M, m, ntiles, s, X32, labels, llr, acc, &hd);
+    }
     (void)n32;
     double* dst = part + ((int64_t)q_snr * gridDim.x + blockIdx.x) * (MODE == kModeHd ? kNPartHd : kNPart);
-    if (MODE == kModeGmi) block_reduce_store(acc, dst);
+    if (MODE == kModeGmi || MODE == kModeMlGmi) block_reduce_store(acc, dst);
     if (MODE == kModeHd) block_reduce_store_hd(acc, hd, dst);
 }
 
@@ -76,8 +80,8 @@ hipError_t launch_vm(const mdgmi_format* f, const float* y, const uint32_t* tx, 
     return hipGetLastError();
 }
 
-// GMI and LLR modes in every launch shape; hard decisions only in the
-// 1-column, 16-wave shape (launch_hd).
+// GMI and LLR modes in every launch shape; hard decisions and max-log
+// metrics only in the 1-column, 16-wave shape (launch_fixed).
 template <int DIM, int NCOL, int WAVES, int G, bool LDS>
 hipError_t launch_v(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n, const SnrArgs& sa,
                     int mode, float* llr, double* part, const uint4* img, int ntiles, int blocks,
@@ -87,23 +91,34 @@ hipError_t launch_v(const mdgmi_format* f, const float* y, const uint32_t* tx, i
     return launch_vm<DIM, NCOL, WAVES, G, LDS, kModeGmi>(f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
 }
 
-template <int DIM>
-hipError_t launch_hd(bool lds, const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
-                     const SnrArgs& sa, double* part, const uint4* img, int ntiles, int blocks, hipStream_t st) {
-#define MDGMI_HD_G(G)                                                                                        \
-    return lds ? launch_vm<DIM, 1, 16, G, true, kModeHd>(f, y, tx, n, sa, nullptr, part, img, ntiles, blocks, \
-                                                          st)                                                 \
-               : launch_vm<DIM, 1, 16, G, false, kModeHd>(f, y, tx, n, sa, nullptr, part, img, ntiles, blocks, st);
+template <int DIM, int MODE>
+hipError_t launch_fixed_m(bool lds, const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
+                          const SnrArgs& sa, float* llr, double* part, const uint4* img, int ntiles, int blocks,
+                          hipStream_t st) {
+#define MDGMI_FIXED_G(G)                                                                                       \
+    return lds ? launch_vm<DIM, 1, 16, G, true, MODE>(f, y, tx, n, sa, llr, part, img, ntiles, blocks, st)     \
+               : launch_vm<DIM, 1, 16, G, false, MODE>(f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
     if (ntiles >= 8) {
-        MDGMI_HD_G(8)
+        MDGMI_FIXED_G(8)
     } else if (ntiles == 4) {
-        MDGMI_HD_G(4)
+        MDGMI_FIXED_G(4)
     } else if (ntiles == 2) {
-        MDGMI_HD_G(2)
+        MDGMI_FIXED_G(2)
     } else {
-        MDGMI_HD_G(1)
+        MDGMI_FIXED_G(1)
     }
-#undef MDGMI_HD_G
+#undef MDGMI_FIXED_G
+}
+
+template <int DIM>
+hipError_t launch_fixed(int mode, bool lds, const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
+                        const SnrArgs& sa, float* llr, double* part, const uint4* img, int ntiles, int blocks,
+                        hipStream_t st) {
+    if (mode == kModeHd)
+        return launch_fixed_m<DIM, kModeHd>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
+    if (mode == kModeMlLlr)
+        return launch_fixed_m<DIM, kModeMlLlr>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
+    return launch_fixed_m<DIM, kModeMlGmi>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
 }
 
 // Variants (sample columns per wave, waves per block, A image in LDS):
@@ -178,8 +193,10 @@ bool mfma_supported(const mdgmi_format* f, double max_s) {
 size_t mfma_image_bytes(const mdgmi_format* f, int n_snr) { return (size_t)n_snr * image_bytes_per_snr(f); }
 
 LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr, int mode) {
-    // hard decisions run the 1-column, 16-wave shape only (LDS image if it fits)
-    const int var = mode == kModeHd ? (image_bytes_per_snr(f) <= 128 * 1024 ? 4 : 6) : pick_variant(f);
+    // hard decisions and max-log metrics run the 1-column, 16-wave shape only
+    // (LDS image if it fits)
+    const bool fixed = mode == kModeHd || mode_is_ml(mode);
+    const int var = fixed ? (image_bytes_per_snr(f) <= 128 * 1024 ? 4 : 6) : pick_variant(f);
     const MfmaVariant& v = kVariants[var];
     const int64_t cols = 32 * v.ncol;
     const int64_t tiles = (n + cols - 1) / cols;
@@ -223,15 +240,15 @@ hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx
     if (e != hipSuccess) return e;
     const int var = pick_variant(f);
     const bool lds = kVariants[var].lds && image_bytes_per_snr(f) <= 128 * 1024;
-    if (mode == kModeHd) {
-        const bool hd_lds = image_bytes_per_snr(f) <= 128 * 1024;
+    if (mode == kModeHd || mode_is_ml(mode)) {
+        const bool flds = image_bytes_per_snr(f) <= 128 * 1024;
         switch (f->dim) {
             case 2:
-                return launch_hd<2>(hd_lds, f, y, tx, n, sa, part, img, ntiles, cfg.blocks_per_snr, st);
+                return launch_fixed<2>(mode, flds, f, y, tx, n, sa, llr, part, img, ntiles, cfg.blocks_per_snr, st);
             case 4:
-                return launch_hd<4>(hd_lds, f, y, tx, n, sa, part, img, ntiles, cfg.blocks_per_snr, st);
+                return launch_fixed<4>(mode, flds, f, y, tx, n, sa, llr, part, img, ntiles, cfg.blocks_per_snr, st);
             default:
-                return launch_hd<8>(hd_lds, f, y, tx, n, sa, part, img, ntiles, cfg.blocks_per_snr, st);
+                return launch_fixed<8>(mode, flds, f, y, tx, n, sa, llr, part, img, ntiles, cfg.blocks_per_snr, st);
         }
     }
     switch (f->dim) {

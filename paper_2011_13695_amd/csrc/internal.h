@@ -30,6 +30,12 @@ constexpr int kNPartHd = kNPart + 2; // ... and, with hard decisions, bit errors
 // What a demapper launch produces: GMI/MI partials, LLRs, or GMI/MI partials
 // with hard-decision error counts.
 constexpr int kModeGmi = 0, kModeLlr = 1, kModeHd = 2;
+// max-log metrics: LLR output, or the GMI of those LLRs (no MI)
+constexpr int kModeMlLlr = 3, kModeMlGmi = 4;
+__host__ __device__ constexpr bool mode_is_llr(int mode) { return mode == kModeLlr || mode == kModeMlLlr; }
+__host__ __device__ constexpr bool mode_is_ml(int mode) { return mode == kModeMlLlr || mode == kModeMlGmi; }
+// what the final reduction writes: GMI/MI, + hard decisions, or GMI only
+constexpr int kReduceGmi = 0, kReduceHd = 1, kReduceMl = 2;
 constexpr int kMaxSnrPerLaunch = 32;
 // Exponents are taken relative to a fixed offset: e_j = 2^(kBias - t_j) with
 // t_j = ||y - x_j||^2 / (2 sigma2) * log2(e) >= 0, so no term can overflow
@@ -75,8 +81,11 @@ hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx
                        const SnrArgs& sa, int mode, float* llr, double* part, void* image,
                        LaunchCfg cfg, hipStream_t st);
 
+size_t sopt_workspace_bytes(int64_t n);
+hipError_t launch_sopt(const mdgmi_format* f, const void* llr, bool f64, const uint32_t* tx, int64_t n, double* out,
+                       void* ws, hipStream_t st);
 hipError_t launch_reduce(const double* part, int n_snr, int blocks_per_snr, int64_t n, int m,
-                         double* out, hipStream_t st, bool hd = false);
+                         double* out, hipStream_t st, int kind = kReduceGmi);
 
 int device_cu_count();
 

@@ -615,5 +615,215 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
     }
 }
 
+// ---- max-log metrics --------------------------------------------------
+// The max-log LLR needs, per bit, the largest u of each class: the same
+// tile walk and fold as the exact sums with max in place of exponential and
+// add (bank[r] = running max of register r, HiMax for the tile-index bits).
+// Max is exact and order-free, so both lane halves hold identical class
+// maxima whatever the combination order.
+template <int DIM, int NCOL, int G, int MAXHI>
+__device__ __forceinline__ void tile_loop_max(const uint4* __restrict__ A, int ntiles, int h, int col,
+                                              const half8 (&bop)[NCOL][Blk<DIM>::value], float (&bank)[NCOL][16],
+                                              HiMax<G, MAXHI> (&hi)[NCOL]) {
+    constexpr int NB = Blk<DIM>::value;
+    constexpr int TS = NB * 64;
+#pragma unroll
+    for (int c = 0; c < NCOL; c++) {
+#pragma unroll
+        for (int r = 0; r < 16; r++) bank[c][r] = -INFINITY;
+        hi[c].zero();
+    }
+    const int tmask = ntiles - 1;
+    const uint4* __restrict__ Al = A + h * 32 + col;
+    half8 a_nxt[NB];
+    f32x16 u_nxt[NCOL];
+    load_a_at<NB>(Al, a_nxt);
+#pragma unroll
+    for (int c = 0; c < NCOL; c++) u_nxt[c] = tile_mfma<NB>(a_nxt, bop[c]);
+    load_a_at<NB>(Al + (1 & tmask) * TS, a_nxt);
+    for (int g0 = 0; g0 < ntiles; g0 += G) {
+        const uint4* __restrict__ Acur = Al + g0 * TS;
+        const uint4* __restrict__ Anxt = Al + ((g0 + G) & tmask) * TS;
+        float T[NCOL][G];
+#pragma unroll
+        for (int i = 0; i < G; i++) {
+            f32x16 u_cur[NCOL];
+#pragma unroll
+            for (int c = 0; c < NCOL; c++) {
+                u_cur[c] = u_nxt[c];
+                u_nxt[c] = tile_mfma<NB>(a_nxt, bop[c]);
+            }
+            if (G == 1)
+                load_a_at<NB>(Al + ((g0 + 2) & tmask) * TS, a_nxt);
+            else if (i + 2 < G)
+                load_a_at<NB>(Acur + (i + 2) * TS, a_nxt);
+            else
+                load_a_at<NB>(Anxt + (i + 2 - G) * TS, a_nxt);
+#pragma unroll
+            for (int c = 0; c < NCOL; c++) {
+                const f32x16& u = u_cur[c];
+#pragma unroll
+                for (int r = 0; r < 16; r++) bank[c][r] = fmaxf(bank[c][r], u[r]);
+                if (G > 1) {
+                    // tile maximum, a tree of 3-input maxima
+                    const float a = fmaxf(fmaxf(u[0], u[1]), u[2]), b = fmaxf(fmaxf(u[3], u[4]), u[5]);
+                    const float d = fmaxf(fmaxf(u[6], u[7]), u[8]), e = fmaxf(fmaxf(u[9], u[10]), u[11]);
+                    const float g = fmaxf(fmaxf(u[12], u[13]), u[14]), q = fmaxf(fmaxf(u[15], a), b);
+                    T[c][i] = fmaxf(fmaxf(q, d), fmaxf(e, g));
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int c = 0; c < NCOL; c++) hi[c].add_group(g0 / G, T[c]);
+    }
+}
+
+// This lane's partial class maxima (the max counterpart of half_partials).
+template <int MAXHI, int G>
+__device__ __forceinline__ void half_partials_max(float* b, const HiMax<G, MAXHI>& hi, int m, float* p0,
+                                                  float* p1) {
+    p0[0] = fmaxf(fmaxf(fmaxf(b[0], b[2]), fmaxf(b[4], b[6])), fmaxf(fmaxf(b[8], b[10]), fmaxf(b[12], b[14])));
+    p1[0] = fmaxf(fmaxf(fmaxf(b[1], b[3]), fmaxf(b[5], b[7])), fmaxf(fmaxf(b[9], b[11]), fmaxf(b[13], b[15])));
+#pragma unroll
+    for (int j = 0; j < 8; j++) b[j] = fmaxf(b[2 * j], b[2 * j + 1]);
+    p0[1] = fmaxf(fmaxf(b[0], b[2]), fmaxf(b[4], b[6]));
+    p1[1] = fmaxf(fmaxf(b[1], b[3]), fmaxf(b[5], b[7]));
+#pragma unroll
+    for (int j = 0; j < 4; j++) b[j] = fmaxf(b[2 * j], b[2 * j + 1]);
+    p0[3] = fmaxf(b[0], b[2]);
+    p1[3] = fmaxf(b[1], b[3]);
+    p0[4] = fmaxf(b[0], b[1]);
+    p1[4] = fmaxf(b[2], b[3]);
+    p0[2] = p1[2] = fmaxf(p0[4], p1[4]);
+#pragma unroll
+    for (int k = 5; k < MDGMI_MAX_BITS; k++) {
+        p0[k] = k < m ? hi.R0[k - 5] : 0.0f;
+        p1[k] = k < m ? hi.R1[k - 5] : 0.0f;
+    }
+}
+
+// Class maxima of label bit k over both halves, identical in every lane.
+__device__ __forceinline__ void full_max(const float* p0, const float* p1, int k, float& U0, float& U1) {
+    if (k == 2) {
+        const Halves t = halves(p0[2]);
+        U0 = t.lo;
+        U1 = t.hi;
+    } else {
+        const Halves a = halves(p0[k]), b = halves(p1[k]);
+        U0 = fmaxf(a.lo, a.hi);
+        U1 = fmaxf(b.lo, b.hi);
+    }
+}
+
+// One column tile with max-log metrics: MODE kModeMlLlr writes LLRs,
+// kModeMlGmi adds the GMI cost of those LLRs to acc (no MI). A sample whose
+// nearest point lies outside the exponent window, whose y is not finite, or
+// (formats with padding rows, M < 32) whose class maximum could be a padding
+// row, takes the FP32 per-class path.
+template <int DIM, int NCOL, int G, int MODE>
+__device__ __forceinline__ void mfma_coltile_ml(const uint4* __restrict__ A, const float* __restrict__ ys,
+                                                const uint32_t* __restrict__ txs, int64_t n, int64_t ct, int M,
+                                                int m, int ntiles, float s, const float* __restrict__ X32,
+                                                const uint32_t* __restrict__ labels, float* __restrict__ llr,
+                                                CostAcc& acc) {
+    constexpr int NB = Blk<DIM>::value;
+    constexpr int MAXHI = MDGMI_MAX_BITS - 5;
+    const int lane = threadIdx.x & 63;
+    const int h = lane >> 5, col = lane & 31;
+    half8 bop[NCOL][NB];
+    int64_t idx[NCOL];
+    float Kc[NCOL];
+    bool fin[NCOL];
+#pragma unroll
+    for (int c = 0; c < NCOL; c++) {
+        idx[c] = (ct * NCOL + c) * 32 + col;
+        const bool valid = idx[c] < n;
+        float yv[DIM], ys2 = 0.0f;
+        fin[c] = true;
+#pragma unroll
+        for (int d = 0; d < DIM; d++) {
+            yv[d] = valid ? ys[idx[c] * DIM + d] : 0.0f;
+            ys2 = fmaf(yv[d], yv[d], ys2);
+            fin[c] = fin[c] && __builtin_isfinite(yv[d]);
+        }
+        Kc[c] = fmaf(-s, ys2, kBias);
+        make_b<DIM>(yv, Kc[c], h, bop[c]);
+    }
+    float bank[NCOL][16];
+    HiMax<G, MAXHI> hi[NCOL];
+    tile_loop_max<DIM, NCOL, G, MAXHI>(A, ntiles, h, col, bop, bank, hi);
+#pragma unroll
+    for (int c = 0; c < NCOL; c++) {
+        const int64_t i = idx[c];
+        float p0[MDGMI_MAX_BITS], p1[MDGMI_MAX_BITS];
+        half_partials_max<MAXHI, G>(bank[c], hi[c], m, p0, p1);
+        float B0, B1;
+        full_max(p0, p1, 2, B0, B1);
+        const float best = fmaxf(B0, B1);
+        bool far = !(best >= kFarLog2) || !fin[c];
+        float cg = 0.0f;
+        constexpr int NJ = (MDGMI_MAX_BITS + 1) / 2;
+        float lam[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; j++) {
+            lam[j] = 0.0f;
+            if (2 * j < m) {  // uniform
+                const int ke = 2 * j, ko = ke + 1 < MDGMI_MAX_BITS ? ke + 1 : ke;
+                float U0e, U1e, U0o = 0.0f, U1o = 0.0f;
+                full_max(p0, p1, ke, U0e, U1e);
+                if (ko < m) full_max(p0, p1, ko, U0o, U1o);
+                if (M < 32) {
+                    // a class maximum near the padding rows' u = K - 60000
+                    const float lim = Kc[c] - 0.5f * kPadNorm;
+                    far = far || fminf(U0e, U1e) < lim || (ko < m && fminf(U0o, U1o) < lim);
+                }
+                const int k = ke + h;
+                const float u0 = h ? U0o : U0e, u1 = h ? U1o : U1e;
+                lam[j] = u1 - u0;  // log2 units
+                if (MODE == kModeMlGmi && k < m) {
+                    const uint32_t row = i < n ? txs[i] : 0u;
+                    const uint32_t slot = labels[row < (uint32_t)M ? row : 0u];
+                    cg += bit_cost2(((slot >> k) & 1) ? u0 - u1 : u1 - u0);
+                }
+            }
+        }
+        if (MODE == kModeMlGmi) cg = half_sum(cg);
+        if (i >= n) continue;
+        if (!far) {
+            if (MODE == kModeMlLlr) {
+#pragma unroll
+                for (int j = 0; j < NJ; j++) {
+                    const int k = 2 * j + h;
+                    if (k < m) llr[i * m + k] = lam[j] * (float)kLn2;
+                }
+            } else if (h == 0) {
+                const uint32_t row = txs[i];
+                acc.add(row < (uint32_t)M ? (double)cg : (double)NAN, 0.0);
+            }
+            continue;
+        }
+        if (h != 0) continue;
+        float yc[DIM], u0[MDGMI_MAX_BITS], u1[MDGMI_MAX_BITS];
+#pragma unroll
+        for (int d = 0; d < DIM; d++) yc[d] = ys[i * DIM + d];
+        class_max_u_f32<DIM>(yc, X32, M, m, s, u0, u1);
+        if (MODE == kModeMlLlr) {
+#pragma unroll
+            for (int k = 0; k < MDGMI_MAX_BITS; k++)
+                if (k < m) llr[i * m + k] = fin[c] ? (u1[k] - u0[k]) * (float)kLn2 : NAN;
+        } else {
+            const uint32_t row = txs[i];
+            const bool row_ok = row < (uint32_t)M;
+            const uint32_t slot = labels[row_ok ? row : 0u];
+            float c2 = 0.0f;
+#pragma unroll
+            for (int k = 0; k < MDGMI_MAX_BITS; k++)
+                if (k < m) c2 += bit_cost2(((slot >> k) & 1) ? u0[k] - u1[k] : u1[k] - u0[k]);
+            acc.add(row_ok && fin[c] ? (double)c2 : (double)NAN, 0.0);
+        }
+    }
+}
+
 }  // namespace mfma
 }  // namespace mdgmi

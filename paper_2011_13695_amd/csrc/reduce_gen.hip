@@ -8,9 +8,10 @@ namespace {
 
 // One block per SNR point; every thread sums a fixed strided subset of the
 // block partials, then a fixed shuffle tree and a fixed per-wave order.
-template <bool HD>
+template <int KIND>
 __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part, int blocks_per_snr, int64_t n,
                                                 int m, double* __restrict__ out) {
+    constexpr bool HD = KIND == kReduceHd;
     constexpr int NP = HD ? kNPartHd : kNPart;
     const int q = blockIdx.x;
     const double* p = part + (size_t)q * blocks_per_snr * NP;
@@ -33,6 +34,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ part,
         o[MDGMI_F_SE_MI] = sqrt(fmax(vm, 0.0) / N);
         o[MDGMI_F_N] = N;
         o[MDGMI_F_NONFINITE] = tot[4];
+        if (KIND == kReduceMl) o[MDGMI_F_MI] = o[MDGMI_F_SE_MI] = NAN;  // no MI from max-log metrics
         if (HD) {
             o[MDGMI_F_BER] = tot[5] / (N * m);
             o[MDGMI_F_SER] = tot[6] / N;
@@ -111,11 +113,13 @@ __global__ __launch_bounds__(256) void k_generate(const double* __restrict__ X64
 }  // namespace
 
 hipError_t launch_reduce(const double* part, int n_snr, int blocks_per_snr, int64_t n, int m, double* out,
-                         hipStream_t st, bool hd) {
-    if (hd)
-        hipLaunchKernelGGL(k_reduce<true>, dim3(n_snr), dim3(256), 0, st, part, blocks_per_snr, n, m, out);
+                         hipStream_t st, int kind) {
+    if (kind == kReduceHd)
+        hipLaunchKernelGGL(k_reduce<kReduceHd>, dim3(n_snr), dim3(256), 0, st, part, blocks_per_snr, n, m, out);
+    else if (kind == kReduceMl)
+        hipLaunchKernelGGL(k_reduce<kReduceMl>, dim3(n_snr), dim3(256), 0, st, part, blocks_per_snr, n, m, out);
     else
-        hipLaunchKernelGGL(k_reduce<false>, dim3(n_snr), dim3(256), 0, st, part, blocks_per_snr, n, m, out);
+        hipLaunchKernelGGL(k_reduce<kReduceGmi>, dim3(n_snr), dim3(256), 0, st, part, blocks_per_snr, n, m, out);
     return hipGetLastError();
 }
 

@@ -38,6 +38,8 @@ MDGMI_NFIELDS = 6
 FIELDS = ("gmi", "mi", "se_gmi", "se_mi", "n", "n_nonfinite")
 MDGMI_NFIELDS_HD = 8
 FIELDS_HD = FIELDS + ("ber", "ser")
+MDGMI_NFIELDS_S = 9
+FIELDS_S = ("gmi_s1", "se_s1", "s_opt", "gmi_sopt", "se_sopt", "ngmi", "n", "n_nonfinite", "iterations")
 
 
 class MdgmiError(RuntimeError):
@@ -72,6 +74,10 @@ def lib():
                                 ctypes.c_size_t, _P]
         L.mdgmi_gmi_hd_workspace_size.argtypes = L.mdgmi_gmi_workspace_size.argtypes
         L.mdgmi_gmi_hd.argtypes = L.mdgmi_gmi.argtypes
+        L.mdgmi_llr_maxlog.argtypes = L.mdgmi_llr.argtypes
+        L.mdgmi_gmi_maxlog.argtypes = L.mdgmi_gmi.argtypes
+        L.mdgmi_gmi_sopt_workspace_size.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
+        L.mdgmi_gmi_sopt.argtypes = [_P, _P, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, ctypes.c_size_t, _P]
         L.mdgmi_q_factor_db.restype = ctypes.c_double
         L.mdgmi_q_factor_db.argtypes = [ctypes.c_double]
         L.mdgmi_set_tuning.argtypes = [ctypes.c_int]
@@ -241,6 +247,63 @@ def mdgmi_gmi_hd(fmt: Format, y, tx_idx, sigma2, path="auto", out=None, ws=None,
         ws = workspace(mdgmi_gmi_hd_workspace_size(fmt, n, n_snr, p))
     _check("mdgmi_gmi_hd", lib().mdgmi_gmi_hd(fmt.handle, _dptr(y), _dptr(tx_idx), n, s2.ctypes.data_as(_P), n_snr,
                                               p, _dptr(out), _dptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def mdgmi_llr_maxlog(fmt: Format, y, sigma2: float, path="auto", llr=None, ws=None, stream=None):
+    """Max-log LLRs (nats) of y [n, dim] -> [n, m] (FP64 path: double, else float)."""
+    import torch
+    assert y.is_cuda and y.is_contiguous() and y.shape[-1] == fmt.dim
+    n = y.numel() // fmt.dim
+    p = _path(path)
+    if llr is None:
+        llr = torch.empty((n, fmt.m), dtype=y.dtype, device=y.device)
+    if ws is None:
+        ws = workspace(mdgmi_llr_workspace_size(fmt, n, p))
+    _check("mdgmi_llr_maxlog", lib().mdgmi_llr_maxlog(fmt.handle, _dptr(y), n, float(sigma2), _dptr(llr), p,
+                                                      _dptr(ws), ws.numel(), _stream(stream)))
+    return llr
+
+
+def mdgmi_gmi_maxlog(fmt: Format, y, tx_idx, sigma2, path="auto", out=None, ws=None, stream=None):
+    """GMI of the max-log LLRs per SNR -> out [n_snr, 6] (MI fields NaN)."""
+    import torch
+    s2 = np.ascontiguousarray(np.atleast_1d(sigma2), dtype=np.float64)
+    n_snr = s2.size
+    assert y.is_cuda and y.is_contiguous() and tx_idx.is_contiguous()
+    n = y.numel() // (fmt.dim * n_snr)
+    assert y.numel() == n_snr * n * fmt.dim and tx_idx.numel() == n_snr * n
+    p = _path(path)
+    if out is None:
+        out = torch.empty((n_snr, MDGMI_NFIELDS), dtype=torch.float64, device=y.device)
+    if ws is None:
+        ws = workspace(mdgmi_gmi_workspace_size(fmt, n, n_snr, p))
+    _check("mdgmi_gmi_maxlog", lib().mdgmi_gmi_maxlog(fmt.handle, _dptr(y), _dptr(tx_idx), n, s2.ctypes.data_as(_P),
+                                                      n_snr, p, _dptr(out), _dptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def mdgmi_gmi_sopt_workspace_size(n: int) -> int:
+    b = ctypes.c_size_t()
+    _check("mdgmi_gmi_sopt_workspace_size", lib().mdgmi_gmi_sopt_workspace_size(n, ctypes.byref(b)))
+    return int(b.value)
+
+
+def mdgmi_gmi_sopt(fmt: Format, llr, tx_idx, out=None, ws=None, stream=None):
+    """s-optimised GMI of LLRs [n, m] (float32 or float64, nats) for the sent
+    rows tx [n] -> out [9] (double, fields FIELDS_S)."""
+    import torch
+    assert llr.is_cuda and llr.is_contiguous() and tx_idx.is_contiguous()
+    assert llr.dtype in (torch.float32, torch.float64)
+    n = llr.numel() // fmt.m
+    assert llr.numel() == n * fmt.m and tx_idx.numel() == n
+    if out is None:
+        out = torch.empty(MDGMI_NFIELDS_S, dtype=torch.float64, device=llr.device)
+    if ws is None:
+        ws = workspace(mdgmi_gmi_sopt_workspace_size(n))
+    _check("mdgmi_gmi_sopt", lib().mdgmi_gmi_sopt(fmt.handle, _dptr(llr), int(llr.dtype == torch.float64),
+                                                  _dptr(tx_idx), n, _dptr(out), _dptr(ws), ws.numel(),
+                                                  _stream(stream)))
     return out
 
 

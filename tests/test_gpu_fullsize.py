@@ -14,7 +14,10 @@ hold at any size:
 * additivity of the reduction: the full-size sums equal the sample-weighted
   sums of two halves run separately (1e-9 relative);
 * the full-size MI agrees with the oracle's MI of the sampled rows within
-  Monte-Carlo error, and MI >= GMI within 3 standard errors.
+  Monte-Carlo error, and MI >= GMI within 3 standard errors;
+* max-log metrics and the s-optimised GMI in the same way (sampled rows,
+  the launch's GMI against the full LLR arrays, s* against the oracle's
+  GMI(s) on the sample).
 """
 import math
 import sys
@@ -117,6 +120,44 @@ def test_mi_against_sampled_oracle(full, orc):
         assert abs(out[q, 1] - r[1]) <= 5.0 * r[3] + 1e-6
         assert abs(out[q, 0] - r[0]) <= 5.0 * r[2] + 1e-6
         assert out[q, 1] >= out[q, 0] - 3.0 * math.hypot(out[q, 2], out[q, 3])
+
+
+def test_maxlog_and_sopt_at_full_size(full, orc):
+    """Max-log metrics on the full 8-D workload in the launch the benchmark
+    times: sampled max-log LLR rows against the oracle, the GMI of the one
+    mdgmi_gmi_maxlog launch against the bit costs of the full max-log LLR
+    arrays, and per SNR point the s-optimised GMI of those arrays: its GMI at
+    s = 1 equals the launch's GMI, GMI(s*) >= GMI(1), and s* maximises the
+    oracle's GMI(s) on a sample within Monte-Carlo error."""
+    wl, f, gf, y, tx, out = full
+    ml = mdgmi.mdgmi_gmi_maxlog(gf, y, tx, wl.sigma2, path="mfma").cpu().numpy()
+    assert np.all(ml[:, 4] == wl.n) and np.all(ml[:, 5] == 0)
+    rng = np.random.default_rng(77)
+    ws = mdgmi.workspace(mdgmi.mdgmi_llr_workspace_size(gf, wl.n, "mfma"))
+    lab = torch.from_numpy(f.labels.astype(np.int64)).cuda()
+    bits = torch.arange(f.m, device="cuda", dtype=torch.int64)
+    for q in range(0, len(wl.sigma2), 3):
+        s2 = float(wl.sigma2[q])
+        lam = mdgmi.mdgmi_llr_maxlog(gf, y[q], s2, path="mfma", ws=ws)
+        rows = np.sort(rng.choice(wl.n, size=ROWS, replace=False))
+        ri = torch.from_numpy(rows).cuda()
+        yr = y[q].index_select(0, ri).cpu().numpy().astype(np.float64)
+        ref = orc.llr_maxlog(yr, f.X, f.labels, s2)
+        got = lam.index_select(0, ri).cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(got - ref) / (LLR_RTOL * np.maximum(np.abs(ref), 1.0))) <= 1.0, q
+        b = ((lab[tx[q].long()].unsqueeze(1) >> bits) & 1).double()
+        u = -(2.0 * b - 1.0) * lam.double()
+        cg = (torch.clamp(u, min=0.0) + torch.log1p(torch.exp(-u.abs()))).sum(dim=1) / math.log(2.0)
+        assert abs(f.m - float(cg.mean()) - ml[q, 0]) <= GMI_TOL32, q
+        so = mdgmi.mdgmi_gmi_sopt(gf, lam, tx[q]).cpu().numpy()
+        assert abs(so[0] - ml[q, 0]) <= 1e-5 and so[3] >= so[0] - 1e-9 and so[8] <= 8
+        tr = tx[q].index_select(0, ri).cpu().numpy().view(np.uint32)
+        g_at = orc.gmi_s(got, f.labels[tr], so[2])
+        s_o, g_o, se_o = orc.gmi_sopt(got, f.labels[tr])
+        assert g_o - g_at[0] <= 3.0 * se_o + 1e-9
+        say(f"[full] max-log q={q}: GMI {ml[q, 0]:.5f} (exact {out[q, 0]:.5f}), s* {so[2]:.4f}, "
+            f"GMI(s*) {so[3]:.5f}")
+        del lam, b, u, cg
 
 
 def test_4d64_workload_full_size(orc):
