@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--no-llr", action="store_true", help="skip timing the LLR-output mode")
     ap.add_argument("--no-hd", action="store_true", help="skip the hard-decision (BER/SER/Q) leg")
     ap.add_argument("--no-maxlog", action="store_true", help="skip the max-log / s-optimised GMI leg")
+    ap.add_argument("--no-paper-formats", action="store_true", help="skip the PAM-N / QAM-N sweep")
     ap.add_argument("--ragged-scale", type=float, default=1.0, help="scale of the ragged sample counts")
     ap.add_argument("--copy-probe", type=float, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration) and exit")
@@ -281,6 +282,46 @@ def maxlog_leg(gf, wl, y, tx, path, gmi_out, exact_ms, reps=3):
                     "and max-log LLRs per SNR point via mdgmi_gmi_sopt (1e7 x 11 LLRs each)"}
 
 
+def paper_formats_leg(n=1 << 20, snr_db=None):
+    """The paper's formats (Gray PAM-2/4/8/16, QAM-4/16/64) over AWGN: an SNR
+    sweep of GMI, MI and bit error rate per format (mdgmi_gmi_hd, AUTO path,
+    samples generated on the device), with the SNR at which the Q-factor
+    reaches the HD-FEC thresholds the paper quotes (8.4 dB, 5.7 dB) and the
+    GMI there. These are the AWGN references for the paper's OSNR results."""
+    import numpy as np
+    import torch
+    import workloads as w
+    from paper_2011_13695_amd import mdgmi
+
+    snr = np.arange(0.0, 40.0 + 1e-9, 1.0) if snr_db is None else np.asarray(snr_db)
+    res = {}
+    t_all = 0.0
+    for k, f in enumerate(w.paper_formats()):
+        gf = mdgmi.Format.of(f)
+        s2 = w.sigma2_from_snr_db(snr, f.dim)
+        y, tx = mdgmi.mdgmi_generate(gf, 1000 + k, s2, n, dtype=torch.float32)
+        ws = mdgmi.workspace(mdgmi.mdgmi_gmi_hd_workspace_size(gf, n, len(snr), "auto"))
+        out = mdgmi.mdgmi_gmi_hd(gf, y, tx, s2, path="auto", ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = mdgmi.mdgmi_gmi_hd(gf, y, tx, s2, path="auto", ws=ws)
+        torch.cuda.synchronize()
+        t_all += time.perf_counter() - t0
+        h = out.cpu().numpy()
+        q = [mdgmi.mdgmi_q_factor_db(float(b)) for b in h[:, 6]]
+        q = [None if not np.isfinite(v) else float(v) for v in q]
+        row = {"m": f.m}
+        for thr in (8.4, 5.7):
+            x = q_crossing([float(v) for v in snr], q, thr)
+            row[f"snr_db_at_q_{thr}dB"] = x
+            row[f"gmi_at_q_{thr}dB"] = None if x is None else float(np.interp(x, snr, h[:, 0]))
+        row["gmi"] = [round(float(v), 5) for v in h[:, 0]]
+        res[f.name] = row
+        del y, tx, ws, out
+    return {"snr_db": [float(v) for v in snr], "n_per_snr": n, "ms_all_formats": t_all * 1e3, "formats": res,
+            "note": "AWGN, unit-energy Gray formats, SNR per symbol; Q = 20 log10(sqrt(2) erfc^-1(2 BER))"}
+
+
 def ragged_leg(args, log, scale=None):
     """Ragged batch: 48 formats (dims 2/4/8, M = 4..4096) x 31 SNR points with
     log-uniform sample counts in [1e4, 1e7], paths and tiles from the
@@ -432,6 +473,8 @@ def main():
         extra["hard_decisions"] = hd_leg(gf, wl, y, tx, args.path, out)
     if not args.no_maxlog:
         extra["maxlog_sopt"] = maxlog_leg(gf, wl, y, tx, args.path, out, ms_per_step)
+    if not args.no_paper_formats:
+        extra["paper_formats"] = paper_formats_leg()
     achieved = pairs / (kernel_ms * 1e-3)
     line = {
         "metric": METRIC,

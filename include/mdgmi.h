@@ -98,7 +98,8 @@ int mdgmi_validate_labels(const uint32_t* labels_host, int32_t M);
  *               above applies to them as given; formats are normally scaled
  *               to unit average energy per N-dimensional symbol).
  *   labels_host host [M] uint32: labels_host[j] is the m-bit label of row j.
- *   M           2^m with 1 <= m <= MDGMI_MAX_BITS;  dim in {2, 4, 8}.
+ *   M           2^m with 1 <= m <= MDGMI_MAX_BITS;  dim in {1, 2, 4, 8} (1: PAM
+ *               on one real axis, as in the IM/DD chain of the paper).
  * On success *out receives a handle owning device memory; release it with
  * mdgmi_format_destroy. Synchronous. */
 int mdgmi_format_create(const double* X_host, const uint32_t* labels_host, int32_t M, int32_t dim,
@@ -240,8 +241,8 @@ int mdgmi_gmi_batched_workspace_size(const mdgmi_instance* inst_host, int32_t n_
 /* One-shot ragged batch. inst_host: host [n_inst]; out: device
  * [n_inst][MDGMI_NFIELDS] double, row q for inst_host[q]. path:
  * MDGMI_PATH_F32_DIRECT, MDGMI_PATH_F32_MFMA_F16SPLIT (every instance needs
- * M >= 128) or MDGMI_PATH_AUTO (per instance: the autotuner's choice, else
- * MFMA for M >= 128). The work list is copied into the workspace on `stream`. */
+ * M >= 128 and dim >= 2) or MDGMI_PATH_AUTO (per instance: the autotuner's
+ * choice, else MFMA for M >= 128; one-dimensional formats always direct). The work list is copied into the workspace on `stream`. */
 int mdgmi_gmi_batched(const mdgmi_instance* inst_host, int32_t n_inst, int32_t path, double* out, void* ws,
                       size_t ws_bytes, void* stream);
 

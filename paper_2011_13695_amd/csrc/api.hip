@@ -230,7 +230,7 @@ int mdgmi_format_create(const double* X_host, const uint32_t* labels_host, int32
                         mdgmi_format** out) {
     if (!X_host || !labels_host || !out) return MDGMI_E_NULL;
     *out = nullptr;
-    if (dim != 2 && dim != 4 && dim != 8) return MDGMI_E_SHAPE;
+    if (dim != 1 && dim != 2 && dim != 4 && dim != 8) return MDGMI_E_SHAPE;
     if (M < 2 || M > (1 << MDGMI_MAX_BITS) || (M & (M - 1)) != 0) return MDGMI_E_SHAPE;
     int rc = mdgmi_validate_labels(labels_host, M);
     if (rc != MDGMI_OK) return rc;

@@ -99,7 +99,7 @@ int mdgmi_tune_clear(void) {
 }
 
 int mdgmi_autotune(int32_t dim, int32_t M, int32_t force, mdgmi_tune_entry* out) {
-    if (dim != 2 && dim != 4 && dim != 8) return MDGMI_E_SHAPE;
+    if (dim != 1 && dim != 2 && dim != 4 && dim != 8) return MDGMI_E_SHAPE;
     if (M < 2 || M > (1 << MDGMI_MAX_BITS) || (M & (M - 1))) return MDGMI_E_SHAPE;
     if (!force) {
         std::lock_guard<std::mutex> g(g_mu);
@@ -237,7 +237,7 @@ int mdgmi_tune_load(const char* path) {
                         "{\"dim\": %d, \"M\": %d, \"path\": %d, \"variant\": %d, \"direct_rate\": %lf, "
                         "\"mfma_rate\": %lf}",
                         &e.dim, &e.M, &e.path, &e.mfma_variant, &e.direct_rate, &e.mfma_rate) == 6) {
-            const bool ok = (e.dim == 2 || e.dim == 4 || e.dim == 8) && e.M >= 2 && e.M <= (1 << MDGMI_MAX_BITS) &&
+            const bool ok = (e.dim == 1 || e.dim == 2 || e.dim == 4 || e.dim == 8) && e.M >= 2 && e.M <= (1 << MDGMI_MAX_BITS) &&
                             (e.path == MDGMI_PATH_F32_DIRECT || e.path == MDGMI_PATH_F32_MFMA_F16SPLIT) &&
                             e.mfma_variant < kMfmaVariants;
             if (ok) {

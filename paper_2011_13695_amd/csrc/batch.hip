@@ -115,7 +115,9 @@ __global__ __launch_bounds__((KIND == kKindMfma ? kMfmaWaves : kDirectWaves) * 6
             else
                 run_mfma_dim<8>(D, in_lds, lds, I.s0, I.s1, acc);
         } else {
-            if (D.dim == 2)
+            if (D.dim == 1)
+                run_direct_dim<1>(D, I.s0, I.s1, acc);
+            else if (D.dim == 2)
                 run_direct_dim<2>(D, I.s0, I.s1, acc);
             else if (D.dim == 4)
                 run_direct_dim<4>(D, I.s0, I.s1, acc);
@@ -167,7 +169,8 @@ size_t al(size_t v) { return (v + 255) / 256 * 256; }
 }  // namespace
 
 int batch_kind_for(const mdgmi_format* f, double s, int path) {
-    const bool mfma_ok = f->M >= 128 && mfma_supported(f, s);
+    // one-dimensional formats run on the direct kernel in a batch
+    const bool mfma_ok = f->dim != 1 && f->M >= 128 && mfma_supported(f, s);
     if (path == MDGMI_PATH_F32_DIRECT) return kKindDirect;
     if (path == MDGMI_PATH_F32_MFMA_F16SPLIT) return mfma_ok ? kKindMfma : -1;
     // AUTO: the tuned choice for this (dim, M) where one exists

@@ -114,6 +114,8 @@ hipError_t launch_direct(const mdgmi_format* f, const float* y, const uint32_t* 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (f->dim) {
+        case 1:
+            return launch_direct_d<1>(f, y, tx, n, sa, mode, llr, part, image, cfg, st);
         case 2:
             return launch_direct_d<2>(f, y, tx, n, sa, mode, llr, part, image, cfg, st);
         case 4:

@@ -188,6 +188,7 @@ hipError_t launch_f64(const mdgmi_format* f, const double* y, const uint32_t* tx
                                f->d_labels, n, f->M, f->m, sa, llr, part);                             \
         break;
     switch (f->dim) {
+        MDGMI_F64_CASE(1)
         MDGMI_F64_CASE(2)
         MDGMI_F64_CASE(4)
         MDGMI_F64_CASE(8)

@@ -114,6 +114,10 @@ template <int DIM>
 hipError_t launch_fixed(int mode, bool lds, const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
                         const SnrArgs& sa, float* llr, double* part, const uint4* img, int ntiles, int blocks,
                         hipStream_t st) {
+    if (mode == kModeGmi)
+        return launch_fixed_m<DIM, kModeGmi>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
+    if (mode == kModeLlr)
+        return launch_fixed_m<DIM, kModeLlr>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
     if (mode == kModeHd)
         return launch_fixed_m<DIM, kModeHd>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
     if (mode == kModeMlLlr)
@@ -195,7 +199,7 @@ size_t mfma_image_bytes(const mdgmi_format* f, int n_snr) { return (size_t)n_snr
 LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr, int mode) {
     // hard decisions and max-log metrics run the 1-column, 16-wave shape only
     // (LDS image if it fits)
-    const bool fixed = mode == kModeHd || mode_is_ml(mode);
+    const bool fixed = mode == kModeHd || mode_is_ml(mode) || f->dim == 1;
     const int var = fixed ? (image_bytes_per_snr(f) <= 128 * 1024 ? 4 : 6) : pick_variant(f);
     const MfmaVariant& v = kVariants[var];
     const int64_t cols = 32 * v.ncol;
@@ -224,6 +228,9 @@ hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx
     uint4* img = (uint4*)image;
     dim3 g((ntiles * 32 + 255) / 256, sa.n_snr);
     switch (f->dim) {
+        case 1:
+            hipLaunchKernelGGL(k_mfma_image<1>, g, dim3(256), 0, st, f->d_X64, f->M, ntiles, sa, img);
+            break;
         case 2:
             hipLaunchKernelGGL(k_mfma_image<2>, g, dim3(256), 0, st, f->d_X64, f->M, ntiles, sa, img);
             break;
@@ -240,9 +247,11 @@ hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx
     if (e != hipSuccess) return e;
     const int var = pick_variant(f);
     const bool lds = kVariants[var].lds && image_bytes_per_snr(f) <= 128 * 1024;
-    if (mode == kModeHd || mode_is_ml(mode)) {
+    if (mode == kModeHd || mode_is_ml(mode) || f->dim == 1) {
         const bool flds = image_bytes_per_snr(f) <= 128 * 1024;
         switch (f->dim) {
+            case 1:
+                return launch_fixed<1>(mode, flds, f, y, tx, n, sa, llr, part, img, ntiles, cfg.blocks_per_snr, st);
             case 2:
                 return launch_fixed<2>(mode, flds, f, y, tx, n, sa, llr, part, img, ntiles, cfg.blocks_per_snr, st);
             case 4:

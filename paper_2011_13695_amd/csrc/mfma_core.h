@@ -21,6 +21,8 @@
 //            B [yh 0..3 yh 0..3   | yl 0..3 1 1 Kh Kl]
 //   2D     : A [x'h0 x'h1 x'l0 x'l1 x'h0 x'h1 0 0 | -nh -nl 1 1 0 0 0 0]
 //            B [yh0 yh1 yh0 yh1 yl0 yl1 0 0        | 1 1 Kh Kl 0 0 0 0]
+//   1D     : A [x'h0 x'l0 x'h0 0 0 0 0 0          | -nh -nl 1 1 0 0 0 0]
+//            B [yh0 yh0 yl0 0 0 0 0 0             | 1 1 Kh Kl 0 0 0 0]
 // with x' = 2 s x, n = s ||x||^2 and K = kBias - s ||y||^2.
 //
 // Output layout of the 32x32 MFMA: lane l, register r holds row
@@ -116,13 +118,21 @@ __device__ inline void image_slot(const double* __restrict__ X64, int M, int nti
         a[0][1].h[5] = nl;
         a[0][1].h[6] = one;
         a[0][1].h[7] = one;
+    } else if (DIM == 2) {
+        a[0][0].h[0] = xh[0];
+        a[0][0].h[1] = xh[DIM - 1];
+        a[0][0].h[2] = xl[0];
+        a[0][0].h[3] = xl[DIM - 1];
+        a[0][0].h[4] = xh[0];
+        a[0][0].h[5] = xh[DIM - 1];
+        a[0][1].h[0] = nh;
+        a[0][1].h[1] = nl;
+        a[0][1].h[2] = one;
+        a[0][1].h[3] = one;
     } else {
         a[0][0].h[0] = xh[0];
-        a[0][0].h[1] = xh[1];
-        a[0][0].h[2] = xl[0];
-        a[0][0].h[3] = xl[1];
-        a[0][0].h[4] = xh[0];
-        a[0][0].h[5] = xh[1];
+        a[0][0].h[1] = xl[0];
+        a[0][0].h[2] = xh[0];
         a[0][1].h[0] = nh;
         a[0][1].h[1] = nl;
         a[0][1].h[2] = one;
@@ -178,14 +188,26 @@ __device__ __forceinline__ void make_b(const float* yv, float K, int h, half8* b
             b0.h[7] = kl;
         }
         bop[0] = b0.v;
+    } else if (DIM == 2) {
+        if (!h) {
+            b0.h[0] = yh[0];
+            b0.h[1] = yh[DIM - 1];
+            b0.h[2] = yh[0];
+            b0.h[3] = yh[DIM - 1];
+            b0.h[4] = yl[0];
+            b0.h[5] = yl[DIM - 1];
+        } else {
+            b0.h[0] = one;
+            b0.h[1] = one;
+            b0.h[2] = kh;
+            b0.h[3] = kl;
+        }
+        bop[0] = b0.v;
     } else {
         if (!h) {
             b0.h[0] = yh[0];
-            b0.h[1] = yh[1];
-            b0.h[2] = yh[0];
-            b0.h[3] = yh[1];
-            b0.h[4] = yl[0];
-            b0.h[5] = yl[1];
+            b0.h[1] = yh[0];
+            b0.h[2] = yl[0];
         } else {
             b0.h[0] = one;
             b0.h[1] = one;

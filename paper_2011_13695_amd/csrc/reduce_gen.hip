@@ -142,6 +142,7 @@ hipError_t launch_generate(const mdgmi_format* f, uint64_t seed, const double* s
                                seed, n, snr_slot0, q0, ga, y, tx);                                         \
         break;
         switch (f->dim) {
+            MDGMI_GEN(1)
             MDGMI_GEN(2)
             MDGMI_GEN(4)
             MDGMI_GEN(8)

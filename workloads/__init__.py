@@ -294,6 +294,13 @@ class Workload:
         return sigma2_from_snr_db(self.snr_db, self.fmt.dim)
 
 
+def paper_formats() -> list:
+    """The modulation formats the paper transmits: Gray PAM-2/4/8/16 on one
+    real axis (IM/DD chain) and Gray square QAM-4/16/64 (Kramers-Kronig
+    chain), unit average energy."""
+    return [pam(1), pam(2), pam(3), pam(4), square_qam(2), square_qam(4), square_qam(6)]
+
+
 def workload_qam16(n: int = 100_000, seed: int = 0) -> Workload:
     return Workload("2D 16-QAM Gray, 11 SNR x 1e5", format_16qam(),
                     np.arange(0.0, 20.0 + 1e-9, 2.0), n, seed, "f64")
