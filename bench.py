@@ -78,6 +78,7 @@ def parse():
     ap.add_argument("--no-hd", action="store_true", help="skip the hard-decision (BER/SER/Q) leg")
     ap.add_argument("--no-maxlog", action="store_true", help="skip the max-log / s-optimised GMI leg")
     ap.add_argument("--no-paper-formats", action="store_true", help="skip the PAM-N / QAM-N sweep")
+    ap.add_argument("--no-stream", action="store_true", help="skip the streaming-monitor leg")
     ap.add_argument("--ragged-scale", type=float, default=1.0, help="scale of the ragged sample counts")
     ap.add_argument("--copy-probe", type=float, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration) and exit")
@@ -322,6 +323,56 @@ def paper_formats_leg(n=1 << 20, snr_db=None):
             "note": "AWGN, unit-energy Gray formats, SNR per symbol; Q = 20 log10(sqrt(2) erfc^-1(2 BER))"}
 
 
+BUFFER_SAMPLES = 1 << 22      # the paper's buffer: 2^22 ADC samples
+BUFFER_BUDGET_MS = 1.049       # 2^22 samples at 4 GSa/s
+
+
+def stream_leg(n_buffers=32, warm=4, lanes=4, distinct=8):
+    """Streaming monitor: buffers of 2^22 samples pushed through
+    mdgmi_stream on `lanes` HIP streams, from device memory and from pinned
+    host memory (PCIe copy included), for the paper's 16-QAM and the 8-D
+    M = 2048 format at 10 dB. `distinct` buffers are generated once and
+    pushed in turn; the rate is over n_buffers pushes after `warm`."""
+    import numpy as np
+    import torch
+    import workloads as w
+    from paper_2011_13695_amd import mdgmi
+
+    res = {"buffer_samples": BUFFER_SAMPLES, "budget_ms_per_buffer": BUFFER_BUDGET_MS, "lanes": lanes}
+    for name, f in (("16-QAM", w.format_16qam()), ("8D-2048", w.format_8d2048())):
+        gf = mdgmi.Format.of(f)
+        s2 = float(w.sigma2_from_snr_db(10.0, f.dim))
+        y, tx = mdgmi.mdgmi_generate(gf, 4242, [s2] * distinct, BUFFER_SAMPLES, dtype=torch.float32)
+        row = {}
+        for mode in ("device", "pinned_host"):
+            if mode == "device":
+                src = [(y[k], tx[k]) for k in range(distinct)]
+            else:
+                src = [(y[k].cpu().pin_memory(), tx[k].cpu().pin_memory()) for k in range(distinct)]
+            st = mdgmi.Stream(gf, s2, BUFFER_SAMPLES, n_lanes=lanes, path="auto", ring=256)
+            for k in range(warm):
+                st.push(*src[k % distinct])
+            st.wait()
+            t0 = time.perf_counter()
+            for k in range(n_buffers):
+                st.push(*src[k % distinct])
+            st.wait()
+            dt = time.perf_counter() - t0
+            tot = st.total()
+            st.close()
+            ms = dt / n_buffers * 1e3
+            row[mode] = {"ms_per_buffer": ms, "real_time_factor": BUFFER_BUDGET_MS / ms,
+                         "sample_points_per_s": BUFFER_SAMPLES * f.M / (ms * 1e-3),
+                         "gmi": float(tot[0]), "mi": float(tot[1])}
+            del src
+        res[name] = row
+        del y, tx
+        torch.cuda.empty_cache()
+    res["note"] = ("real_time_factor = 1.049 ms budget / measured ms per buffer (> 1 keeps up); pinned_host "
+                   "includes the PCIe copy of y and tx for every buffer")
+    return res
+
+
 def ragged_leg(args, log, scale=None):
     """Ragged batch: 48 formats (dims 2/4/8, M = 4..4096) x 31 SNR points with
     log-uniform sample counts in [1e4, 1e7], paths and tiles from the
@@ -475,6 +526,10 @@ def main():
         extra["maxlog_sopt"] = maxlog_leg(gf, wl, y, tx, args.path, out, ms_per_step)
     if not args.no_paper_formats:
         extra["paper_formats"] = paper_formats_leg()
+    if not args.no_stream:
+        y = tx = None  # the workload's 5.7 GB are not needed any more
+        torch.cuda.empty_cache()
+        extra["stream"] = stream_leg()
     achieved = pairs / (kernel_ms * 1e-3)
     line = {
         "metric": METRIC,
@@ -506,7 +561,7 @@ def main():
     if args.learned_samples > 0:
         line["learned"] = learned_leg(gf, wl, args, lambda m: log("learned: " + m))
     if not args.no_ragged:
-        del y, tx
+        y = tx = None
         torch.cuda.empty_cache()
         line["ragged_batch"] = ragged_leg(args, log)
         # the same set with 1/100 of the samples: launch-bound per instance

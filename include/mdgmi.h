@@ -215,6 +215,49 @@ int mdgmi_gmi_sopt_workspace_size(int64_t n, size_t* bytes);
 int mdgmi_gmi_sopt(const mdgmi_format* fmt, const void* llr, int32_t llr_is_f64, const uint32_t* tx_idx,
                    int64_t n, double* out, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- streaming monitor ---------------------------------------------------
+ * GMI/MI of a receiver's output as it arrives, in fixed-size buffers (the
+ * paper's receiver processes its ADC stream in buffers of 2^22 samples on
+ * several streams ordered by events; real-time GPU receiver architecture
+ * section). Each buffer holds up to buffer_n received samples of one format
+ * at one noise level, with the rows that were sent. Buffers are taken in
+ * turn by n_lanes HIP streams (default priority), each with its own device
+ * buffers; a separate stream accumulates the buffers in push order, so the
+ * per-buffer rows and the running totals are bit-identical for any number
+ * of lanes, and each buffer's row equals mdgmi_gmi on the same samples.
+ *   mdgmi_stream_create  sigma2 > 0 fixed for the stream; buffer_n >= 1;
+ *                        1 <= n_lanes <= 8; path as for mdgmi_gmi (resolved
+ *                        once); ring >= 1 result rows kept on the device.
+ *                        Allocates all device memory (synchronous).
+ *   mdgmi_stream_push    one buffer of n <= buffer_n samples: y [n][dim]
+ *                        (double on the FP64 path, else float) and tx_idx
+ *                        [n] uint32. from_host = 1: host pointers, copied
+ *                        asynchronously on the buffer's lane (use pinned
+ *                        memory for overlap; keep it unchanged until
+ *                        mdgmi_stream_wait(index) returns); from_host = 0:
+ *                        device pointers read in place (same lifetime
+ *                        rule). *index receives the buffer's sequence number.
+ *   mdgmi_stream_wait    block until buffer `index` (and every earlier one)
+ *                        is accumulated; index < 0 waits for all.
+ *   mdgmi_stream_result  host [MDGMI_NFIELDS] row of buffer `index` (waits);
+ *                        MDGMI_E_ARG once the ring has moved past it.
+ *   mdgmi_stream_total   host [MDGMI_NFIELDS] over every buffer since create
+ *                        or reset (waits for all).
+ *   mdgmi_stream_reset   zero the running totals (waits for all).
+ * A stream object is used from one host thread at a time. */
+typedef struct mdgmi_stream mdgmi_stream;
+int mdgmi_stream_create(const mdgmi_format* fmt, double sigma2, int64_t buffer_n, int32_t n_lanes, int32_t path,
+                        int32_t ring, mdgmi_stream** out);
+int mdgmi_stream_push(mdgmi_stream* s, const void* y, const uint32_t* tx_idx, int64_t n, int32_t from_host,
+                      int64_t* index);
+int mdgmi_stream_wait(mdgmi_stream* s, int64_t index);
+int mdgmi_stream_result(mdgmi_stream* s, int64_t index, double* out_host);
+int mdgmi_stream_total(mdgmi_stream* s, double* out_host);
+int mdgmi_stream_reset(mdgmi_stream* s);
+/* Buffers pushed so far and the resolved path. */
+int mdgmi_stream_info(const mdgmi_stream* s, int64_t* pushed, int32_t* path);
+int mdgmi_stream_destroy(mdgmi_stream* s);
+
 /* Q-factor in dB of a bit error rate, 20 log10(sqrt(2) erfc^-1(2 ber)) (the
  * Gaussian-noise conversion; the paper states no formula). Host-only, no
  * GPU needed; +inf for ber = 0, -inf for ber = 0.5, NaN outside [0, 0.5]. */

@@ -26,8 +26,6 @@ int device_cu_count() {
     return cache[dev];
 }
 
-namespace {
-
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -69,13 +67,7 @@ double s_of(double sigma2) { return kLog2e / (2.0 * sigma2); }
 
 int part_stride(int mode) { return mode == kModeHd ? kNPartHd : kNPart; }
 
-struct GmiPlan {
-    int path;
-    LaunchCfg cfg;
-    size_t part_bytes, image_bytes, total;
-};
-
-GmiPlan plan_gmi(const mdgmi_format* f, int64_t n, int n_snr, int path, int mode = kModeGmi) {
+GmiPlan plan_gmi(const mdgmi_format* f, int64_t n, int n_snr, int path, int mode) {
     GmiPlan p{};
     p.path = path;
     const int per_launch = std::min(n_snr, kMaxSnrPerLaunch);
@@ -106,6 +98,18 @@ SnrArgs snr_args(const double* sigma2, int q0, int cnt) {
     }
     return sa;
 }
+
+hipError_t launch_exact(const mdgmi_format* f, int path, const void* y, const uint32_t* tx, int64_t n,
+                        const SnrArgs& sa, int mode, void* llr, double* part, void* image, LaunchCfg cfg,
+                        hipStream_t st) {
+    if (path == MDGMI_PATH_F64)
+        return launch_f64(f, (const double*)y, tx, n, sa, mode, (double*)llr, part, cfg, st);
+    if (path == MDGMI_PATH_F32_DIRECT)
+        return launch_direct(f, (const float*)y, tx, n, sa, mode, (float*)llr, part, (float*)image, cfg, st);
+    return launch_mfma(f, (const float*)y, tx, n, sa, mode, (float*)llr, part, image, cfg, st);
+}
+
+namespace {
 
 
 int gmi_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, int32_t path, int mode, size_t* bytes) {

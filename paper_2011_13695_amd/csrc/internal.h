@@ -81,6 +81,27 @@ hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx
                        const SnrArgs& sa, int mode, float* llr, double* part, void* image,
                        LaunchCfg cfg, hipStream_t st);
 
+// Host-side planning shared by the entry points (api.hip).
+size_t align_up(size_t v);
+bool finite_pos(double v);
+int check_device(const mdgmi_format* f);
+// Resolve MDGMI_PATH_AUTO and check that the path can serve the format at
+// the largest s = log2(e) / (2 sigma2) of the call.
+int resolve_path(const mdgmi_format* f, int path, double max_s, int* out);
+double s_of(double sigma2);
+int part_stride(int mode);
+struct GmiPlan {
+    int path;
+    LaunchCfg cfg;
+    size_t part_bytes, image_bytes, total;
+};
+GmiPlan plan_gmi(const mdgmi_format* f, int64_t n, int n_snr, int path, int mode = kModeGmi);
+SnrArgs snr_args(const double* sigma2, int q0, int cnt);
+// One demapper launch on the resolved path (image built inside).
+hipError_t launch_exact(const mdgmi_format* f, int path, const void* y, const uint32_t* tx, int64_t n,
+                        const SnrArgs& sa, int mode, void* llr, double* part, void* image, LaunchCfg cfg,
+                        hipStream_t st);
+
 size_t sopt_workspace_bytes(int64_t n);
 hipError_t launch_sopt(const mdgmi_format* f, const void* llr, bool f64, const uint32_t* tx, int64_t n, double* out,
                        void* ws, hipStream_t st);

@@ -307,6 +307,97 @@ def mdgmi_gmi_sopt(fmt: Format, llr, tx_idx, out=None, ws=None, stream=None):
     return out
 
 
+def _stream_sigs():
+    L = lib()
+    if getattr(L, "_stream_sigs", False):
+        return L
+    L.mdgmi_stream_create.argtypes = [_P, ctypes.c_double, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.POINTER(_P)]
+    L.mdgmi_stream_push.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]
+    L.mdgmi_stream_wait.argtypes = [_P, ctypes.c_int64]
+    L.mdgmi_stream_result.argtypes = [_P, ctypes.c_int64, _P]
+    L.mdgmi_stream_total.argtypes = [_P, _P]
+    L.mdgmi_stream_reset.argtypes = [_P]
+    L.mdgmi_stream_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
+    L.mdgmi_stream_destroy.argtypes = [_P]
+    L._stream_sigs = True
+    return L
+
+
+class Stream:
+    """Streaming GMI/MI monitor over fixed-size buffers (mdgmi_stream_*)."""
+
+    def __init__(self, fmt: Format, sigma2: float, buffer_n: int, n_lanes: int = 4, path="auto", ring: int = 1024):
+        L = _stream_sigs()
+        self.fmt = fmt
+        h = _P()
+        _check("mdgmi_stream_create", L.mdgmi_stream_create(fmt.handle, float(sigma2), int(buffer_n), int(n_lanes),
+                                                            _path(path), int(ring), ctypes.byref(h)))
+        self.handle = h
+        self._inflight = {}
+
+    def push(self, y, tx_idx) -> int:
+        """y [n, dim], tx [n]: torch tensors (device: read in place; CPU,
+        preferably pinned: copied asynchronously) or numpy arrays (copied;
+        kept alive here until the buffer has been waited for)."""
+        import torch
+        if isinstance(y, torch.Tensor):
+            assert y.is_contiguous() and tx_idx.is_contiguous()
+            host = int(not y.is_cuda)
+            yp, tp = _P(y.data_ptr()), _P(tx_idx.data_ptr())
+            n = y.numel() // self.fmt.dim
+        else:
+            y = np.ascontiguousarray(y)
+            tx_idx = np.ascontiguousarray(tx_idx, dtype=np.uint32)
+            host, yp, tp, n = 1, y.ctypes.data_as(_P), tx_idx.ctypes.data_as(_P), y.size // self.fmt.dim
+        idx = ctypes.c_int64()
+        _check("mdgmi_stream_push", _stream_sigs().mdgmi_stream_push(self.handle, yp, tp, n, host, ctypes.byref(idx)))
+        self._inflight[int(idx.value)] = (y, tx_idx)
+        return int(idx.value)
+
+    def _release(self, upto=None):
+        for k in [k for k in self._inflight if upto is None or k <= upto]:
+            del self._inflight[k]
+
+    def wait(self, index: int = -1) -> None:
+        _check("mdgmi_stream_wait", _stream_sigs().mdgmi_stream_wait(self.handle, int(index)))
+        self._release(None if index < 0 else index)
+
+    def result(self, index: int):
+        out = np.empty(MDGMI_NFIELDS)
+        _check("mdgmi_stream_result", _stream_sigs().mdgmi_stream_result(self.handle, int(index),
+                                                                          out.ctypes.data_as(_P)))
+        self._release(index)
+        return out
+
+    def total(self):
+        out = np.empty(MDGMI_NFIELDS)
+        _check("mdgmi_stream_total", _stream_sigs().mdgmi_stream_total(self.handle, out.ctypes.data_as(_P)))
+        self._release()
+        return out
+
+    def reset(self) -> None:
+        _check("mdgmi_stream_reset", _stream_sigs().mdgmi_stream_reset(self.handle))
+        self._release()
+
+    def info(self):
+        n, p = ctypes.c_int64(), ctypes.c_int32()
+        _check("mdgmi_stream_info", _stream_sigs().mdgmi_stream_info(self.handle, ctypes.byref(n), ctypes.byref(p)))
+        return int(n.value), int(p.value)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _stream_sigs().mdgmi_stream_destroy(self.handle)
+            self.handle = None
+            self._inflight = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def mdgmi_q_factor_db(ber: float) -> float:
     """Q-factor (dB) of a bit error rate under the Gaussian-noise conversion."""
     return float(lib().mdgmi_q_factor_db(float(ber)))
