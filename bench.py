@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--path", default="mfma", choices=["mfma", "direct", "f64", "auto"])
+    ap.add_argument("--path", default="mfma", choices=["mfma", "mfma_bf16", "direct", "f64", "auto"])
     ap.add_argument("--n", type=int, default=10_000_000, help="samples per SNR point")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -79,6 +79,7 @@ def parse():
     ap.add_argument("--no-maxlog", action="store_true", help="skip the max-log / s-optimised GMI leg")
     ap.add_argument("--no-paper-formats", action="store_true", help="skip the PAM-N / QAM-N sweep")
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming-monitor leg")
+    ap.add_argument("--no-bf16", action="store_true", help="skip timing the bf16-split MFMA path beside")
     ap.add_argument("--ragged-scale", type=float, default=1.0, help="scale of the ragged sample counts")
     ap.add_argument("--copy-probe", type=float, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration) and exit")
@@ -501,6 +502,12 @@ def main():
                                 "ms_per_step": dwall / max(2, args.steps // 3) * 1e3,
                                 "max_abs_dgmi_vs_timed_path": float(np.abs(dout[:, :2] - out[:, :2]).max()),
                                 "speedup_timed_path_vs_direct": dwall / max(2, args.steps // 3) / (wall / args.steps)}
+    if not args.no_bf16 and args.path == "mfma":
+        bsteps = max(2, args.steps // 3)
+        bwall, bms, bout = run_path("mfma_bf16", bsteps, 1)
+        extra["mfma_bf16"] = {"value": pairs / (bwall / bsteps), "ms_per_step": bwall / bsteps * 1e3,
+                              "max_abs_dgmi_vs_timed_path": float(np.abs(bout[:, :2] - out[:, :2]).max()),
+                              "note": "the same workload on the bf16 three-part split (any SNR range)"}
     if not args.no_llr:
         # LLR output of every sample (11 FP32 per sample written to HBM)
         lam = torch.empty((wl.n, f.m), dtype=torch.float32, device="cuda")

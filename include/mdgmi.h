@@ -60,7 +60,12 @@ typedef enum {
     MDGMI_PATH_F64 = 0,              /* FP64 throughout, exact per class          */
     MDGMI_PATH_F32_DIRECT = 1,       /* FP32 distances on the vector ALUs         */
     MDGMI_PATH_F32_MFMA_F16SPLIT = 2,/* distance term on MFMA, fp16 hi+lo split,  */
-                                     /* FP32 accumulate; log-sum-exp in FP32      */
+                                     /* FP32 accumulate; log-sum-exp in FP32;     */
+                                     /* needs 2s max|x| and s max||x||^2 < 3e4    */
+    MDGMI_PATH_F32_MFMA_BF16SPLIT = 3,/* distance term on MFMA, bf16 three-part  */
+                                     /* split (six products per coordinate,       */
+                                     /* ~24 bits), FP32 accumulate: any SNR; one  */
+                                     /* launch shape; not in ragged batches       */
     MDGMI_PATH_AUTO = 5              /* fastest FP32 exact path for the shape:    */
                                      /* the autotuner's choice for (dim, M), else */
                                      /* MFMA from M = 128 and direct below        */

@@ -49,6 +49,10 @@ int resolve_path(const mdgmi_format* f, int path, double max_s, int* out) {
             if (!mfma_supported(f, max_s)) return MDGMI_E_UNSUPPORTED;
             *out = path;
             return MDGMI_OK;
+        case MDGMI_PATH_F32_MFMA_BF16SPLIT:
+            if (!mfma_supported(f, max_s, 1)) return MDGMI_E_UNSUPPORTED;
+            *out = path;
+            return MDGMI_OK;
         case MDGMI_PATH_AUTO: {
             const bool mfma_ok = f->M >= 32 && mfma_supported(f, max_s);
             const int t = tuned_path(f->dim, f->M);
@@ -78,8 +82,9 @@ GmiPlan plan_gmi(const mdgmi_format* f, int64_t n, int n_snr, int path, int mode
         p.cfg = direct_cfg(f, n);
         p.image_bytes = direct_image_bytes(f, per_launch);
     } else {
-        p.cfg = mfma_cfg(f, n, n_snr, mode);
-        p.image_bytes = mfma_image_bytes(f, per_launch);
+        const int split = path == MDGMI_PATH_F32_MFMA_BF16SPLIT ? 1 : 0;
+        p.cfg = mfma_cfg(f, n, n_snr, mode, split);
+        p.image_bytes = mfma_image_bytes(f, per_launch, split);
     }
     p.part_bytes = (size_t)n_snr * p.cfg.blocks_per_snr * part_stride(mode) * sizeof(double);
     p.total = align_up(p.part_bytes) + align_up(p.image_bytes);
@@ -106,7 +111,8 @@ hipError_t launch_exact(const mdgmi_format* f, int path, const void* y, const ui
         return launch_f64(f, (const double*)y, tx, n, sa, mode, (double*)llr, part, cfg, st);
     if (path == MDGMI_PATH_F32_DIRECT)
         return launch_direct(f, (const float*)y, tx, n, sa, mode, (float*)llr, part, (float*)image, cfg, st);
-    return launch_mfma(f, (const float*)y, tx, n, sa, mode, (float*)llr, part, image, cfg, st);
+    return launch_mfma(f, (const float*)y, tx, n, sa, mode, (float*)llr, part, image, cfg, st,
+                       path == MDGMI_PATH_F32_MFMA_BF16SPLIT ? 1 : 0);
 }
 
 namespace {
@@ -117,7 +123,9 @@ int gmi_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, int32_
     if (n < 1 || n_snr < 1) return MDGMI_E_SHAPE;
     int p = path;
     if (p == MDGMI_PATH_AUTO) p = MDGMI_PATH_F32_MFMA_F16SPLIT;
-    if (p != MDGMI_PATH_F64 && p != MDGMI_PATH_F32_DIRECT && p != MDGMI_PATH_F32_MFMA_F16SPLIT) return MDGMI_E_ARG;
+    if (p != MDGMI_PATH_F64 && p != MDGMI_PATH_F32_DIRECT && p != MDGMI_PATH_F32_MFMA_F16SPLIT &&
+        p != MDGMI_PATH_F32_MFMA_BF16SPLIT)
+        return MDGMI_E_ARG;
     GmiPlan pl = plan_gmi(fmt, n, n_snr, p, mode);
     // AUTO resolves per call (format size, tuning, fp16 range); size for
     // whichever of the two FP32 paths it may take.
@@ -152,14 +160,8 @@ int run_gmi(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int6
         const int cnt = std::min(kMaxSnrPerLaunch, n_snr - q0);
         SnrArgs sa = snr_args(sigma2_host, q0, cnt);
         double* pq = part + (size_t)q0 * pl.cfg.blocks_per_snr * part_stride(mode);
-        hipError_t e;
-        if (p == MDGMI_PATH_F64)
-            e = launch_f64(fmt, (const double*)y, tx_idx, n, sa, mode, nullptr, pq, pl.cfg, st);
-        else if (p == MDGMI_PATH_F32_DIRECT)
-            e = launch_direct(fmt, (const float*)y, tx_idx, n, sa, mode, nullptr, pq, (float*)image, pl.cfg, st);
-        else
-            e = launch_mfma(fmt, (const float*)y, tx_idx, n, sa, mode, nullptr, pq, image, pl.cfg, st);
-        if (e != hipSuccess) return MDGMI_E_HIP;
+        if (launch_exact(fmt, p, y, tx_idx, n, sa, mode, nullptr, pq, image, pl.cfg, st) != hipSuccess)
+            return MDGMI_E_HIP;
     }
     const int kind = mode == kModeHd ? kReduceHd : (mode == kModeMlGmi ? kReduceMl : kReduceGmi);
     hipError_t e = launch_reduce(part, n_snr, pl.cfg.blocks_per_snr, n, fmt->m, out, st, kind);
@@ -184,15 +186,8 @@ int run_llr(const mdgmi_format* fmt, const void* y, int64_t n, double sigma2, vo
     if (rc != MDGMI_OK) return rc;
     SnrArgs sa = snr_args(&sigma2, 0, 1);
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e;
-    if (p == MDGMI_PATH_F64)
-        e = launch_f64(fmt, (const double*)y, nullptr, n, sa, mode, (double*)llr, nullptr, f64_cfg(fmt, n), st);
-    else if (p == MDGMI_PATH_F32_DIRECT)
-        e = launch_direct(fmt, (const float*)y, nullptr, n, sa, mode, (float*)llr, nullptr, (float*)ws,
-                          direct_cfg(fmt, n), st);
-    else
-        e = launch_mfma(fmt, (const float*)y, nullptr, n, sa, mode, (float*)llr, nullptr, ws,
-                        mfma_cfg(fmt, n, 1, mode), st);
+    const GmiPlan pl = plan_gmi(fmt, n, 1, p, mode);
+    hipError_t e = launch_exact(fmt, p, y, nullptr, n, sa, mode, llr, nullptr, ws, pl.cfg, st);
     return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
 }
 }  // namespace
@@ -317,6 +312,8 @@ int mdgmi_llr_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t path, s
         *bytes = align_up(direct_image_bytes(fmt, 1));
     else if (p == MDGMI_PATH_F32_MFMA_F16SPLIT)
         *bytes = align_up(std::max(mfma_image_bytes(fmt, 1), direct_image_bytes(fmt, 1)));
+    else if (p == MDGMI_PATH_F32_MFMA_BF16SPLIT)
+        *bytes = align_up(mfma_image_bytes(fmt, 1, 1));
     else
         return MDGMI_E_ARG;
     return MDGMI_OK;

@@ -429,7 +429,8 @@ int check_instances(const mdgmi_instance* inst, int n_inst) {
 int check_batch_path(int path) {
     return (path == MDGMI_PATH_F32_DIRECT || path == MDGMI_PATH_F32_MFMA_F16SPLIT || path == MDGMI_PATH_AUTO)
                ? MDGMI_OK
-               : (path == MDGMI_PATH_F64 ? MDGMI_E_UNSUPPORTED : MDGMI_E_ARG);
+               : (path == MDGMI_PATH_F64 || path == MDGMI_PATH_F32_MFMA_BF16SPLIT ? MDGMI_E_UNSUPPORTED
+                                                                                  : MDGMI_E_ARG);
 }
 
 }  // namespace

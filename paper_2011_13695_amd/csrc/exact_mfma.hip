@@ -1,6 +1,7 @@
 // FP32 exact demapper with the distance term on the matrix cores: per-SNR
 // kernels over one format (see mfma_core.h for the arithmetic and layouts).
 #include <algorithm>
+#include <cmath>
 
 #include "mfma_core.h"
 
@@ -11,22 +12,22 @@ namespace {
 using namespace mfma;
 
 // Per-SNR A images: [q][tile][blk][half][row].
-template <int DIM>
+template <int DIM, int S>
 __global__ void k_mfma_image(const double* __restrict__ X64, int M, int ntiles, SnrArgs sa,
                              uint4* __restrict__ img) {
-    constexpr int NB = Blk<DIM>::value;
+    constexpr int NB = Blk<DIM, S>::value;
     const int q = blockIdx.y;
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= ntiles * 32) return;
-    image_slot<DIM>(X64, M, ntiles, sa.s64[q], slot, img + (size_t)q * ntiles * NB * 64);
+    image_slot<DIM, S>(X64, M, ntiles, sa.s64[q], slot, img + (size_t)q * ntiles * NB * 64);
 }
 
-template <int DIM, int NCOL, int WAVES, int G, bool LDS_IMG, int MODE>
+template <int DIM, int NCOL, int WAVES, int G, bool LDS_IMG, int MODE, int S = kSplitF16>
 __global__ __launch_bounds__(WAVES * 64) void k_mfma(
     const float* __restrict__ y, const uint32_t* __restrict__ tx, const uint4* __restrict__ img,
     const float* __restrict__ X32, const float* __restrict__ n32, const uint32_t* __restrict__ labels,
     int64_t n, int M, int m, int ntiles, SnrArgs sa, float* __restrict__ llr, double* __restrict__ part) {
-    constexpr int NB = Blk<DIM>::value;
+    constexpr int NB = Blk<DIM, S>::value;
     extern __shared__ uint4 lds_img[];
     const int q_snr = blockIdx.y;
     const float s = sa.s32[q_snr];
@@ -46,9 +47,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_mfma(
     const int64_t ncoltiles = (n + 32 * NCOL - 1) / (32 * NCOL);
     for (int64_t ct = (int64_t)blockIdx.x * WAVES + wave; ct < ncoltiles; ct += (int64_t)gridDim.x * WAVES) {
         if constexpr (mode_is_ml(MODE))
-            mfma_coltile_ml<DIM, NCOL, G, MODE>(A, ys, txs, n, ct, M, m, ntiles, s, X32, labels, llr, acc);
+            mfma_coltile_ml<DIM, NCOL, G, MODE, S>(A, ys, txs, n, ct, M, m, ntiles, s, X32, labels, llr, acc);
         else
-            mfma_coltile<DIM, NCOL, G, MODE>(A, ys, txs, n, ct, M, m, ntiles, s, X32, labels, llr, acc, &hd);
+            mfma_coltile<DIM, NCOL, G, MODE, S>(A, ys, txs, n, ct, M, m, ntiles, s, X32, labels, llr, acc, &hd);
     }
     (void)n32;
     double* dst = part + ((int64_t)q_snr * gridDim.x + blockIdx.x) * (MODE == kModeHd ? kNPartHd : kNPart);
@@ -64,18 +65,18 @@ struct MfmaVariant {
 
 int g_variant_override = -1;  // set through mdgmi_set_tuning for sweeps
 
-template <int DIM, int NCOL, int WAVES, int G, bool LDS, int MODE>
+template <int DIM, int NCOL, int WAVES, int G, bool LDS, int MODE, int S = kSplitF16>
 hipError_t launch_vm(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n, const SnrArgs& sa,
                      float* llr, double* part, const uint4* img, int ntiles, int blocks, hipStream_t st) {
-    constexpr int NB = Blk<DIM>::value;
+    constexpr int NB = Blk<DIM, S>::value;
     dim3 grid(blocks, sa.n_snr), block(WAVES * 64);
     size_t lds = LDS ? (size_t)ntiles * NB * 64 * sizeof(uint4) : 0;
     if (LDS) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_mfma<DIM, NCOL, WAVES, G, true, MODE>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_mfma<DIM, NCOL, WAVES, G, true, MODE, S>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_mfma<DIM, NCOL, WAVES, G, LDS, MODE>), grid, block, lds, st, y, tx, img, f->d_X32,
+    hipLaunchKernelGGL((k_mfma<DIM, NCOL, WAVES, G, LDS, MODE, S>), grid, block, lds, st, y, tx, img, f->d_X32,
                        f->d_n32, f->d_labels, n, f->M, f->m, ntiles, sa, llr, part);
     return hipGetLastError();
 }
@@ -91,13 +92,13 @@ hipError_t launch_v(const mdgmi_format* f, const float* y, const uint32_t* tx, i
     return launch_vm<DIM, NCOL, WAVES, G, LDS, kModeGmi>(f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
 }
 
-template <int DIM, int MODE>
+template <int DIM, int MODE, int S>
 hipError_t launch_fixed_m(bool lds, const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
                           const SnrArgs& sa, float* llr, double* part, const uint4* img, int ntiles, int blocks,
                           hipStream_t st) {
 #define MDGMI_FIXED_G(G)                                                                                       \
-    return lds ? launch_vm<DIM, 1, 16, G, true, MODE>(f, y, tx, n, sa, llr, part, img, ntiles, blocks, st)     \
-               : launch_vm<DIM, 1, 16, G, false, MODE>(f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
+    return lds ? launch_vm<DIM, 1, 16, G, true, MODE, S>(f, y, tx, n, sa, llr, part, img, ntiles, blocks, st)  \
+               : launch_vm<DIM, 1, 16, G, false, MODE, S>(f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
     if (ntiles >= 8) {
         MDGMI_FIXED_G(8)
     } else if (ntiles == 4) {
@@ -110,19 +111,19 @@ hipError_t launch_fixed_m(bool lds, const mdgmi_format* f, const float* y, const
 #undef MDGMI_FIXED_G
 }
 
-template <int DIM>
+template <int DIM, int S = kSplitF16>
 hipError_t launch_fixed(int mode, bool lds, const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
                         const SnrArgs& sa, float* llr, double* part, const uint4* img, int ntiles, int blocks,
                         hipStream_t st) {
     if (mode == kModeGmi)
-        return launch_fixed_m<DIM, kModeGmi>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
+        return launch_fixed_m<DIM, kModeGmi, S>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
     if (mode == kModeLlr)
-        return launch_fixed_m<DIM, kModeLlr>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
+        return launch_fixed_m<DIM, kModeLlr, S>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
     if (mode == kModeHd)
-        return launch_fixed_m<DIM, kModeHd>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
+        return launch_fixed_m<DIM, kModeHd, S>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
     if (mode == kModeMlLlr)
-        return launch_fixed_m<DIM, kModeMlLlr>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
-    return launch_fixed_m<DIM, kModeMlGmi>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
+        return launch_fixed_m<DIM, kModeMlLlr, S>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
+    return launch_fixed_m<DIM, kModeMlGmi, S>(lds, f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
 }
 
 // Variants (sample columns per wave, waves per block, A image in LDS):
@@ -171,10 +172,20 @@ constexpr int kNumVariants = kMfmaVariants;
 const MfmaVariant kVariants[kNumVariants] = {{1, 4, true},  {2, 4, true},  {1, 8, true},  {2, 8, true},
                                              {1, 16, true}, {1, 12, true}, {1, 16, false}, {1, 8, false}};
 
-size_t image_bytes_per_snr(const mdgmi_format* f) {
-    int ntiles = (f->M + 31) / 32;
-    return (size_t)ntiles * (f->dim == 8 ? 2 : 1) * 64 * sizeof(uint4);
+int blocks_of(int dim, int split) {
+    if (split == kSplitBF16) return (6 * dim + 6 + 15) / 16;
+    return dim == 8 ? 2 : 1;
 }
+
+size_t image_bytes_per_snr(const mdgmi_format* f, int split = kSplitF16) {
+    int ntiles = (f->M + 31) / 32;
+    return (size_t)ntiles * blocks_of(f->dim, split) * 64 * sizeof(uint4);
+}
+
+bool bf16_wide(const mdgmi_format* f, int split) {
+    return split == kSplitBF16 && f->dim > 1 && image_bytes_per_snr(f, split) > 128 * 1024;
+}
+
 
 int pick_variant(const mdgmi_format* f) {
     if (g_variant_override >= 0 && g_variant_override < kNumVariants) return g_variant_override;
@@ -187,27 +198,31 @@ int pick_variant(const mdgmi_format* f) {
 
 }  // namespace
 
-bool mfma_supported(const mdgmi_format* f, double max_s) {
+bool mfma_supported(const mdgmi_format* f, double max_s, int split) {
     // fp16 range of the split factors: 2 s |x| and s ||x||^2 must stay well
     // inside 65504 (the per-sample term K is checked in the kernel's range
-    // through the far-point path).
+    // through the far-point path). bf16 has the FP32 exponent range.
+    if (split == kSplitBF16) return std::isfinite(max_s) && std::isfinite(f->max_norm2);
     return 2.0 * max_s * f->max_abs < 30000.0 && max_s * f->max_norm2 < 30000.0;
 }
 
-size_t mfma_image_bytes(const mdgmi_format* f, int n_snr) { return (size_t)n_snr * image_bytes_per_snr(f); }
+size_t mfma_image_bytes(const mdgmi_format* f, int n_snr, int split) {
+    return (size_t)n_snr * image_bytes_per_snr(f, split);
+}
 
-LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr, int mode) {
-    // hard decisions and max-log metrics run the 1-column, 16-wave shape only
-    // (LDS image if it fits)
-    const bool fixed = mode == kModeHd || mode_is_ml(mode) || f->dim == 1;
-    const int var = fixed ? (image_bytes_per_snr(f) <= 128 * 1024 ? 4 : 6) : pick_variant(f);
-    const MfmaVariant& v = kVariants[var];
+LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr, int mode, int split) {
+    // hard decisions, max-log metrics, 1-D formats and the bf16 split run the
+    // 1-column, 16-wave shape only (LDS image if it fits)
+    const bool fixed = mode == kModeHd || mode_is_ml(mode) || f->dim == 1 || split == kSplitBF16;
+    const int var = fixed ? (image_bytes_per_snr(f, split) <= 128 * 1024 ? 4 : 6) : pick_variant(f);
+    const MfmaVariant wide{2, 8, false};
+    const MfmaVariant& v = bf16_wide(f, split) ? wide : kVariants[var];
     const int64_t cols = 32 * v.ncol;
     const int64_t tiles = (n + cols - 1) / cols;
     const int64_t want = (tiles + v.waves - 1) / v.waves;
     // One resident round of blocks over all CUs: blocks per CU limited by
     // the LDS image (160 KiB per CU) and by a target of 16 waves per CU.
-    const size_t img = image_bytes_per_snr(f);
+    const size_t img = image_bytes_per_snr(f, split);
     const bool lds = v.lds && img <= 128 * 1024;
     const int by_lds = lds ? std::max(1, (int)((160 * 1024) / (img + 2048))) : 8;
     const int by_waves = std::max(1, 16 / v.waves);
@@ -221,45 +236,80 @@ LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr, int mode) {
     return c;
 }
 
-hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
-                       const SnrArgs& sa, int mode, float* llr, double* part, void* image,
-                       LaunchCfg cfg, hipStream_t st) {
-    const int ntiles = (f->M + 31) / 32;
-    uint4* img = (uint4*)image;
+// bf16 images above the LDS budget are read from L2, 4 KB per tile and wave
+// for 8-D: two sample columns per wave halve that traffic (8 waves per block
+// for the registers). Such images have at least 32 tiles, so G = 8.
+template <int DIM, int S>
+hipError_t launch_wide_l2(int mode, const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
+                          const SnrArgs& sa, float* llr, double* part, const uint4* img, int ntiles, int blocks,
+                          hipStream_t st) {
+    switch (mode) {
+        case kModeGmi:
+            return launch_vm<DIM, 2, 8, 8, false, kModeGmi, S>(f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
+        case kModeLlr:
+            return launch_vm<DIM, 2, 8, 8, false, kModeLlr, S>(f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
+        case kModeHd:
+            return launch_vm<DIM, 2, 8, 8, false, kModeHd, S>(f, y, tx, n, sa, llr, part, img, ntiles, blocks, st);
+        case kModeMlLlr:
+            return launch_vm<DIM, 2, 8, 8, false, kModeMlLlr, S>(f, y, tx, n, sa, llr, part, img, ntiles, blocks,
+                                                                  st);
+        default:
+            return launch_vm<DIM, 2, 8, 8, false, kModeMlGmi, S>(f, y, tx, n, sa, llr, part, img, ntiles, blocks,
+                                                                  st);
+    }
+}
+
+template <int S>
+hipError_t image_and_fixed(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n, const SnrArgs& sa,
+                           int mode, float* llr, double* part, uint4* img, int ntiles, LaunchCfg cfg,
+                           hipStream_t st) {
     dim3 g((ntiles * 32 + 255) / 256, sa.n_snr);
     switch (f->dim) {
         case 1:
-            hipLaunchKernelGGL(k_mfma_image<1>, g, dim3(256), 0, st, f->d_X64, f->M, ntiles, sa, img);
+            hipLaunchKernelGGL((k_mfma_image<1, S>), g, dim3(256), 0, st, f->d_X64, f->M, ntiles, sa, img);
             break;
         case 2:
-            hipLaunchKernelGGL(k_mfma_image<2>, g, dim3(256), 0, st, f->d_X64, f->M, ntiles, sa, img);
+            hipLaunchKernelGGL((k_mfma_image<2, S>), g, dim3(256), 0, st, f->d_X64, f->M, ntiles, sa, img);
             break;
         case 4:
-            hipLaunchKernelGGL(k_mfma_image<4>, g, dim3(256), 0, st, f->d_X64, f->M, ntiles, sa, img);
+            hipLaunchKernelGGL((k_mfma_image<4, S>), g, dim3(256), 0, st, f->d_X64, f->M, ntiles, sa, img);
             break;
         case 8:
-            hipLaunchKernelGGL(k_mfma_image<8>, g, dim3(256), 0, st, f->d_X64, f->M, ntiles, sa, img);
+            hipLaunchKernelGGL((k_mfma_image<8, S>), g, dim3(256), 0, st, f->d_X64, f->M, ntiles, sa, img);
             break;
         default:
             return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int var = pick_variant(f);
-    const bool lds = kVariants[var].lds && image_bytes_per_snr(f) <= 128 * 1024;
-    if (mode == kModeHd || mode_is_ml(mode) || f->dim == 1) {
-        const bool flds = image_bytes_per_snr(f) <= 128 * 1024;
+    const bool tuned_shape = S == kSplitF16 && !(mode == kModeHd || mode_is_ml(mode) || f->dim == 1);
+    if (S == kSplitBF16 && bf16_wide(f, S)) {
+        const int b = cfg.blocks_per_snr;
         switch (f->dim) {
-            case 1:
-                return launch_fixed<1>(mode, flds, f, y, tx, n, sa, llr, part, img, ntiles, cfg.blocks_per_snr, st);
             case 2:
-                return launch_fixed<2>(mode, flds, f, y, tx, n, sa, llr, part, img, ntiles, cfg.blocks_per_snr, st);
+                return launch_wide_l2<2, S>(mode, f, y, tx, n, sa, llr, part, img, ntiles, b, st);
             case 4:
-                return launch_fixed<4>(mode, flds, f, y, tx, n, sa, llr, part, img, ntiles, cfg.blocks_per_snr, st);
+                return launch_wide_l2<4, S>(mode, f, y, tx, n, sa, llr, part, img, ntiles, b, st);
             default:
-                return launch_fixed<8>(mode, flds, f, y, tx, n, sa, llr, part, img, ntiles, cfg.blocks_per_snr, st);
+                return launch_wide_l2<8, S>(mode, f, y, tx, n, sa, llr, part, img, ntiles, b, st);
         }
     }
+    if (!tuned_shape) {
+        const bool flds = image_bytes_per_snr(f, S) <= 128 * 1024;
+        const int b = cfg.blocks_per_snr;
+        switch (f->dim) {
+            case 1:
+                return launch_fixed<1, S>(mode, flds, f, y, tx, n, sa, llr, part, img, ntiles, b, st);
+            case 2:
+                return launch_fixed<2, S>(mode, flds, f, y, tx, n, sa, llr, part, img, ntiles, b, st);
+            case 4:
+                return launch_fixed<4, S>(mode, flds, f, y, tx, n, sa, llr, part, img, ntiles, b, st);
+            default:
+                return launch_fixed<8, S>(mode, flds, f, y, tx, n, sa, llr, part, img, ntiles, b, st);
+        }
+    }
+    const int var = pick_variant(f);
+    const bool lds = kVariants[var].lds && image_bytes_per_snr(f) <= 128 * 1024;
     switch (f->dim) {
         case 2:
             return launch_d<2>(var, lds, f, y, tx, n, sa, mode, llr, part, img, ntiles, cfg.blocks_per_snr, st);
@@ -268,6 +318,16 @@ hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx
         default:
             return launch_d<8>(var, lds, f, y, tx, n, sa, mode, llr, part, img, ntiles, cfg.blocks_per_snr, st);
     }
+}
+
+hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
+                       const SnrArgs& sa, int mode, float* llr, double* part, void* image,
+                       LaunchCfg cfg, hipStream_t st, int split) {
+    const int ntiles = (f->M + 31) / 32;
+    uint4* img = (uint4*)image;
+    if (split == kSplitBF16)
+        return image_and_fixed<kSplitBF16>(f, y, tx, n, sa, mode, llr, part, img, ntiles, cfg, st);
+    return image_and_fixed<kSplitF16>(f, y, tx, n, sa, mode, llr, part, img, ntiles, cfg, st);
 }
 
 }  // namespace mdgmi

@@ -74,12 +74,13 @@ hipError_t launch_direct(const mdgmi_format* f, const float* y, const uint32_t* 
                          const SnrArgs& sa, int mode, float* llr, double* part, float* image,
                          LaunchCfg cfg, hipStream_t st);
 
-bool mfma_supported(const mdgmi_format* f, double max_s);
-LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr, int mode = kModeGmi);
-size_t mfma_image_bytes(const mdgmi_format* f, int n_snr);
+// split: 0 = fp16 hi + lo operands, 1 = bf16 in three parts (see mfma_core.h)
+bool mfma_supported(const mdgmi_format* f, double max_s, int split = 0);
+LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr, int mode = kModeGmi, int split = 0);
+size_t mfma_image_bytes(const mdgmi_format* f, int n_snr, int split = 0);
 hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
                        const SnrArgs& sa, int mode, float* llr, double* part, void* image,
-                       LaunchCfg cfg, hipStream_t st);
+                       LaunchCfg cfg, hipStream_t st, int split = 0);
 
 // Host-side planning shared by the entry points (api.hip).
 size_t align_up(size_t v);

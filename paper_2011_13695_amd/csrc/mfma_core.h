@@ -38,13 +38,22 @@ namespace mdgmi {
 namespace mfma {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr float kPadNorm = 60000.0f;   // padding rows: u = K - 60000 -> e = 0
 
-template <int DIM>
+// Operand split of the distance term: fp16 hi + lo (two products per
+// coordinate, fp16 range) or bf16 in three parts (six products per
+// coordinate, about 24 significant bits, FP32 range). Operands of either
+// split travel as half8 registers (16 bytes); the bf16 MFMA reinterprets them.
+constexpr int kSplitF16 = 0, kSplitBF16 = 1;
+
+// K = 16 blocks per point: fp16 needs 2 for 8-D (K = 28), else 1; bf16 needs
+// ceil((6 DIM + 6) / 16).
+template <int DIM, int S = kSplitF16>
 struct Blk {
-    static constexpr int value = DIM == 8 ? 2 : 1;
+    static constexpr int value = S == kSplitF16 ? (DIM == 8 ? 2 : 1) : (6 * DIM + 6 + 15) / 16;
 };
 
 __device__ __forceinline__ void split16(double v, _Float16& hi, _Float16& lo) {
@@ -65,9 +74,87 @@ union H8 {
 // A image of one (format, SNR): [tile][blk][half][row] of 8 halves (16 B);
 // writes the entries of one slot (slot < ntiles * 32; slots >= M are padding
 // rows whose exponentials vanish).
+// bf16 layout: entry k of the K vector sits in block k / 16, lane half
+// (k % 16) / 8, position k % 8. For each coordinate d the six products
+// x1 y1, x1 y2, x2 y1, x1 y3, x2 y2, x3 y1 (dropped: x2 y3, x3 y2, x3 y3,
+// ~2^-24 relative), then -n1 -n2 -n3 against ones and ones against K1 K2 K3.
 template <int DIM>
+struct Bf16K {
+    static constexpr int K = 6 * DIM + 6;
+};
+
+__device__ __forceinline__ void split3_bf16(double v, __bf16& a, __bf16& b, __bf16& c) {
+    a = (__bf16)v;
+    const double r1 = v - (double)a;
+    b = (__bf16)r1;
+    c = (__bf16)(r1 - (double)b);
+}
+__device__ __forceinline__ void split3_bf16f(float v, __bf16& a, __bf16& b, __bf16& c) {
+    a = (__bf16)v;
+    const float r1 = v - (float)a;
+    b = (__bf16)r1;
+    c = (__bf16)(r1 - (float)b);
+}
+
+union B8 {
+    half8 v;
+    uint4 u;
+    __bf16 h[8];
+};
+
+template <int DIM>
+__device__ inline void image_slot_bf16(const double* __restrict__ X64, int M, double s, int slot,
+                                       uint4* __restrict__ base) {
+    constexpr int NB = Blk<DIM, kSplitBF16>::value;
+    const int t = slot >> 5, row = slot & 31;
+    __bf16 a[NB * 16];
+#pragma unroll
+    for (int k = 0; k < NB * 16; k++) a[k] = (__bf16)0.0f;
+    const __bf16 one = (__bf16)1.0f;
+    if (slot < M) {
+        double n2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; d++) {
+            const double x = X64[(size_t)slot * DIM + d];
+            n2 += x * x;
+            __bf16 x1, x2, x3;
+            split3_bf16(2.0 * s * x, x1, x2, x3);
+            a[6 * d + 0] = x1;
+            a[6 * d + 1] = x1;
+            a[6 * d + 2] = x2;
+            a[6 * d + 3] = x1;
+            a[6 * d + 4] = x2;
+            a[6 * d + 5] = x3;
+        }
+        __bf16 n1, nb, n3;
+        split3_bf16(-(s * n2), n1, nb, n3);
+        a[6 * DIM + 0] = n1;
+        a[6 * DIM + 1] = nb;
+        a[6 * DIM + 2] = n3;
+    } else {
+        a[6 * DIM + 0] = (__bf16)(-kPadNorm);
+    }
+    a[6 * DIM + 3] = one;
+    a[6 * DIM + 4] = one;
+    a[6 * DIM + 5] = one;
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            B8 v;
+#pragma unroll
+            for (int i = 0; i < 8; i++) v.h[i] = a[16 * b + 8 * h + i];
+            base[((t * NB + b) * 2 + h) * 32 + row] = v.u;
+        }
+}
+
+template <int DIM, int S = kSplitF16>
 __device__ inline void image_slot(const double* __restrict__ X64, int M, int ntiles, double s, int slot,
                                   uint4* __restrict__ base) {
+    if (S == kSplitBF16) {
+        image_slot_bf16<DIM>(X64, M, s, slot, base);
+        return;
+    }
     constexpr int NB = Blk<DIM>::value;
     const int t = slot >> 5, row = slot & 31;
     H8 a[NB][2];
@@ -145,9 +232,49 @@ __device__ inline void image_slot(const double* __restrict__ X64, int M, int nti
     (void)ntiles;
 }
 
-// B operands of one sample column for lane half h.
+// bf16 B operands of one sample column for lane half h (layout of Bf16K).
 template <int DIM>
+__device__ __forceinline__ void make_b_bf16(const float* yv, float K, int h, half8* bop) {
+    constexpr int NB = Blk<DIM, kSplitBF16>::value;
+    __bf16 b[NB * 16];
+#pragma unroll
+    for (int k = 0; k < NB * 16; k++) b[k] = (__bf16)0.0f;
+    const __bf16 one = (__bf16)1.0f;
+#pragma unroll
+    for (int d = 0; d < DIM; d++) {
+        __bf16 y1, y2, y3;
+        split3_bf16f(yv[d], y1, y2, y3);
+        b[6 * d + 0] = y1;
+        b[6 * d + 1] = y2;
+        b[6 * d + 2] = y1;
+        b[6 * d + 3] = y3;
+        b[6 * d + 4] = y2;
+        b[6 * d + 5] = y1;
+    }
+    __bf16 k1, k2, k3;
+    split3_bf16f(K, k1, k2, k3);
+    b[6 * DIM + 0] = one;
+    b[6 * DIM + 1] = one;
+    b[6 * DIM + 2] = one;
+    b[6 * DIM + 3] = k1;
+    b[6 * DIM + 4] = k2;
+    b[6 * DIM + 5] = k3;
+#pragma unroll
+    for (int blk = 0; blk < NB; blk++) {
+        B8 v;
+#pragma unroll
+        for (int i = 0; i < 8; i++) v.h[i] = h ? b[16 * blk + 8 + i] : b[16 * blk + i];
+        bop[blk] = v.v;
+    }
+}
+
+// B operands of one sample column for lane half h.
+template <int DIM, int S = kSplitF16>
 __device__ __forceinline__ void make_b(const float* yv, float K, int h, half8* bop) {
+    if (S == kSplitBF16) {
+        make_b_bf16<DIM>(yv, K, h, bop);
+        return;
+    }
     _Float16 yh[DIM], yl[DIM], kh, kl;
 #pragma unroll
     for (int d = 0; d < DIM; d++) split16f(yv[d], yh[d], yl[d]);
@@ -245,8 +372,17 @@ __device__ __forceinline__ float half_sum(float v) {
     return t.lo + t.hi;
 }
 
-template <int NB>
+template <int NB, int S = kSplitF16>
 __device__ __forceinline__ f32x16 tile_mfma(const half8* a, const half8* b) {
+    if (S == kSplitBF16) {
+        f32x16 u = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[0]),
+                                                           __builtin_bit_cast(bf16x8, b[0]), (f32x16){}, 0, 0, 0);
+#pragma unroll
+        for (int k = 1; k < NB; k++)
+            u = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a[k]),
+                                                        __builtin_bit_cast(bf16x8, b[k]), u, 0, 0, 0);
+        return u;
+    }
     f32x16 u = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[0], b[0], (f32x16){}, 0, 0, 0);
     if (NB == 2) u = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[NB - 1], b[NB - 1], u, 0, 0, 0);
     return u;
@@ -264,11 +400,11 @@ __device__ __forceinline__ f32x16 tile_mfma(const half8* a, const half8* b) {
 // t + 2 past the group are the first two of the next group). CLAMP caps each
 // exponent at 110 so that sums of up to 2^12 terms stay finite when the
 // offset has been raised for far classes (only those classes are read then).
-template <int DIM, int NCOL, int G, bool CLAMP, int MAXHI, bool TRACK = false>
+template <int DIM, int NCOL, int G, bool CLAMP, int MAXHI, bool TRACK = false, int S = kSplitF16>
 __device__ __forceinline__ void tile_loop(const uint4* __restrict__ A, int ntiles, int h, int col,
-                                          const half8 (&bop)[NCOL][Blk<DIM>::value], float (&bank)[NCOL][16],
+                                          const half8 (&bop)[NCOL][Blk<DIM, S>::value], float (&bank)[NCOL][16],
                                           HiAcc<G, MAXHI> (&hi)[NCOL], float* umax = nullptr) {
-    constexpr int NB = Blk<DIM>::value;
+    constexpr int NB = Blk<DIM, S>::value;
     constexpr int TS = NB * 64;  // uint4 per tile of the image
 #pragma unroll
     for (int c = 0; c < NCOL; c++) {
@@ -283,7 +419,7 @@ __device__ __forceinline__ void tile_loop(const uint4* __restrict__ A, int ntile
     f32x16 u_nxt[NCOL];
     load_a_at<NB>(Al, a_nxt);
 #pragma unroll
-    for (int c = 0; c < NCOL; c++) u_nxt[c] = tile_mfma<NB>(a_nxt, bop[c]);
+    for (int c = 0; c < NCOL; c++) u_nxt[c] = tile_mfma<NB, S>(a_nxt, bop[c]);
     load_a_at<NB>(Al + (1 & tmask) * TS, a_nxt);
     for (int g0 = 0; g0 < ntiles; g0 += G) {
         const uint4* __restrict__ Acur = Al + g0 * TS;
@@ -295,7 +431,7 @@ __device__ __forceinline__ void tile_loop(const uint4* __restrict__ A, int ntile
 #pragma unroll
             for (int c = 0; c < NCOL; c++) {
                 u_cur[c] = u_nxt[c];
-                u_nxt[c] = tile_mfma<NB>(a_nxt, bop[c]);
+                u_nxt[c] = tile_mfma<NB, S>(a_nxt, bop[c]);
             }
             if (G == 1)
                 load_a_at<NB>(Al + ((g0 + 2) & tmask) * TS, a_nxt);
@@ -383,12 +519,12 @@ __device__ __forceinline__ void full_sums(const float* p0, const float* p1, int 
 // raised by 100 (the same fold, the exponents of the near points capped);
 // classes still out of range, or non-finite inputs, take the exact
 // per-class path. p0/p1 are the first pass's partials of this lane.
-template <int DIM, int G, int MAXHI>
+template <int DIM, int G, int MAXHI, int S = kSplitF16>
 __device__ __forceinline__ void llr_far_pass(const uint4* __restrict__ A, const float* __restrict__ ys, int64_t n,
                                           int64_t i, int M, int m, int ntiles, float s,
                                           const float* __restrict__ X32, float* __restrict__ llr, const float* p0,
                                           const float* p1) {
-    constexpr int NB = Blk<DIM>::value;
+    constexpr int NB = Blk<DIM, S>::value;
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5, col = lane & 31;
     const float thr = ex2(kFarLog2);
@@ -418,10 +554,10 @@ __device__ __forceinline__ void llr_far_pass(const uint4* __restrict__ A, const 
         yv[d] = valid ? ys[i * DIM + d] : 0.0f;
         ys2 = fmaf(yv[d], yv[d], ys2);
     }
-    make_b<DIM>(yv, fmaf(-s, ys2, kBias + 100.0f), h, bop[0]);
+    make_b<DIM, S>(yv, fmaf(-s, ys2, kBias + 100.0f), h, bop[0]);
     float bank[1][16];
     HiAcc<G, MAXHI> hi[1];
-    tile_loop<DIM, 1, G, true, MAXHI>(A, ntiles, h, col, bop, bank, hi);
+    tile_loop<DIM, 1, G, true, MAXHI, false, S>(A, ntiles, h, col, bop, bank, hi);
     float q0[MDGMI_MAX_BITS], q1[MDGMI_MAX_BITS];
     half_partials<MAXHI, G>(bank[0], hi[0], m, q0, q1);
     float out[NJ];
@@ -471,7 +607,7 @@ __device__ __forceinline__ void llr_far_pass(const uint4* __restrict__ A, const 
 // (format, SNR) instance, against all points of its A image. Costs go to
 // acc (GMI mode) or LLRs to llr (LLR mode). All 64 lanes of the wave must
 // call it together (the MFMA and the half-wave swaps need every lane).
-template <int DIM, int NCOL, int G, int MODE>
+template <int DIM, int NCOL, int G, int MODE, int S = kSplitF16>
 __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const float* __restrict__ ys,
                                              const uint32_t* __restrict__ txs, int64_t n, int64_t ct, int M,
                                              int m, int ntiles, float s, const float* __restrict__ X32,
@@ -479,7 +615,7 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
                                              CostAcc& acc, HdAcc* hd = nullptr) {
     constexpr bool LLR = MODE == kModeLlr;
     constexpr bool HD = MODE == kModeHd;
-    constexpr int NB = Blk<DIM>::value;
+    constexpr int NB = Blk<DIM, S>::value;
     constexpr int MAXHI = MDGMI_MAX_BITS - 5;
     constexpr int TS = NB * 64;
     const int lane = threadIdx.x & 63;
@@ -497,12 +633,12 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
             ys2 = fmaf(yv[d], yv[d], ys2);
         }
         const float K = fmaf(-s, ys2, kBias);
-        make_b<DIM>(yv, K, h, bop[c]);
+        make_b<DIM, S>(yv, K, h, bop[c]);
     }
     float bank[NCOL][16];
     HiAcc<G, MAXHI> hi[NCOL];
     float umax[NCOL];
-    tile_loop<DIM, NCOL, G, false, MAXHI, HD>(A, ntiles, h, col, bop, bank, hi, umax);
+    tile_loop<DIM, NCOL, G, false, MAXHI, HD, S>(A, ntiles, h, col, bop, bank, hi, umax);
     // ---- epilogue ----
     // Each lane folds its own 16 rows into per-bit partial class sums; the
     // two lane halves (rows differing in label bit 2) are combined with one
@@ -531,7 +667,7 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
             // a class of some sample of this column lies too far for the
             // common offset (or y is not finite): second pass for the column
             if (__ballot(!(smin >= ex2(kFarLog2))) != 0ull) {
-                llr_far_pass<DIM, G, MAXHI>(A, ys, n, i, M, m, ntiles, s, X32, llr, p0, p1);
+                llr_far_pass<DIM, G, MAXHI, S>(A, ys, n, i, M, m, ntiles, s, X32, llr, p0, p1);
                 continue;
             }
 #pragma unroll
@@ -565,7 +701,7 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
         // ((r >> 3) << 2) | (r & 3).
         half8 ad[NB];
         load_a_at<NB>(A + (int)(slot >> 5) * TS + h * 32 + (int)(slot & 31), ad);
-        const f32x16 ud = tile_mfma<NB>(ad, bop[c]);
+        const f32x16 ud = tile_mfma<NB, S>(ad, bop[c]);
         const int q = ((col >> 3) << 2) | (col & 3);
         float dv = 0.0f;
 #pragma unroll
@@ -643,11 +779,11 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
 // add (bank[r] = running max of register r, HiMax for the tile-index bits).
 // Max is exact and order-free, so both lane halves hold identical class
 // maxima whatever the combination order.
-template <int DIM, int NCOL, int G, int MAXHI>
+template <int DIM, int NCOL, int G, int MAXHI, int S = kSplitF16>
 __device__ __forceinline__ void tile_loop_max(const uint4* __restrict__ A, int ntiles, int h, int col,
-                                              const half8 (&bop)[NCOL][Blk<DIM>::value], float (&bank)[NCOL][16],
+                                              const half8 (&bop)[NCOL][Blk<DIM, S>::value], float (&bank)[NCOL][16],
                                               HiMax<G, MAXHI> (&hi)[NCOL]) {
-    constexpr int NB = Blk<DIM>::value;
+    constexpr int NB = Blk<DIM, S>::value;
     constexpr int TS = NB * 64;
 #pragma unroll
     for (int c = 0; c < NCOL; c++) {
@@ -661,7 +797,7 @@ __device__ __forceinline__ void tile_loop_max(const uint4* __restrict__ A, int n
     f32x16 u_nxt[NCOL];
     load_a_at<NB>(Al, a_nxt);
 #pragma unroll
-    for (int c = 0; c < NCOL; c++) u_nxt[c] = tile_mfma<NB>(a_nxt, bop[c]);
+    for (int c = 0; c < NCOL; c++) u_nxt[c] = tile_mfma<NB, S>(a_nxt, bop[c]);
     load_a_at<NB>(Al + (1 & tmask) * TS, a_nxt);
     for (int g0 = 0; g0 < ntiles; g0 += G) {
         const uint4* __restrict__ Acur = Al + g0 * TS;
@@ -673,7 +809,7 @@ __device__ __forceinline__ void tile_loop_max(const uint4* __restrict__ A, int n
 #pragma unroll
             for (int c = 0; c < NCOL; c++) {
                 u_cur[c] = u_nxt[c];
-                u_nxt[c] = tile_mfma<NB>(a_nxt, bop[c]);
+                u_nxt[c] = tile_mfma<NB, S>(a_nxt, bop[c]);
             }
             if (G == 1)
                 load_a_at<NB>(Al + ((g0 + 2) & tmask) * TS, a_nxt);
@@ -743,13 +879,13 @@ __device__ __forceinline__ void full_max(const float* p0, const float* p1, int k
 // nearest point lies outside the exponent window, whose y is not finite, or
 // (formats with padding rows, M < 32) whose class maximum could be a padding
 // row, takes the FP32 per-class path.
-template <int DIM, int NCOL, int G, int MODE>
+template <int DIM, int NCOL, int G, int MODE, int S = kSplitF16>
 __device__ __forceinline__ void mfma_coltile_ml(const uint4* __restrict__ A, const float* __restrict__ ys,
                                                 const uint32_t* __restrict__ txs, int64_t n, int64_t ct, int M,
                                                 int m, int ntiles, float s, const float* __restrict__ X32,
                                                 const uint32_t* __restrict__ labels, float* __restrict__ llr,
                                                 CostAcc& acc) {
-    constexpr int NB = Blk<DIM>::value;
+    constexpr int NB = Blk<DIM, S>::value;
     constexpr int MAXHI = MDGMI_MAX_BITS - 5;
     const int lane = threadIdx.x & 63;
     const int h = lane >> 5, col = lane & 31;
@@ -770,11 +906,11 @@ __device__ __forceinline__ void mfma_coltile_ml(const uint4* __restrict__ A, con
             fin[c] = fin[c] && __builtin_isfinite(yv[d]);
         }
         Kc[c] = fmaf(-s, ys2, kBias);
-        make_b<DIM>(yv, Kc[c], h, bop[c]);
+        make_b<DIM, S>(yv, Kc[c], h, bop[c]);
     }
     float bank[NCOL][16];
     HiMax<G, MAXHI> hi[NCOL];
-    tile_loop_max<DIM, NCOL, G, MAXHI>(A, ntiles, h, col, bop, bank, hi);
+    tile_loop_max<DIM, NCOL, G, MAXHI, S>(A, ntiles, h, col, bop, bank, hi);
 #pragma unroll
     for (int c = 0; c < NCOL; c++) {
         const int64_t i = idx[c];

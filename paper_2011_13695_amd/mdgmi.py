@@ -30,9 +30,11 @@ MDGMI_E_ARG = -9
 MDGMI_PATH_F64 = 0
 MDGMI_PATH_F32_DIRECT = 1
 MDGMI_PATH_F32_MFMA_F16SPLIT = 2
+MDGMI_PATH_F32_MFMA_BF16SPLIT = 3
 MDGMI_PATH_AUTO = 5
 PATHS = {"f64": MDGMI_PATH_F64, "direct": MDGMI_PATH_F32_DIRECT,
-         "mfma": MDGMI_PATH_F32_MFMA_F16SPLIT, "auto": MDGMI_PATH_AUTO}
+         "mfma": MDGMI_PATH_F32_MFMA_F16SPLIT, "mfma_bf16": MDGMI_PATH_F32_MFMA_BF16SPLIT,
+         "auto": MDGMI_PATH_AUTO}
 
 MDGMI_NFIELDS = 6
 FIELDS = ("gmi", "mi", "se_gmi", "se_mi", "n", "n_nonfinite")

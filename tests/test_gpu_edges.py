@@ -23,9 +23,9 @@ if not torch.cuda.is_available():
 
 from paper_2011_13695_amd import mdgmi  # noqa: E402
 
-PATHS = ["f64", "direct", "mfma"]
+PATHS = ["f64", "direct", "mfma", "mfma_bf16"]
 LLR_RTOL = 1e-3
-GMI_TOL = {"f64": 1e-10, "direct": 1e-4, "mfma": 1e-4}
+GMI_TOL = {"f64": 1e-10, "direct": 1e-4, "mfma": 1e-4, "mfma_bf16": 1e-4}
 
 
 def say(*a):
@@ -161,3 +161,24 @@ def test_qam16_workload_full_size(orc, path):
     q = 5
     lam = mdgmi.mdgmi_llr(gf, y[q], float(wl.sigma2[q]), path=path).cpu().numpy().astype(np.float64)
     assert llr_ratio(lam, orc.llr(yh[q], f.X, f.labels, float(wl.sigma2[q]))) <= (1e-6 if path == "f64" else 1.0)
+
+
+def test_bf16_split_beyond_the_fp16_range(orc):
+    """At SNRs where the fp16 split's factors overflow (the path reports
+    MDGMI_E_UNSUPPORTED), the bf16 three-part split still runs the distance
+    term on the matrix cores and matches the oracle."""
+    for f, snr in ((w.format_4d64(), 48.0), (w.format_16qam(), 50.0), (w.pam(4), 55.0)):
+        gf = mdgmi.Format.of(f)
+        s2 = float(w.sigma2_from_snr_db(snr, f.dim))
+        y, tx = w.channel_samples(f, s2, seed=12, snr_slot=0, n=3001)
+        y = y.astype(np.float32).astype(np.float64)
+        say(f"[edge] bf16 split {f.name} at {snr} dB")
+        with pytest.raises(mdgmi.MdgmiError) as e:
+            mdgmi.mdgmi_gmi(gf, dev(y[None], torch.float32), dev_u32(tx[None]), [s2], path="mfma")
+        assert e.value.code == mdgmi.MDGMI_E_UNSUPPORTED
+        out = mdgmi.mdgmi_gmi(gf, dev(y[None], torch.float32), dev_u32(tx[None]), [s2],
+                              path="mfma_bf16").cpu().numpy()
+        ref = orc.gmi(y, tx, f.X, f.labels, s2)
+        assert np.max(np.abs(out[0, :2] - ref[:2])) <= 1e-4
+        lam = mdgmi.mdgmi_llr(gf, dev(y, torch.float32), s2, path="mfma_bf16").cpu().numpy().astype(np.float64)
+        assert llr_ratio(lam, orc.llr(y, f.X, f.labels, s2)) <= 1.0

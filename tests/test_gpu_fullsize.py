@@ -160,6 +160,36 @@ def test_maxlog_and_sopt_at_full_size(full, orc):
         del lam, b, u, cg
 
 
+def test_bf16_split_at_full_size(full, orc):
+    """The bf16 three-part split on the full 8-D workload: sampled LLR rows
+    against the oracle, and its one-launch GMI/MI against the fp16 split's
+    (both within 1e-4 of the same exact values, so within 2e-4 of each other)
+    and against the bit costs of its own full LLR arrays."""
+    wl, f, gf, y, tx, out = full
+    ob = mdgmi.mdgmi_gmi(gf, y, tx, wl.sigma2, path="mfma_bf16").cpu().numpy()
+    assert np.all(ob[:, 4] == wl.n) and np.all(ob[:, 5] == 0)
+    assert np.max(np.abs(ob[:, :2] - out[:, :2])) <= 2e-4
+    rng = np.random.default_rng(1616)
+    ws = mdgmi.workspace(mdgmi.mdgmi_llr_workspace_size(gf, wl.n, "mfma_bf16"))
+    lab = torch.from_numpy(f.labels.astype(np.int64)).cuda()
+    bits = torch.arange(f.m, device="cuda", dtype=torch.int64)
+    for q in (0, 8, 15):
+        s2 = float(wl.sigma2[q])
+        lam = mdgmi.mdgmi_llr(gf, y[q], s2, path="mfma_bf16", ws=ws)
+        rows = np.sort(rng.choice(wl.n, size=ROWS, replace=False))
+        ri = torch.from_numpy(rows).cuda()
+        yr = y[q].index_select(0, ri).cpu().numpy().astype(np.float64)
+        ref = orc.llr(yr, f.X, f.labels, s2)
+        got = lam.index_select(0, ri).cpu().numpy().astype(np.float64)
+        assert np.max(np.abs(got - ref) / (LLR_RTOL * np.maximum(np.abs(ref), 1.0))) <= 1.0, q
+        b = ((lab[tx[q].long()].unsqueeze(1) >> bits) & 1).double()
+        u = -(2.0 * b - 1.0) * lam.double()
+        cg = (torch.clamp(u, min=0.0) + torch.log1p(torch.exp(-u.abs()))).sum(dim=1) / math.log(2.0)
+        assert abs(f.m - float(cg.mean()) - ob[q, 0]) <= GMI_TOL32, q
+        say(f"[full] bf16 q={q}: GMI {ob[q, 0]:.6f} (fp16 {out[q, 0]:.6f})")
+        del lam, b, u, cg
+
+
 def test_4d64_workload_full_size(orc):
     """21 SNR points x 1e7 samples of the 4-D M = 64 format on the default
     (autotuned or untuned) path: sampled LLR rows against the oracle, the

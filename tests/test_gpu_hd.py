@@ -31,8 +31,8 @@ if not torch.cuda.is_available():
 
 from paper_2011_13695_amd import mdgmi  # noqa: E402
 
-PATHS = ["f64", "direct", "mfma"]
-GMI_TOL = {"f64": 1e-10, "direct": 1e-4, "mfma": 1e-4}
+PATHS = ["f64", "direct", "mfma", "mfma_bf16"]
+GMI_TOL = {"f64": 1e-10, "direct": 1e-4, "mfma": 1e-4, "mfma_bf16": 1e-4}
 LOG2E = 1.0 / math.log(2.0)
 
 

@@ -27,9 +27,9 @@ if not torch.cuda.is_available():
 
 from paper_2011_13695_amd import mdgmi  # noqa: E402
 
-PATHS = ["f64", "direct", "mfma"]
-LLR_RTOL = {"f64": 1e-9, "direct": 1e-3, "mfma": 1e-3}
-GMI_TOL = {"f64": 1e-10, "direct": 1e-4, "mfma": 1e-4}
+PATHS = ["f64", "direct", "mfma", "mfma_bf16"]
+LLR_RTOL = {"f64": 1e-9, "direct": 1e-3, "mfma": 1e-3, "mfma_bf16": 1e-3}
+GMI_TOL = {"f64": 1e-10, "direct": 1e-4, "mfma": 1e-4, "mfma_bf16": 1e-4}
 
 
 def say(*a):

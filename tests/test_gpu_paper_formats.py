@@ -24,9 +24,9 @@ if not torch.cuda.is_available():
 
 from paper_2011_13695_amd import mdgmi  # noqa: E402
 
-PATHS = ["f64", "direct", "mfma"]
-GMI_TOL = {"f64": 1e-10, "direct": 1e-4, "mfma": 1e-4}
-LLR_RTOL = {"f64": 1e-9, "direct": 1e-3, "mfma": 1e-3}
+PATHS = ["f64", "direct", "mfma", "mfma_bf16"]
+GMI_TOL = {"f64": 1e-10, "direct": 1e-4, "mfma": 1e-4, "mfma_bf16": 1e-4}
+LLR_RTOL = {"f64": 1e-9, "direct": 1e-3, "mfma": 1e-3, "mfma_bf16": 1e-3}
 FORMATS = {f.name: f for f in w.paper_formats()}
 SNRS = {"2-PAM": [0.0, 6.0, 12.0], "4-PAM": [4.0, 12.0, 20.0], "8-PAM": [8.0, 18.0, 28.0],
         "16-PAM": [14.0, 24.0, 34.0], "4-QAM": [0.0, 6.0, 12.0], "16-QAM": [4.0, 12.0, 20.0],

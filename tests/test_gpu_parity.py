@@ -23,7 +23,7 @@ if not torch.cuda.is_available():
 
 from paper_2011_13695_amd import mdgmi  # noqa: E402
 
-F32_PATHS = ["direct", "mfma"]
+F32_PATHS = ["direct", "mfma", "mfma_bf16"]
 LLR_RTOL = 1e-3
 GMI_TOL32 = 1e-4
 
