@@ -68,7 +68,8 @@ typedef enum {
                                      /* launch shape; not in ragged batches       */
     MDGMI_PATH_AUTO = 5              /* fastest FP32 exact path for the shape:    */
                                      /* the autotuner's choice for (dim, M), else */
-                                     /* MFMA from M = 128 and direct below        */
+                                     /* MFMA from M = 128 and direct below; the   */
+                                     /* bf16 split where fp16 is out of range     */
 } mdgmi_path;
 
 /* Fields of one GMI/MI result row (doubles). */

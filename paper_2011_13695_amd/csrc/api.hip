@@ -56,10 +56,15 @@ int resolve_path(const mdgmi_format* f, int path, double max_s, int* out) {
         case MDGMI_PATH_AUTO: {
             const bool mfma_ok = f->M >= 32 && mfma_supported(f, max_s);
             const int t = tuned_path(f->dim, f->M);
-            if (t == MDGMI_PATH_F32_DIRECT || (t == MDGMI_PATH_F32_MFMA_F16SPLIT && mfma_ok))
+            const bool want_mfma = t == MDGMI_PATH_F32_MFMA_F16SPLIT || (t < 0 && f->M >= 128);
+            if (t == MDGMI_PATH_F32_DIRECT)
                 *out = t;
+            else if (want_mfma && mfma_ok)
+                *out = MDGMI_PATH_F32_MFMA_F16SPLIT;
+            else if (want_mfma && mfma_supported(f, max_s, 1))
+                *out = MDGMI_PATH_F32_MFMA_BF16SPLIT;  // beyond the fp16 range: the bf16 split
             else  // untuned: below 128 points the per-sample work of the MFMA path dominates
-                *out = mfma_ok && f->M >= 128 ? MDGMI_PATH_F32_MFMA_F16SPLIT : MDGMI_PATH_F32_DIRECT;
+                *out = MDGMI_PATH_F32_DIRECT;
             return MDGMI_OK;
         }
         default:
@@ -130,7 +135,8 @@ int gmi_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, int32_
     // AUTO resolves per call (format size, tuning, fp16 range); size for
     // whichever of the two FP32 paths it may take.
     if (path == MDGMI_PATH_AUTO)
-        pl.total = std::max(pl.total, plan_gmi(fmt, n, n_snr, MDGMI_PATH_F32_DIRECT, mode).total);
+        pl.total = std::max({pl.total, plan_gmi(fmt, n, n_snr, MDGMI_PATH_F32_DIRECT, mode).total,
+                             plan_gmi(fmt, n, n_snr, MDGMI_PATH_F32_MFMA_BF16SPLIT, mode).total});
     *bytes = pl.total;
     return MDGMI_OK;
 }
@@ -310,8 +316,9 @@ int mdgmi_llr_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t path, s
         *bytes = 0;
     else if (p == MDGMI_PATH_F32_DIRECT)
         *bytes = align_up(direct_image_bytes(fmt, 1));
-    else if (p == MDGMI_PATH_F32_MFMA_F16SPLIT)
-        *bytes = align_up(std::max(mfma_image_bytes(fmt, 1), direct_image_bytes(fmt, 1)));
+    else if (p == MDGMI_PATH_F32_MFMA_F16SPLIT)  // (AUTO may also resolve to direct or bf16)
+        *bytes = align_up(std::max({mfma_image_bytes(fmt, 1), direct_image_bytes(fmt, 1),
+                                    path == MDGMI_PATH_AUTO ? mfma_image_bytes(fmt, 1, 1) : size_t(0)}));
     else if (p == MDGMI_PATH_F32_MFMA_BF16SPLIT)
         *bytes = align_up(mfma_image_bytes(fmt, 1, 1));
     else

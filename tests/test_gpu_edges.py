@@ -182,3 +182,22 @@ def test_bf16_split_beyond_the_fp16_range(orc):
         assert np.max(np.abs(out[0, :2] - ref[:2])) <= 1e-4
         lam = mdgmi.mdgmi_llr(gf, dev(y, torch.float32), s2, path="mfma_bf16").cpu().numpy().astype(np.float64)
         assert llr_ratio(lam, orc.llr(y, f.X, f.labels, s2)) <= 1.0
+
+
+def test_auto_takes_the_bf16_split_beyond_the_fp16_range(orc):
+    """AUTO on a large format at an SNR outside the fp16 split's range runs
+    the bf16 split (bit-identical to asking for it) rather than the slower
+    direct path; within range it keeps the fp16 split."""
+    f = w.random_shells(8, 256, 19)
+    gf = mdgmi.Format.of(f)
+    mdgmi.mdgmi_tune_clear()
+    for snr, expect in ((45.0, "mfma_bf16"), (10.0, "mfma")):
+        s2 = float(w.sigma2_from_snr_db(snr, 8))
+        y, tx = w.channel_samples(f, s2, seed=4, snr_slot=0, n=2500)
+        yd, td = dev(y[None], torch.float32), dev_u32(tx[None])
+        auto = mdgmi.mdgmi_gmi(gf, yd, td, [s2], path="auto").cpu().numpy()
+        same = mdgmi.mdgmi_gmi(gf, yd, td, [s2], path=expect).cpu().numpy()
+        np.testing.assert_array_equal(auto, same)
+        ref = orc.gmi(y.astype(np.float32).astype(np.float64), tx, f.X, f.labels, s2)
+        assert np.max(np.abs(auto[0, :2] - ref[:2])) <= 1e-4
+        say(f"[edge] AUTO at {snr} dB -> {expect}: GMI {auto[0, 0]:.6f}")
