@@ -148,7 +148,7 @@ def learned_leg(gf, wl, args, log):
     snr = np.asarray(wl.snr_db, dtype=np.float64)
     n_snr = snr.size
     n_eval = max(1024, int(args.learned_eval) // n_snr)
-    ev, y, tx = learned.evaluate(tr.net, gf, snr, n_eval)
+    ev, y, tx = learned.evaluate(tr.net, gf, snr, n_eval, sopt=True)
     s2 = learned.sigma2_of(snr, gf.dim)
     stream = torch.cuda.current_stream()
     out = torch.empty((n_snr, mdgmi.MDGMI_NFIELDS), dtype=torch.float64, device="cuda")
@@ -182,6 +182,8 @@ def learned_leg(gf, wl, args, log):
         "snr_db": [float(v) for v in snr],
         "gmi_exact": [float(v) for v in ev.gmi_exact], "gmi_learned": [float(v) for v in ev.gmi_learned],
         "gmi_loss": [float(v) for v in ev.loss], "route": ev.route,
+        "s_opt_learned": [float(v) for v in ev.s_opt],
+        "gmi_loss_sopt": [float(a - b) for a, b in zip(ev.gmi_exact, ev.gmi_learned_sopt)],
         "n_learned_snr": int(sum(routed)), "max_loss_bound": 0.01,
         "note": "learned value counts n*M sample*points per sample demapped by the network; mixed routes "
                 "each SNR point to the learned kernel where its paired GMI loss <= 0.01 bit, else exact",

@@ -112,10 +112,12 @@ class Evaluation:
     loss: list                   # GMI_exact - GMI_learned, paired
     route: list                  # "learned" or "exact" per SNR
     gmi: list                    # the routed estimate
+    s_opt: list = field(default_factory=list)         # s maximising GMI(s) of the learned LLRs
+    gmi_learned_sopt: list = field(default_factory=list)  # GMI(s*) of the learned LLRs
 
 
 def evaluate(net: mdgmi.MLP, gf: mdgmi.Format, snr_db, n: int, seed: int = 99, max_loss: float = 0.01,
-             path: str = "mfma", snr_slot0: int = 5_000_000):
+             path: str = "mfma", snr_slot0: int = 5_000_000, sopt: bool = False):
     """Paired learned vs exact GMI on the same held-out device samples, and
     the per-SNR route."""
     import torch
@@ -128,4 +130,28 @@ def evaluate(net: mdgmi.MLP, gf: mdgmi.Format, snr_db, n: int, seed: int = 99, m
     ok = np.isfinite(le[:, 0]) & (loss <= max_loss)
     route = ["learned" if v else "exact" for v in ok]
     gmi = np.where(ok, le[:, 0], ex[:, 0])
-    return Evaluation(list(snr), list(ex[:, 0]), list(le[:, 0]), list(loss), route, list(gmi)), y, tx
+    ev = Evaluation(list(snr), list(ex[:, 0]), list(le[:, 0]), list(loss), route, list(gmi))
+    if sopt:
+        ev.s_opt, ev.gmi_learned_sopt = sopt_of_learned(net, gf, y, tx, snr)
+    return ev, y, tx
+
+
+def sopt_of_learned(net: mdgmi.MLP, gf: mdgmi.Format, y, tx, snr_db, chunk: int = 1 << 20):
+    """Per SNR point, the s-optimised GMI of the network's LLRs (a decoder
+    that scales them by s): the learned LLRs of every sample are formed in
+    chunks, then mdgmi_gmi_sopt finds s*."""
+    import torch
+    s_opt, g_opt = [], []
+    n = y.shape[1]
+    lam = torch.empty((n, gf.m), dtype=torch.float32, device="cuda")
+    x = torch.empty((min(chunk, n), gf.dim + 1), dtype=torch.float32, device="cuda")
+    for q, v in enumerate(snr_db):
+        for c0 in range(0, n, chunk):
+            c1 = min(n, c0 + chunk)
+            xs = x[: c1 - c0]
+            mdgmi.mdgmi_mlp_features(y[q, c0:c1].contiguous(), float(v), x=xs)
+            net.forward(xs, out=lam[c0:c1])
+        o = mdgmi.mdgmi_gmi_sopt(gf, lam, tx[q]).cpu().numpy()
+        s_opt.append(float(o[mdgmi.FIELDS_S.index("s_opt")]))
+        g_opt.append(float(o[mdgmi.FIELDS_S.index("gmi_sopt")]))
+    return s_opt, g_opt

@@ -57,10 +57,13 @@ def test_training_lowers_loss_and_approaches_exact_gmi(qam16):
     res = tr.train(log=say)
     first, last = res.losses[0][1], res.losses[-1][1]
     assert last < 0.5 * first
-    ev, _, _ = learned.evaluate(tr.net, gf, [4.0, 8.0, 12.0], 20000)
-    say(f"[learned] exact {ev.gmi_exact} learned {ev.gmi_learned}")
+    ev, _, _ = learned.evaluate(tr.net, gf, [4.0, 8.0, 12.0], 20000, sopt=True)
+    say(f"[learned] exact {ev.gmi_exact} learned {ev.gmi_learned} s* {ev.s_opt} GMI(s*) {ev.gmi_learned_sopt}")
     assert max(ev.loss) < 0.1          # 16-QAM is easy for a small network
     assert min(ev.loss) > -0.01        # a mismatched metric cannot beat the exact GMI by more than MC noise
+    # the s-optimised GMI of the learned LLRs: at least GMI(1), at most the exact GMI (within MC noise)
+    for g1, gs, ge in zip(ev.gmi_learned, ev.gmi_learned_sopt, ev.gmi_exact):
+        assert gs >= g1 - 1e-6 and gs <= ge + 0.01
 
 
 def test_fallback_routes_to_exact(qam16):
