@@ -80,10 +80,77 @@ def parse():
     ap.add_argument("--no-paper-formats", action="store_true", help="skip the PAM-N / QAM-N sweep")
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming-monitor leg")
     ap.add_argument("--no-bf16", action="store_true", help="skip timing the bf16-split MFMA path beside")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip the 16-QAM FP64 and 4-D M=64 configurations")
     ap.add_argument("--ragged-scale", type=float, default=1.0, help="scale of the ragged sample counts")
     ap.add_argument("--copy-probe", type=float, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration) and exit")
     return ap.parse_args()
+
+
+def other_configs_leg(cpu_samples=20_000):
+    """The two other single-GPU configurations beside the timed one, GPU and
+    FP64 oracle on identical samples: 16-QAM (11 SNR x 1e5) on the FP64 GPU
+    path against the oracle over all samples, and the 4-D M = 64 workload
+    (21 SNR x 1e7) on every FP32 path, with the oracle timed and compared on
+    the first cpu_samples samples of each SNR point."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import workloads as w
+    from paper_2011_13695_amd import mdgmi
+
+    def gpu_time(gf, y, tx, s2, path, reps=3):
+        ws = mdgmi.workspace(mdgmi.mdgmi_gmi_workspace_size(gf, y.shape[1], len(s2), path))
+        out = mdgmi.mdgmi_gmi(gf, y, tx, s2, path=path, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            mdgmi.mdgmi_gmi(gf, y, tx, s2, path=path, ws=ws, out=out)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, out.cpu().numpy()
+
+    res = {}
+    # 16-QAM, FP64 on the GPU, every sample through the oracle
+    wl = w.workload_qam16()
+    f = wl.fmt
+    gf = mdgmi.Format.of(f)
+    y, tx = mdgmi.mdgmi_generate(gf, wl.seed, wl.sigma2, wl.n, dtype=torch.float64)
+    t, out = gpu_time(gf, y, tx, wl.sigma2, "f64")
+    yh, th = y.cpu().numpy(), tx.cpu().numpy().view(np.uint32)
+    t0 = time.perf_counter()
+    ref = oracle.gmi_per_snr(yh, th, f.X, f.labels, wl.sigma2)
+    tc = time.perf_counter() - t0
+    pairs = len(wl.sigma2) * wl.n * f.M
+    res["16qam_f64"] = {"workload": wl.name, "gpu_f64_value": pairs / t, "gpu_ms": t * 1e3,
+                        "oracle_value": pairs / tc, "oracle_cores": oracle.num_threads(),
+                        "max_abs_dgmi_dmi_vs_oracle": float(np.abs(out[:, :2] - ref[:, :2]).max())}
+    del y, tx
+    # 4-D M = 64
+    wl = w.workload_4d64()
+    f = wl.fmt
+    gf = mdgmi.Format.of(f)
+    y, tx = mdgmi.mdgmi_generate(gf, wl.seed, wl.sigma2, wl.n, dtype=torch.float32)
+    pairs = len(wl.sigma2) * wl.n * f.M
+    row = {"workload": wl.name}
+    for path in ("direct", "mfma", "mfma_bf16", "auto"):
+        t, out = gpu_time(gf, y, tx, wl.sigma2, path)
+        row[path] = {"value": pairs / t, "ms": t * 1e3, "exp_peak_frac": pairs / t / EXP_PEAK}
+    ys = y[:, :cpu_samples].contiguous()
+    ts = tx[:, :cpu_samples].contiguous()
+    _, sub = gpu_time(gf, ys, ts, wl.sigma2, "auto", reps=1)
+    yh, th = ys.cpu().numpy().astype(np.float64), ts.cpu().numpy().view(np.uint32)
+    t0 = time.perf_counter()
+    ref = oracle.gmi_per_snr(yh, th, f.X, f.labels, wl.sigma2)
+    tc = time.perf_counter() - t0
+    row["oracle_value"] = len(wl.sigma2) * cpu_samples * f.M / tc
+    row["oracle_sample"] = f"first {cpu_samples} samples of each SNR point"
+    row["max_abs_dgmi_dmi_vs_oracle_on_sample"] = float(np.abs(sub[:, :2] - ref[:, :2]).max())
+    res["4d64"] = row
+    del y, tx, ys, ts
+    torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(wl, target_s: float):
@@ -539,6 +606,10 @@ def main():
         y = tx = None  # the workload's 5.7 GB are not needed any more
         torch.cuda.empty_cache()
         extra["stream"] = stream_leg()
+    if not args.no_other_configs:
+        y = tx = None
+        torch.cuda.empty_cache()
+        extra["other_configs"] = other_configs_leg()
     achieved = pairs / (kernel_ms * 1e-3)
     line = {
         "metric": METRIC,
