@@ -60,6 +60,7 @@ FORMATS = {
     "sh8d-512": lambda: w.random_shells(8, 512, 14),
     "sh2d-4096": lambda: w.random_shells(2, 4096, 15),
     "sh8d-4096": lambda: w.random_shells(8, 4096, 16),
+    "sh4d-4096": lambda: w.random_shells(4, 4096, 17),
     "qp8d-256": lambda: w.qam_product(8, 8),
     "qp4d-32": lambda: w.qam_product(4, 5),
 }
@@ -85,7 +86,7 @@ LLR_CASES = [
     ("8d2048", 2.0), ("8d2048", 17.0),
     ("qpsk", 5.0), ("bpsk2d", 3.0), ("8psk", 14.0),
     ("sh2d-32", 10.0), ("sh4d-128", 20.0), ("sh8d-16", 6.0), ("sh8d-512", 12.0),
-    ("sh2d-4096", 25.0), ("sh8d-4096", 9.0), ("qp8d-256", 15.0), ("qp4d-32", 22.0),
+    ("sh2d-4096", 25.0), ("sh8d-4096", 9.0), ("sh4d-4096", 14.0), ("qp8d-256", 15.0), ("qp4d-32", 22.0),
 ]
 
 

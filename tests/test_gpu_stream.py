@@ -143,3 +143,35 @@ def test_f64_path_stream(orc):
     st.close()
     ref = orc.gmi(np.concatenate([a for a, _ in ys]), np.concatenate([b for _, b in ys]), f.X, f.labels, s2)
     assert np.max(np.abs(tot[:2] - ref[:2])) <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["16qam", "8d2048"])
+def test_benchmark_configuration(orc, name):
+    """2^22-sample buffers on 4 lanes, as the benchmark times them: every
+    row bit-identical to mdgmi_gmi on that buffer (itself checked against
+    the oracle at full size elsewhere), the total equal to the sample-weighted
+    rows, and 512 sampled samples of the last buffer against the oracle's
+    per-sample costs."""
+    f = w.format_16qam() if name == "16qam" else w.format_8d2048()
+    gf = mdgmi.Format.of(f)
+    s2 = float(w.sigma2_from_snr_db(10.0, f.dim))
+    nb = 1 << 22
+    y, tx = mdgmi.mdgmi_generate(gf, 77, [s2] * 3, nb, dtype=torch.float32)
+    st = mdgmi.Stream(gf, s2, nb, n_lanes=4, path="auto")
+    for k in range(3):
+        st.push(y[k], tx[k])
+    rows = np.array([st.result(k) for k in range(3)])
+    tot = st.total()
+    st.close()
+    for k in range(3):
+        one = mdgmi.mdgmi_gmi(gf, y[k:k + 1], tx[k:k + 1], [s2], path="auto").cpu().numpy()[0]
+        np.testing.assert_array_equal(rows[k], one)
+    assert abs(np.mean(rows[:, 0]) - tot[0]) <= 1e-12 and tot[4] == 3 * nb
+    idx = torch.from_numpy(np.sort(np.random.default_rng(3).choice(nb, 512, replace=False))).cuda()
+    ys = y[2].index_select(0, idx).cpu().numpy().astype(np.float64)
+    ts = tx[2].index_select(0, idx).cpu().numpy().view(np.uint32)
+    cg, cm = orc.costs(ys, ts, f.X, f.labels, s2)
+    # the sampled costs' mean estimates the buffer's GMI/MI within Monte-Carlo error
+    se_g = np.std(cg, ddof=1) / np.sqrt(len(cg))
+    assert abs((f.m - cg.mean()) - rows[2, 0]) <= 5 * se_g + 1e-9
+    say(f"[stream] {name} 2^22 x 3 on 4 lanes: GMI {tot[0]:.5f}")
