@@ -75,21 +75,35 @@ def density_gmi_mi_2d(X, labels, sigma2, n_grid: int = 801, span: float = 9.0):
     return _density_terms(lp, labels, M, m, dA)
 
 
-def _density_terms(lp, labels, M, m, dvol):
-    """lp[g, j] = log p(y_g | x_j). Returns (sum_k I(B_k;Y), I(X;Y)) in bits."""
+def _density_terms(lp, labels, M, m, dvol, per_bit=False):
+    """lp[g, j] = log p(y_g | x_j). Returns (sum_k I(B_k;Y), I(X;Y)) in bits,
+    or with per_bit the list of I(B_k;Y) instead of their sum."""
     labels = np.asarray(labels, dtype=np.int64)
     lpy = _logsumexp(lp, 1) - math.log(M)                    # log p(y)
     py_j = np.exp(lp)                                        # p(y | x_j)
     # I(X;Y) = (1/M) sum_j int p(y|x_j) log2(p(y|x_j)/p(y)) dy
     mi = float(np.sum(py_j * (lp - lpy[:, None])) * dvol / M) * LOG2E
-    gmi = 0.0
+    bits = []
     for k in range(m):
+        ik = 0.0
         for b in (0, 1):
             sel = ((labels >> k) & 1) == b
             lpb = _logsumexp(lp[:, sel], 1) - math.log(sel.sum())   # log p(y | b_k = b)
             pb = np.exp(lpb)
-            gmi += 0.5 * float(np.sum(pb * (lpb - lpy)) * dvol) * LOG2E
-    return gmi, mi
+            ik += 0.5 * float(np.sum(pb * (lpb - lpy)) * dvol) * LOG2E
+        bits.append(ik)
+    return (bits if per_bit else sum(bits)), mi
+
+
+def density_bitwise_1d(X, labels, sigma2, n_grid: int = 20001, span: float = 9.0):
+    """[I(B_k; Y) for each label bit k] of a 1-D constellation (bits)."""
+    x = np.asarray(X, dtype=np.float64).reshape(-1)
+    M = x.size
+    m = int(M).bit_length() - 1
+    s = math.sqrt(sigma2)
+    y = np.linspace(x.min() - span * s, x.max() + span * s, n_grid)
+    lp = -((y[:, None] - x[None, :]) ** 2) / (2 * sigma2) - 0.5 * math.log(2 * math.pi * sigma2)
+    return _density_terms(lp, labels, M, m, y[1] - y[0], per_bit=True)[0]
 
 
 def oracle_expectation(oracle_costs, X, labels, sigma2, n: int = 40):
