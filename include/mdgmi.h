@@ -221,6 +221,18 @@ int mdgmi_gmi_sopt_workspace_size(int64_t n, size_t* bytes);
 int mdgmi_gmi_sopt(const mdgmi_format* fmt, const void* llr, int32_t llr_is_f64, const uint32_t* tx_idx,
                    int64_t n, double* out, void* ws, size_t ws_bytes, void* stream);
 
+/* Per-bit GMI of given LLRs (the LLRs as given, s = 1): for each label bit k
+ *   GMI_k = 1 - (1/n) sum_i log2(1 + exp(-(2 b_k(i) - 1) lambda_ik)),
+ * the bit's share of the GMI (sum_k GMI_k = MDGMI_S_GMI1 of mdgmi_gmi_sopt).
+ *   llr, tx_idx as for mdgmi_gmi_sopt
+ *   out    device [2 m + 2] double: out[2k] = GMI_k, out[2k+1] its standard
+ *          error (k < m), out[2m] = n, out[2m+1] = samples with a non-finite
+ *          cost (those make the GMI_k NaN)
+ *   ws     device workspace of mdgmi_gmi_bits_workspace_size bytes */
+int mdgmi_gmi_bits_workspace_size(int64_t n, size_t* bytes);
+int mdgmi_gmi_bits(const mdgmi_format* fmt, const void* llr, int32_t llr_is_f64, const uint32_t* tx_idx,
+                   int64_t n, double* out, void* ws, size_t ws_bytes, void* stream);
+
 /* ---- streaming monitor ---------------------------------------------------
  * GMI/MI of a receiver's output as it arrives, in fixed-size buffers (the
  * paper's receiver processes its ADC stream in buffers of 2^22 samples on

@@ -380,6 +380,25 @@ int mdgmi_gmi_sopt(const mdgmi_format* fmt, const void* llr, int32_t llr_is_f64,
     return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
 }
 
+int mdgmi_gmi_bits_workspace_size(int64_t n, size_t* bytes) {
+    if (!bytes) return MDGMI_E_NULL;
+    if (n < 1) return MDGMI_E_SHAPE;
+    *bytes = bits_workspace_bytes(n);
+    return MDGMI_OK;
+}
+
+int mdgmi_gmi_bits(const mdgmi_format* fmt, const void* llr, int32_t llr_is_f64, const uint32_t* tx_idx, int64_t n,
+                   double* out, void* ws, size_t ws_bytes, void* stream) {
+    if (!fmt || !llr || !tx_idx || !out) return MDGMI_E_NULL;
+    if (n < 1) return MDGMI_E_SHAPE;
+    if (llr_is_f64 != 0 && llr_is_f64 != 1) return MDGMI_E_ARG;
+    if (!ws || ws_bytes < bits_workspace_bytes(n)) return MDGMI_E_WORKSPACE;
+    int rc = check_device(fmt);
+    if (rc != MDGMI_OK) return rc;
+    hipError_t e = launch_bits(fmt, llr, llr_is_f64 == 1, tx_idx, n, out, ws, (hipStream_t)stream);
+    return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+}
+
 double mdgmi_q_factor_db(double ber) {
     if (!(ber >= 0.0 && ber <= 0.5)) return std::numeric_limits<double>::quiet_NaN();
     if (ber == 0.0) return std::numeric_limits<double>::infinity();

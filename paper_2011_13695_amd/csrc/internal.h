@@ -104,6 +104,9 @@ hipError_t launch_exact(const mdgmi_format* f, int path, const void* y, const ui
                         hipStream_t st);
 
 size_t sopt_workspace_bytes(int64_t n);
+size_t bits_workspace_bytes(int64_t n);
+hipError_t launch_bits(const mdgmi_format* f, const void* llr, bool f64, const uint32_t* tx, int64_t n, double* out,
+                       void* ws, hipStream_t st);
 hipError_t launch_sopt(const mdgmi_format* f, const void* llr, bool f64, const uint32_t* tx, int64_t n, double* out,
                        void* ws, hipStream_t st);
 hipError_t launch_reduce(const double* part, int n_snr, int blocks_per_snr, int64_t n, int m,

@@ -1,4 +1,5 @@
-// s-optimised GMI of given LLRs (any demapper: exact, max-log, learned).
+// s-optimised GMI and per-bit GMI of given LLRs (any demapper: exact,
+// max-log, learned).
 //
 // For LLRs lambda_ik and sent bits b_k(i), with v_ik = (2 b_k(i) - 1) lambda_ik,
 //     GMI(s) = m - (1/n) sum_i sum_k log2(1 + exp(-s v_ik)),   s >= 0,
@@ -165,6 +166,62 @@ __global__ __launch_bounds__(256) void k_sopt_update(const double* __restrict__ 
     if (hi < INFINITY && hi - lo <= tol * hi) state[kStDone] = 1.0;
 }
 
+// ---- per-bit GMI of given LLRs (s = 1) ---------------------------------
+// GMI_k = 1 - mean_i log2(1 + exp(-v_ik)): per-bit FP64 sums of the cost and
+// its square, one pass, then a one-block finish in a fixed order.
+constexpr int kBitsPart = 2 * MDGMI_MAX_BITS + 1;
+
+template <typename T>
+__global__ __launch_bounds__(kSoptThreads) void k_bits_pass(const T* __restrict__ llr,
+                                                             const uint32_t* __restrict__ tx,
+                                                             const uint32_t* __restrict__ labels, int M, int64_t n,
+                                                             int m, double* __restrict__ part) {
+    double v[kBitsPart] = {};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t row = tx[i];
+        const bool row_ok = row < (uint32_t)M;
+        const uint32_t slot = labels[row_ok ? row : 0u];
+        bool fin = row_ok;
+#pragma unroll
+        for (int k = 0; k < MDGMI_MAX_BITS; k++) {
+            if (k < m) {
+                const T lam = llr[i * m + k];
+                const T u = ((slot >> k) & 1u) ? -lam : lam;   // cost = log(1 + e^u)
+                double c = (double)((u > T(0) ? u : T(0)) + log1p(exp(-fabs(u)))) * kLog2e;
+                if (!row_ok) c = NAN;
+                fin = fin && __builtin_isfinite(c);
+                v[2 * k] += c;
+                v[2 * k + 1] += c * c;
+            }
+        }
+        v[2 * MDGMI_MAX_BITS] += fin ? 0.0 : 1.0;
+    }
+    block_reduce_vals<kBitsPart>(v, part + (size_t)blockIdx.x * kBitsPart);
+}
+
+__global__ __launch_bounds__(256) void k_bits_finish(const double* __restrict__ part, int nblocks, int64_t n, int m,
+                                                     double* __restrict__ out) {
+    double v[kBitsPart] = {};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < kBitsPart; k++) v[k] += part[(size_t)b * kBitsPart + k];
+    }
+    __shared__ double tot[kBitsPart];
+    block_reduce_vals<kBitsPart>(v, tot);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double N = (double)n;
+    for (int k = 0; k < m; k++) {
+        const double s1 = tot[2 * k], s2 = tot[2 * k + 1];
+        const double var = n > 1 ? (s2 - s1 * s1 / N) / (N - 1.0) : 0.0;
+        out[2 * k] = 1.0 - s1 / N;
+        out[2 * k + 1] = sqrt(fmax(var, 0.0) / N);
+    }
+    out[2 * m] = N;
+    out[2 * m + 1] = tot[2 * MDGMI_MAX_BITS];
+}
+
 int sopt_blocks(int64_t n) {
     const int64_t want = (n + kSoptThreads - 1) / kSoptThreads;
     const int64_t cap = (int64_t)device_cu_count() * 8;
@@ -172,6 +229,22 @@ int sopt_blocks(int64_t n) {
 }
 
 }  // namespace
+
+size_t bits_workspace_bytes(int64_t n) { return (size_t)sopt_blocks(n) * kBitsPart * sizeof(double); }
+
+hipError_t launch_bits(const mdgmi_format* f, const void* llr, bool f64, const uint32_t* tx, int64_t n, double* out,
+                       void* ws, hipStream_t st) {
+    double* part = (double*)ws;
+    const int nb = sopt_blocks(n);
+    if (f64)
+        hipLaunchKernelGGL(k_bits_pass<double>, dim3(nb), dim3(kSoptThreads), 0, st, (const double*)llr, tx,
+                           f->d_labels, f->M, n, f->m, part);
+    else
+        hipLaunchKernelGGL(k_bits_pass<float>, dim3(nb), dim3(kSoptThreads), 0, st, (const float*)llr, tx,
+                           f->d_labels, f->M, n, f->m, part);
+    hipLaunchKernelGGL(k_bits_finish, dim3(1), dim3(256), 0, st, part, nb, n, f->m, out);
+    return hipGetLastError();
+}
 
 size_t sopt_workspace_bytes(int64_t n) {
     return (size_t)(kStateLen + (size_t)sopt_blocks(n) * kSoptPart) * sizeof(double);

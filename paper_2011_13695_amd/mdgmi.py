@@ -80,6 +80,8 @@ def lib():
         L.mdgmi_gmi_maxlog.argtypes = L.mdgmi_gmi.argtypes
         L.mdgmi_gmi_sopt_workspace_size.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
         L.mdgmi_gmi_sopt.argtypes = [_P, _P, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, ctypes.c_size_t, _P]
+        L.mdgmi_gmi_bits_workspace_size.argtypes = L.mdgmi_gmi_sopt_workspace_size.argtypes
+        L.mdgmi_gmi_bits.argtypes = L.mdgmi_gmi_sopt.argtypes
         L.mdgmi_q_factor_db.restype = ctypes.c_double
         L.mdgmi_q_factor_db.argtypes = [ctypes.c_double]
         L.mdgmi_set_tuning.argtypes = [ctypes.c_int]
@@ -304,6 +306,27 @@ def mdgmi_gmi_sopt(fmt: Format, llr, tx_idx, out=None, ws=None, stream=None):
     if ws is None:
         ws = workspace(mdgmi_gmi_sopt_workspace_size(n))
     _check("mdgmi_gmi_sopt", lib().mdgmi_gmi_sopt(fmt.handle, _dptr(llr), int(llr.dtype == torch.float64),
+                                                  _dptr(tx_idx), n, _dptr(out), _dptr(ws), ws.numel(),
+                                                  _stream(stream)))
+    return out
+
+
+def mdgmi_gmi_bits(fmt: Format, llr, tx_idx, out=None, ws=None, stream=None):
+    """Per-bit GMI of LLRs [n, m] (float32 or float64, nats) for the sent rows
+    tx [n] -> out [2 m + 2] (double): GMI_k and its standard error per bit,
+    then n and the non-finite count."""
+    import torch
+    assert llr.is_cuda and llr.is_contiguous() and tx_idx.is_contiguous()
+    assert llr.dtype in (torch.float32, torch.float64)
+    n = llr.numel() // fmt.m
+    assert llr.numel() == n * fmt.m and tx_idx.numel() == n
+    if out is None:
+        out = torch.empty(2 * fmt.m + 2, dtype=torch.float64, device=llr.device)
+    if ws is None:
+        b = ctypes.c_size_t()
+        _check("mdgmi_gmi_bits_workspace_size", lib().mdgmi_gmi_bits_workspace_size(n, ctypes.byref(b)))
+        ws = workspace(b.value)
+    _check("mdgmi_gmi_bits", lib().mdgmi_gmi_bits(fmt.handle, _dptr(llr), int(llr.dtype == torch.float64),
                                                   _dptr(tx_idx), n, _dptr(out), _dptr(ws), ws.numel(),
                                                   _stream(stream)))
     return out

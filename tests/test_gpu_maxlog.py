@@ -196,3 +196,50 @@ def test_sopt_edge_cases():
     with pytest.raises(mdgmi.MdgmiError) as e:
         mdgmi.mdgmi_gmi_sopt(gf, dev(right, torch.float32), dev_u32(tx), ws=mdgmi.workspace(8))
     assert e.value.code == mdgmi.MDGMI_E_WORKSPACE
+
+
+@pytest.mark.parametrize("source", ["exact", "maxlog"])
+@pytest.mark.parametrize("path", PATHS)
+def test_per_bit_gmi_on_gpu_llrs(orc, source, path):
+    """mdgmi_gmi_bits on the LLRs the GPU produced, against the oracle's
+    per-bit GMI of the same values; the bits sum to the GMI at s = 1."""
+    f = w.format_16qam() if path == "direct" else w.format_4d64()
+    gf = mdgmi.Format.of(f)
+    n = 30011
+    s2 = float(w.sigma2_from_snr_db(8.0, f.dim))
+    y, tx = w.channel_samples(f, s2, seed=29, snr_slot=0, n=n)
+    fn = mdgmi.mdgmi_llr if source == "exact" else mdgmi.mdgmi_llr_maxlog
+    lam = fn(gf, dev(y, dt(path)), s2, path=path)
+    out = mdgmi.mdgmi_gmi_bits(gf, lam, dev_u32(tx)).cpu().numpy()
+    so = mdgmi.mdgmi_gmi_sopt(gf, lam, dev_u32(tx)).cpu().numpy()
+    g, se = orc.gmi_bits(lam.cpu().numpy().astype(np.float64), f.labels[tx])
+    tol = 1e-9 if path == "f64" else 1e-6
+    m = f.m
+    assert np.max(np.abs(out[0:2 * m:2] - g)) <= tol
+    np.testing.assert_allclose(out[1:2 * m:2], se, rtol=1e-3)
+    assert out[2 * m] == n and out[2 * m + 1] == 0
+    # same costs, summed per bit vs per sample: FP32 terms round differently
+    assert abs(np.sum(out[0:2 * m:2]) - so[0]) <= (1e-12 if path == "f64" else 1e-6)
+    say(f"[bits] {source} {path}: " + " ".join(f"{v:.4f}" for v in out[0:2 * m:2]))
+
+
+def test_per_bit_gmi_edges():
+    f = w.square_qam(2)
+    gf = mdgmi.Format.of(f)
+    rng = np.random.default_rng(5)
+    n = 777
+    tx = rng.integers(0, 4, n).astype(np.uint32)
+    bits = ((tx[:, None] >> np.arange(2)) & 1).astype(np.float64)
+    lam = (2.0 * bits - 1.0) * 3.0
+    out = mdgmi.mdgmi_gmi_bits(gf, dev(lam, torch.float32), dev_u32(tx)).cpu().numpy()
+    want = 1.0 - np.log2(1.0 + np.exp(-3.0))
+    np.testing.assert_allclose(out[[0, 2]], [want, want], rtol=1e-6)
+    assert out[1] == pytest.approx(0.0, abs=1e-12) and out[4] == n and out[5] == 0
+    bad = lam.copy()
+    bad[3, 1] = np.nan
+    out = mdgmi.mdgmi_gmi_bits(gf, dev(bad, torch.float32), dev_u32(tx)).cpu().numpy()
+    assert out[5] == 1 and np.isnan(out[2])
+    tx2 = tx.copy()
+    tx2[0] = 4
+    out = mdgmi.mdgmi_gmi_bits(gf, dev(lam, torch.float64), dev_u32(tx2)).cpu().numpy()
+    assert out[5] == 1 and np.isnan(out[0]) and np.isnan(out[2])
