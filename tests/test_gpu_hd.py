@@ -206,3 +206,33 @@ def test_hd_workspace_and_errors():
     with pytest.raises(mdgmi.MdgmiError) as e:
         mdgmi.mdgmi_gmi_hd(gf, y, tx, [0.1], path="direct", ws=mdgmi.workspace(8))
     assert e.value.code == mdgmi.MDGMI_E_WORKSPACE
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_hd_and_maxlog_many_snrs_in_one_call(path):
+    """41 SNR points in one call (two launches of at most 32 points, and
+    per-SNR partials of 7 values with hard decisions): every row equals the
+    call for that SNR point alone; error counts are integers, so BER/SER
+    agree exactly, GMI/MI to rounding."""
+    f = w.format_4d64()
+    gf = mdgmi.Format.of(f)
+    snrs = np.linspace(-5.0, 25.0, 41)
+    s2s = w.sigma2_from_snr_db(snrs, 4)
+    n = 1501
+    ys, txs = zip(*(w.channel_samples(f, float(v), seed=61, snr_slot=q, n=n) for q, v in enumerate(s2s)))
+    y = np.stack(ys)
+    tx = np.stack(txs)
+    if path != "f64":
+        y = y.astype(np.float32).astype(np.float64)
+    yd, td = dev(y, dt(path)), dev_u32(tx)
+    out = mdgmi.mdgmi_gmi_hd(gf, yd, td, s2s, path=path).cpu().numpy()
+    ml = mdgmi.mdgmi_gmi_maxlog(gf, yd, td, s2s, path=path).cpu().numpy()
+    for q in (0, 20, 31, 32, 40):
+        one = mdgmi.mdgmi_gmi_hd(gf, yd[q:q + 1].contiguous(), td[q:q + 1].contiguous(), [s2s[q]],
+                                 path=path).cpu().numpy()[0]
+        np.testing.assert_array_equal(out[q, 4:], one[4:])
+        np.testing.assert_allclose(out[q, :4], one[:4], rtol=1e-12, atol=1e-12)
+        mo = mdgmi.mdgmi_gmi_maxlog(gf, yd[q:q + 1].contiguous(), td[q:q + 1].contiguous(), [s2s[q]],
+                                    path=path).cpu().numpy()[0]
+        np.testing.assert_allclose(ml[q, [0, 2]], mo[[0, 2]], rtol=1e-12, atol=1e-12)
+        assert np.isnan(ml[q, 1]) and ml[q, 4] == n
