@@ -6,7 +6,10 @@ step = one mdgmi_gmi call over the whole batch (per-SNR staging, demapping
 with exact per-bit LLRs, fused FP64 GMI/MI reduction). Metric: demapped
 sample*points per second = n_snr * n * M / time.
 
-Beside it: the FP32 direct-distance path on the same samples, the learned
+Beside it: the FP32 direct-distance path and the bf16-split MFMA path on the
+same samples, LLR output, hard decisions (BER/SER/Q), max-log and
+s-optimised GMI, the paper's PAM/QAM formats, the streaming monitor, the
+16-QAM FP64 and 4-D M=64 configurations, the ragged batch, the learned
 demapper (trained on exact-LLR targets, then timed against the exact path on
 the same held-out samples with per-SNR fallback), and the FP64 CPU oracle on
 a bounded sample.

@@ -66,3 +66,43 @@ def test_null_handles_rejected():
     assert L.mdgmi_gmi_workspace_size(None, 10, 1, 1, ctypes.byref(b)) == mdgmi.MDGMI_E_NULL
     assert L.mdgmi_llr(None, None, 10, 1.0, None, 1, None, 0, None) == mdgmi.MDGMI_E_NULL
     assert L.mdgmi_format_destroy(None) == mdgmi.MDGMI_E_NULL
+
+
+def test_new_entry_points_reject_bad_arguments_host_side():
+    """Checks that return before any device call (no GPU needed)."""
+    L = mdgmi.lib()
+    mdgmi._stream_sigs()
+    P = ctypes.c_void_p
+    b = ctypes.c_size_t()
+    assert L.mdgmi_gmi_sopt_workspace_size(0, ctypes.byref(b)) == mdgmi.MDGMI_E_SHAPE
+    assert L.mdgmi_gmi_sopt_workspace_size(10, None) == mdgmi.MDGMI_E_NULL
+    assert L.mdgmi_gmi_bits_workspace_size(0, ctypes.byref(b)) == mdgmi.MDGMI_E_SHAPE
+    assert L.mdgmi_gmi_bits_workspace_size(10, None) == mdgmi.MDGMI_E_NULL
+    assert L.mdgmi_gmi_sopt(None, None, 0, None, 10, None, None, 0, None) == mdgmi.MDGMI_E_NULL
+    assert L.mdgmi_gmi_bits(None, None, 0, None, 10, None, None, 0, None) == mdgmi.MDGMI_E_NULL
+    assert L.mdgmi_gmi_hd_workspace_size(None, 10, 1, 1, ctypes.byref(b)) == mdgmi.MDGMI_E_NULL
+    assert L.mdgmi_gmi_hd(None, None, None, 10, None, 1, 1, None, None, 0, None) == mdgmi.MDGMI_E_NULL
+    assert L.mdgmi_gmi_maxlog(None, None, None, 10, None, 1, 1, None, None, 0, None) == mdgmi.MDGMI_E_NULL
+    assert L.mdgmi_llr_maxlog(None, None, 10, 1.0, None, 1, None, 0, None) == mdgmi.MDGMI_E_NULL
+    h = P()
+    assert L.mdgmi_stream_create(None, 1.0, 10, 1, 1, 4, ctypes.byref(h)) == mdgmi.MDGMI_E_NULL
+    assert L.mdgmi_stream_push(None, None, None, 10, 0, None) == mdgmi.MDGMI_E_NULL
+    assert L.mdgmi_stream_wait(None, 0) == mdgmi.MDGMI_E_NULL
+    assert L.mdgmi_stream_total(None, None) == mdgmi.MDGMI_E_NULL
+    assert L.mdgmi_stream_destroy(None) == mdgmi.MDGMI_E_NULL
+
+
+def test_bench_refuses_several_gpus_and_interpolates_q_thresholds():
+    import json
+    import sys
+
+    out = subprocess.run([sys.executable, "bench.py", "--gpus", "2"], capture_output=True, text=True,
+                         cwd=str(mdgmi.LIB_PATH.parents[1]), timeout=120)
+    assert out.returncode == 2
+    assert "single-GPU" in json.loads(out.stdout.strip().splitlines()[-1])["error"]
+    sys.path.insert(0, str(mdgmi.LIB_PATH.parents[1]))
+    import bench
+    snr = [0.0, 1.0, 2.0, 3.0]
+    assert bench.q_crossing(snr, [1.0, 2.0, 3.0, 4.0], 2.5) == pytest.approx(1.5)
+    assert bench.q_crossing(snr, [1.0, 2.0, None, None], 8.4) == pytest.approx(2.0)   # BER 0: Q unbounded
+    assert bench.q_crossing(snr, [1.0, 2.0, 3.0, 4.0], 9.0) is None
