@@ -114,6 +114,17 @@ def _path(path) -> int:
     return PATHS[path] if isinstance(path, str) else int(path)
 
 
+def _check_y(y, path: int, tx_idx=None):
+    """The element type of y follows the path (double on the FP64 path, float
+    otherwise; AUTO never resolves to FP64); sent rows are 32-bit."""
+    import torch
+    want = torch.float64 if path == MDGMI_PATH_F64 else torch.float32
+    if y.dtype != want:
+        raise TypeError(f"y must be {want} on this path, got {y.dtype}")
+    if tx_idx is not None and tx_idx.dtype not in (torch.int32, torch.uint32):
+        raise TypeError(f"tx_idx must be a 32-bit integer tensor, got {tx_idx.dtype}")
+
+
 def mdgmi_status_string(code: int) -> str:
     return lib().mdgmi_status_string(int(code)).decode()
 
@@ -202,6 +213,7 @@ def mdgmi_llr(fmt: Format, y, sigma2: float, path="auto", llr=None, ws=None, str
     assert y.is_cuda and y.is_contiguous() and y.shape[-1] == fmt.dim
     n = y.numel() // fmt.dim
     p = _path(path)
+    _check_y(y, p)
     if llr is None:
         llr = torch.empty((n, fmt.m), dtype=y.dtype, device=y.device)
     if ws is None:
@@ -220,6 +232,7 @@ def mdgmi_gmi(fmt: Format, y, tx_idx, sigma2, path="auto", out=None, ws=None, st
     n = y.numel() // (fmt.dim * n_snr)
     assert y.numel() == n_snr * n * fmt.dim and tx_idx.numel() == n_snr * n
     p = _path(path)
+    _check_y(y, p, tx_idx)
     if out is None:
         out = torch.empty((n_snr, MDGMI_NFIELDS), dtype=torch.float64, device=y.device)
     if ws is None:
@@ -245,6 +258,7 @@ def mdgmi_gmi_hd(fmt: Format, y, tx_idx, sigma2, path="auto", out=None, ws=None,
     n = y.numel() // (fmt.dim * n_snr)
     assert y.numel() == n_snr * n * fmt.dim and tx_idx.numel() == n_snr * n
     p = _path(path)
+    _check_y(y, p, tx_idx)
     if out is None:
         out = torch.empty((n_snr, MDGMI_NFIELDS_HD), dtype=torch.float64, device=y.device)
     if ws is None:
@@ -260,6 +274,7 @@ def mdgmi_llr_maxlog(fmt: Format, y, sigma2: float, path="auto", llr=None, ws=No
     assert y.is_cuda and y.is_contiguous() and y.shape[-1] == fmt.dim
     n = y.numel() // fmt.dim
     p = _path(path)
+    _check_y(y, p)
     if llr is None:
         llr = torch.empty((n, fmt.m), dtype=y.dtype, device=y.device)
     if ws is None:
@@ -278,6 +293,7 @@ def mdgmi_gmi_maxlog(fmt: Format, y, tx_idx, sigma2, path="auto", out=None, ws=N
     n = y.numel() // (fmt.dim * n_snr)
     assert y.numel() == n_snr * n * fmt.dim and tx_idx.numel() == n_snr * n
     p = _path(path)
+    _check_y(y, p, tx_idx)
     if out is None:
         out = torch.empty((n_snr, MDGMI_NFIELDS), dtype=torch.float64, device=y.device)
     if ws is None:
@@ -360,6 +376,7 @@ class Stream:
                                                             _path(path), int(ring), ctypes.byref(h)))
         self.handle = h
         self._inflight = {}
+        self.path = self.info()[1]
 
     def push(self, y, tx_idx) -> int:
         """y [n, dim], tx [n]: torch tensors (device: read in place; CPU,
@@ -368,11 +385,12 @@ class Stream:
         import torch
         if isinstance(y, torch.Tensor):
             assert y.is_contiguous() and tx_idx.is_contiguous()
+            _check_y(y, self.path, tx_idx)
             host = int(not y.is_cuda)
             yp, tp = _P(y.data_ptr()), _P(tx_idx.data_ptr())
             n = y.numel() // self.fmt.dim
         else:
-            y = np.ascontiguousarray(y)
+            y = np.ascontiguousarray(y, dtype=np.float64 if self.path == MDGMI_PATH_F64 else np.float32)
             tx_idx = np.ascontiguousarray(tx_idx, dtype=np.uint32)
             host, yp, tp, n = 1, y.ctypes.data_as(_P), tx_idx.ctypes.data_as(_P), y.size // self.fmt.dim
         idx = ctypes.c_int64()

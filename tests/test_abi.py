@@ -106,3 +106,22 @@ def test_bench_refuses_several_gpus_and_interpolates_q_thresholds():
     assert bench.q_crossing(snr, [1.0, 2.0, 3.0, 4.0], 2.5) == pytest.approx(1.5)
     assert bench.q_crossing(snr, [1.0, 2.0, None, None], 8.4) == pytest.approx(2.0)   # BER 0: Q unbounded
     assert bench.q_crossing(snr, [1.0, 2.0, 3.0, 4.0], 9.0) is None
+
+
+def test_binding_checks_element_types():
+    """The C ABI reads y as double on the FP64 path and float otherwise; the
+    binding refuses a tensor of the other type instead of passing its bytes."""
+    torch = pytest.importorskip("torch")
+    y64 = torch.zeros((4, 2), dtype=torch.float64)
+    y32 = torch.zeros((4, 2), dtype=torch.float32)
+    tx = torch.zeros(4, dtype=torch.int32)
+    mdgmi._check_y(y64, mdgmi.MDGMI_PATH_F64, tx)
+    for p in (mdgmi.MDGMI_PATH_AUTO, mdgmi.MDGMI_PATH_F32_DIRECT, mdgmi.MDGMI_PATH_F32_MFMA_F16SPLIT,
+              mdgmi.MDGMI_PATH_F32_MFMA_BF16SPLIT):
+        mdgmi._check_y(y32, p, tx)
+        with pytest.raises(TypeError):
+            mdgmi._check_y(y64, p)
+    with pytest.raises(TypeError):
+        mdgmi._check_y(y32, mdgmi.MDGMI_PATH_F64)
+    with pytest.raises(TypeError):
+        mdgmi._check_y(y32, mdgmi.MDGMI_PATH_AUTO, tx.to(torch.int64))
