@@ -242,10 +242,15 @@ __device__ inline void block_reduce_store_hd(CostAcc a, HdAcc h, double* dst) {
 // point. t_j = s * ||y - x_j||^2 in log2 units, computed directly.
 // Outputs: lsb[k] = log2 sum_{j in class(k,b)} 2^-t_j  (k < m, b = 0, 1),
 //          ltot = log2 sum_j 2^-t_j,  ti = t of slot `sent` (if sent >= 0).
+// t_j must stay a rounded product: contracted into fma(-s, d, cmin),
+// cmin - t_j of the nearest point would be the product's rounding error
+// instead of 0, thousands of log2 units once t reaches 2^30. Contraction is
+// therefore off in these per-class paths.
 template <int DIM>
 __device__ inline void exact_classes_f32(const float* yv, const float* __restrict__ X32, int M, int m,
                                          float s, int sent, float* ls0, float* ls1, float& ltot, float& ti,
                                          float* tmin_out = nullptr) {
+#pragma clang fp contract(off)
     float cmin0[MDGMI_MAX_BITS], cmin1[MDGMI_MAX_BITS];
     float tmin = INFINITY;
 #pragma unroll
@@ -257,7 +262,7 @@ __device__ inline void exact_classes_f32(const float* yv, const float* __restric
             float e = yv[q] - X32[j * DIM + q];
             d = fmaf(e, e, d);
         }
-        float t = s * d;
+        const float t = s * d;
         tmin = fminf(tmin, t);
 #pragma unroll
         for (int k = 0; k < MDGMI_MAX_BITS; k++) {
@@ -281,7 +286,7 @@ __device__ inline void exact_classes_f32(const float* yv, const float* __restric
             float e = yv[q] - X32[j * DIM + q];
             d = fmaf(e, e, d);
         }
-        float t = s * d;
+        const float t = s * d;
         tot += ex2(tmin - t);
 #pragma unroll
         for (int k = 0; k < MDGMI_MAX_BITS; k++) {
@@ -311,6 +316,7 @@ __device__ inline void exact_classes_f32(const float* yv, const float* __restric
 template <int DIM>
 __device__ inline void class_max_u_f32(const float* yv, const float* __restrict__ X32, int M, int m, float s,
                                        float* u0, float* u1) {
+#pragma clang fp contract(off)
 #pragma unroll
     for (int k = 0; k < MDGMI_MAX_BITS; k++) u0[k] = u1[k] = -INFINITY;
     for (int j = 0; j < M; j++) {
