@@ -28,6 +28,11 @@ FLAGS = [
     f"-I{ROOT / 'include'}",
 ]
 
+# Per-file flags. The 4x4-block MFMA shape keeps its accumulators in
+# ordinary VGPRs: the exponentials read every MFMA result, and AGPR results
+# would cost one extra v_accvgpr_read per (sample, point).
+EXTRA_FLAGS = {"exact_mfma4.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
 
 def sources():
     return sorted(CSRC.glob("*.hip"))
@@ -35,7 +40,7 @@ def sources():
 
 def _compile(src: Path) -> Path:
     obj = BUILD / (src.stem + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", str(src), "-o", str(obj)]
+    cmd = [HIPCC, *FLAGS, *EXTRA_FLAGS.get(src.name, []), "-c", str(src), "-o", str(obj)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src.name}:\n{r.stderr}")

@@ -54,16 +54,19 @@ int resolve_path(const mdgmi_format* f, int path, double max_s, int* out) {
             *out = path;
             return MDGMI_OK;
         case MDGMI_PATH_AUTO: {
-            const bool mfma_ok = f->M >= 32 && mfma_supported(f, max_s);
+            const bool small = small_shape_fits(f);
+            const bool mfma_ok = (f->M >= 32 || small) && mfma_supported(f, max_s);
             const int t = tuned_path(f->dim, f->M);
-            const bool want_mfma = t == MDGMI_PATH_F32_MFMA_F16SPLIT || (t < 0 && f->M >= 128);
+            // untuned: the per-sample 4x4 shape for small formats, the 32 x 32
+            // shape from 128 points; between them the vector-ALU kernel
+            const bool want_mfma = t == MDGMI_PATH_F32_MFMA_F16SPLIT || (t < 0 && (f->M >= 128 || small));
             if (t == MDGMI_PATH_F32_DIRECT)
                 *out = t;
             else if (want_mfma && mfma_ok)
                 *out = MDGMI_PATH_F32_MFMA_F16SPLIT;
-            else if (want_mfma && mfma_supported(f, max_s, 1))
+            else if (want_mfma && f->M >= 128 && mfma_supported(f, max_s, 1))
                 *out = MDGMI_PATH_F32_MFMA_BF16SPLIT;  // beyond the fp16 range: the bf16 split
-            else  // untuned: below 128 points the per-sample work of the MFMA path dominates
+            else
                 *out = MDGMI_PATH_F32_DIRECT;
             return MDGMI_OK;
         }

@@ -165,7 +165,7 @@ int mdgmi_autotune(int32_t dim, int32_t M, int32_t force, mdgmi_tune_entry* out)
         best.direct_rate = time_call(MDGMI_PATH_F32_DIRECT);
         double best_rate = best.direct_rate;
         best.mfma_rate = 0.0;
-        if (M >= 32 && mfma_supported(f, kLog2e / (2.0 * sigma2))) {
+        if ((M >= 32 || small_shape_fits(f)) && mfma_supported(f, kLog2e / (2.0 * sigma2))) {
             for (int v = 0; v < kMfmaVariants; v++) {
                 mdgmi_set_tuning(v);
                 const double r = time_call(MDGMI_PATH_F32_MFMA_F16SPLIT);

@@ -168,7 +168,7 @@ hipError_t launch_d(int var, bool lds, const mdgmi_format* f, const float* y, co
 #undef MDGMI_VG
 }
 
-constexpr int kNumVariants = kMfmaVariants;
+constexpr int kNumVariants = 8;  // 32 x 32 shapes; kSmallVariant follows them
 const MfmaVariant kVariants[kNumVariants] = {{1, 4, true},  {2, 4, true},  {1, 8, true},  {2, 8, true},
                                              {1, 16, true}, {1, 12, true}, {1, 16, false}, {1, 8, false}};
 
@@ -196,6 +196,15 @@ int pick_variant(const mdgmi_format* f) {
     return image_bytes_per_snr(f) > 32 * 1024 ? 4 : 2;
 }
 
+// The per-sample 4x4 shape serves small fp16-split formats unless a 32 x 32
+// variant is asked for (override or tuning table).
+bool use_small(const mdgmi_format* f, int split) {
+    if (split != kSplitF16 || !small_shape_fits(f)) return false;
+    int v = g_variant_override;
+    if (v < 0 || v >= kMfmaVariants) v = tuned_mfma_variant(f->dim, f->M);
+    return v < 0 || v >= kMfmaVariants || v == kSmallVariant;
+}
+
 }  // namespace
 
 bool mfma_supported(const mdgmi_format* f, double max_s, int split) {
@@ -207,10 +216,14 @@ bool mfma_supported(const mdgmi_format* f, double max_s, int split) {
 }
 
 size_t mfma_image_bytes(const mdgmi_format* f, int n_snr, int split) {
-    return (size_t)n_snr * image_bytes_per_snr(f, split);
+    const size_t big = (size_t)n_snr * image_bytes_per_snr(f, split);
+    // either shape may run (the choice follows tuning), so size for both
+    if (split == kSplitF16 && small_shape_fits(f)) return std::max(big, small_image_bytes(f, n_snr));
+    return big;
 }
 
 LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr, int mode, int split) {
+    if (use_small(f, split)) return small_cfg(f, n, n_snr);
     // hard decisions, max-log metrics, 1-D formats and the bf16 split run the
     // 1-column, 16-wave shape only (LDS image if it fits)
     const bool fixed = mode == kModeHd || mode_is_ml(mode) || f->dim == 1 || split == kSplitBF16;
@@ -325,6 +338,7 @@ hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx
                        LaunchCfg cfg, hipStream_t st, int split) {
     const int ntiles = (f->M + 31) / 32;
     uint4* img = (uint4*)image;
+    if (use_small(f, split)) return launch_small(f, y, tx, n, sa, mode, llr, part, image, cfg, st);
     if (split == kSplitBF16)
         return image_and_fixed<kSplitBF16>(f, y, tx, n, sa, mode, llr, part, img, ntiles, cfg, st);
     return image_and_fixed<kSplitF16>(f, y, tx, n, sa, mode, llr, part, img, ntiles, cfg, st);

@@ -24,7 +24,8 @@ struct mdgmi_format {
 
 namespace mdgmi {
 
-constexpr int kMfmaVariants = 8;     // MFMA launch shapes (see mdgmi_set_tuning)
+constexpr int kMfmaVariants = 9;     // MFMA launch shapes (see mdgmi_set_tuning)
+constexpr int kSmallVariant = 8;     // ... the last: one sample per lane, 4x4 MFMA blocks
 constexpr int kNPart = 5;           // per-block FP64 partials: sum cG, sum cG^2, sum cM, sum cM^2, nonfinite
 constexpr int kNPartHd = kNPart + 2; // ... and, with hard decisions, bit errors and symbol errors
 // What a demapper launch produces: GMI/MI partials, LLRs, or GMI/MI partials
@@ -73,6 +74,14 @@ size_t direct_image_bytes(const mdgmi_format* f, int n_snr);
 hipError_t launch_direct(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
                          const SnrArgs& sa, int mode, float* llr, double* part, float* image,
                          LaunchCfg cfg, hipStream_t st);
+
+// Per-sample 4x4-block shape of the fp16-split path for 4 <= M <= 256
+// (8-D: M <= 64), exact_mfma4.hip; used by launch_mfma where it applies.
+bool small_shape_fits(const mdgmi_format* f);
+size_t small_image_bytes(const mdgmi_format* f, int n_snr);
+LaunchCfg small_cfg(const mdgmi_format* f, int64_t n, int n_snr);
+hipError_t launch_small(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n, const SnrArgs& sa,
+                        int mode, float* llr, double* part, void* image, LaunchCfg cfg, hipStream_t st);
 
 // split: 0 = fp16 hi + lo operands, 1 = bf16 in three parts (see mfma_core.h)
 bool mfma_supported(const mdgmi_format* f, double max_s, int split = 0);
