@@ -32,6 +32,7 @@
 // bits above. Everything is unrolled for the format size, so no per-bit
 // work depends on run-time values.
 #include <algorithm>
+#include <utility>
 
 #include "mfma_core.h"
 
@@ -102,40 +103,37 @@ __device__ __forceinline__ void half_maxes(float* v, float* s0, float* s1) {
 }
 
 // u of the lane's sample against the four points of group ABID of the
-// register set a (broadcast from block ABID to every block).
+// register set a (broadcast from block ABID to every block); the
+// accumulator starts at c0 = {K, K, K, K}.
 template <int NK, int ABID>
-__device__ __forceinline__ f32x4 chain_group(const half4* a, const half4* b, float K) {
-    f32x4 c = {K, K, K, K};
+__device__ __forceinline__ f32x4 chain_group(const half4* a, const half4* b, const f32x4& c0) {
+    f32x4 c = __builtin_amdgcn_mfma_f32_4x4x4f16(a[0], b[0], c0, 4, ABID, 0);
 #pragma unroll
-    for (int k = 0; k < NK; k++) c = __builtin_amdgcn_mfma_f32_4x4x4f16(a[k], b[k], c, 4, ABID, 0);
+    for (int k = 1; k < NK; k++) c = __builtin_amdgcn_mfma_f32_4x4x4f16(a[k], b[k], c, 4, ABID, 0);
     return c;
 }
 
 // u of the lane's sample against the point whose A operands the lane itself
 // supplies (no broadcast): register l & 3 of the result.
 template <int NK>
-__device__ __forceinline__ f32x4 chain_own(const half4* a, const half4* b, float K) {
-    f32x4 c = {K, K, K, K};
+__device__ __forceinline__ f32x4 chain_own(const half4* a, const half4* b, const f32x4& c0) {
+    f32x4 c = __builtin_amdgcn_mfma_f32_4x4x4f16(a[0], b[0], c0, 0, 0, 0);
 #pragma unroll
-    for (int k = 0; k < NK; k++) c = __builtin_amdgcn_mfma_f32_4x4x4f16(a[k], b[k], c, 0, 0, 0);
+    for (int k = 1; k < NK; k++) c = __builtin_amdgcn_mfma_f32_4x4x4f16(a[k], b[k], c, 0, 0, 0);
     return c;
 }
 
-// Group g of the image: ABID = g mod 16 of set g / 16. Called from fully
-// unrolled loops, where g is a constant and the switch folds away.
-template <int NK, int NSET>
-__device__ __forceinline__ f32x4 group_u(const half4 (&a)[NSET][NK], int g, const half4* b, float K) {
-    const half4* as = a[g / 16];
-    switch (g % 16) {
-#define MDGMI_G(I) \
-    case I:        \
-        return chain_group<NK, I>(as, b, K);
-        MDGMI_G(0) MDGMI_G(1) MDGMI_G(2) MDGMI_G(3) MDGMI_G(4) MDGMI_G(5) MDGMI_G(6) MDGMI_G(7)
-        MDGMI_G(8) MDGMI_G(9) MDGMI_G(10) MDGMI_G(11) MDGMI_G(12) MDGMI_G(13) MDGMI_G(14)
-        default:
-            return chain_group<NK, 15>(as, b, K);
-#undef MDGMI_G
-    }
+// f(std::integral_constant<int, 0>) ... f(std::integral_constant<int, N - 1>)
+// in order: the group walk is unrolled by construction, so every group
+// index (ABID, register set, bank slot) is a compile-time constant however
+// large the format.
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 template <int NG>
@@ -194,10 +192,14 @@ __device__ __forceinline__ void small_sample(const half4 (&a)[Sets<NG>::value][N
     constexpr bool ML = mode_is_ml(MODE), HD = MODE == kModeHd;
     const int lane = threadIdx.x & 63;
     const bool valid = i < n;
+    // lanes past n read the last sample (no branch around the loads) and
+    // then work on y = 0
+    const int64_t ic = valid ? i : n - 1;
     float yv[DIM], ys2 = 0.0f;
 #pragma unroll
     for (int d = 0; d < DIM; d++) {
-        yv[d] = valid ? ys[i * DIM + d] : 0.0f;
+        const float v = ys[ic * DIM + d];
+        yv[d] = valid ? v : 0.0f;
         ys2 = fmaf(yv[d], yv[d], ys2);
     }
     // y beyond the fp16 range of its split (or not finite) takes the FP32
@@ -231,21 +233,22 @@ __device__ __forceinline__ void small_sample(const half4 (&a)[Sets<NG>::value][N
     constexpr bool SENT = !mode_is_llr(MODE) && !ML;
     uint32_t row = 0u, slot = 0u;
     if (SENT) {
-        row = valid ? txs[i] : 0u;
+        const uint32_t r = txs[ic];
+        row = valid ? r : 0u;
         slot = labels[row < (uint32_t)M ? row : 0u];
     }
     half4 ad[NK];
-    constexpr int NSET = Sets<NG>::value;
-    // Kc = K, passed through an empty asm after each group so that the MFMAs
-    // of group g + 2 cannot be hoisted above the exponentials of group g:
-    // one group of lookahead, not every group's u held in registers at once
-    float Kc = K;
-    f32x4 nxt = group_u<NK, NSET>(a, 0, bo, Kc);
-#pragma unroll
-    for (int g = 0; g < NG; g++) {
+    // Kc = {K, K, K, K}, passed through an empty asm after each group so that
+    // the MFMAs of group g + 2 cannot be hoisted above the exponentials of
+    // group g: one group of lookahead, not every group's u held in registers
+    // at once. The same four registers seed every chain.
+    f32x4 Kc = {K, K, K, K};
+    f32x4 nxt = chain_group<NK, 0>(a[0], bo, Kc);
+    static_for<NG>([&](auto gc) {
+        constexpr int g = decltype(gc)::value;
         const f32x4 u = nxt;
-        if (g + 1 < NG) nxt = group_u<NK, NSET>(a, g + 1, bo, Kc);
-        if (SENT && g == NG / 2) {
+        if constexpr (g + 1 < NG) nxt = chain_group<NK, (g + 1) % 16>(a[(g + 1) / 16], bo, Kc);
+        if constexpr (SENT && g == NG / 2) {
 #pragma unroll
             for (int k = 0; k < NK; k++) {
                 H4 v;
@@ -253,24 +256,24 @@ __device__ __forceinline__ void small_sample(const half4 (&a)[Sets<NG>::value][N
                 ad[k] = v.v;
             }
         }
-        const int c = g / GPC, r0 = 4 * (g % GPC);
-        const bool first = g % GPC == 0;
+        constexpr int c = g / GPC, r0 = 4 * (g % GPC);
+        constexpr bool first = g % GPC == 0;
         if constexpr (ML) {
 #pragma unroll
             for (int r = 0; r < 4; r++) bank[r0 + r] = c == 0 ? u[r] : fmaxf(bank[r0 + r], u[r]);
-            if (NC > 1) {
+            if constexpr (NC > 1) {
                 const float gm = fmaxf(fmaxf(u[0], u[1]), fmaxf(u[2], u[3]));
                 T[c] = first ? gm : fmaxf(T[c], gm);
             }
         } else {
-            if (HD) umax = fmaxf(fmaxf(umax, fmaxf(u[0], u[1])), fmaxf(u[2], u[3]));
+            if constexpr (HD) umax = fmaxf(fmaxf(umax, fmaxf(u[0], u[1])), fmaxf(u[2], u[3]));
             float e[4];
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 e[r] = ex2(u[r]);
                 bank[r0 + r] = c == 0 ? e[r] : bank[r0 + r] + e[r];
             }
-            if (NC > 1) {
+            if constexpr (NC > 1) {
                 const float gs = (e[0] + e[1]) + (e[2] + e[3]);
                 T[c] = first ? gs : T[c] + gs;
             }
@@ -280,7 +283,7 @@ __device__ __forceinline__ void small_sample(const half4 (&a)[Sets<NG>::value][N
         asm volatile("" : "+v"(Kc) : "v"(bank[r0]), "v"(bank[r0 + 1]), "v"(bank[r0 + 2]), "v"(bank[r0 + 3]),
                      "v"(NC > 1 ? T[c] : 0.0f), "v"(umax));
         __builtin_amdgcn_sched_barrier(0);
-    }
+    });
     // per-bit class sums (or maxima): bits below CHB from the bank, the
     // rest from the chunk totals
     float S0[m], S1[m];
@@ -349,9 +352,9 @@ __device__ __forceinline__ void small_sample(const half4 (&a)[Sets<NG>::value][N
     // its own sent point as A row l & 3 of its block, so register l & 3 of
     // the output is u_i(y), bit-identical to the value inside the class sums
     // (a broadcast MFMA and a plain one form element (i, j) alike)
-    const f32x4 ud = chain_own<NK>(ad, bo, K);
-    const int q = lane & 3;
-    const float ui = q == 0 ? ud[0] : (q == 1 ? ud[1] : (q == 2 ? ud[2] : ud[3]));
+    const f32x4 ud = chain_own<NK>(ad, bo, Kc);
+    const bool q1 = lane & 1, q2 = lane & 2;
+    const float ui = q2 ? (q1 ? ud[3] : ud[2]) : (q1 ? ud[1] : ud[0]);
     float cg = 0.0f, cm, be = 0.0f, sym;
 #pragma unroll
     for (int k = 0; k < m; k++) {
