@@ -255,6 +255,7 @@ __device__ inline void exact_classes_f32(const float* yv, const float* __restric
     float tmin = INFINITY;
 #pragma unroll
     for (int k = 0; k < MDGMI_MAX_BITS; k++) cmin0[k] = cmin1[k] = INFINITY;
+#pragma unroll 2
     for (int j = 0; j < M; j++) {
         float d = 0.0f;
 #pragma unroll
@@ -279,6 +280,7 @@ __device__ inline void exact_classes_f32(const float* yv, const float* __restric
     float tot = 0.0f;
 #pragma unroll
     for (int k = 0; k < MDGMI_MAX_BITS; k++) S0[k] = S1[k] = 0.0f;
+#pragma unroll 2
     for (int j = 0; j < M; j++) {
         float d = 0.0f;
 #pragma unroll
@@ -319,6 +321,7 @@ __device__ inline void class_max_u_f32(const float* yv, const float* __restrict_
 #pragma clang fp contract(off)
 #pragma unroll
     for (int k = 0; k < MDGMI_MAX_BITS; k++) u0[k] = u1[k] = -INFINITY;
+#pragma unroll 2
     for (int j = 0; j < M; j++) {
         float d = 0.0f;
 #pragma unroll
