@@ -305,8 +305,11 @@ int mdgmi_gmi_batched_workspace_size(const mdgmi_instance* inst_host, int32_t n_
 /* One-shot ragged batch. inst_host: host [n_inst]; out: device
  * [n_inst][MDGMI_NFIELDS] double, row q for inst_host[q]. path:
  * MDGMI_PATH_F32_DIRECT, MDGMI_PATH_F32_MFMA_F16SPLIT (every instance needs
- * M >= 128 and dim >= 2) or MDGMI_PATH_AUTO (per instance: the autotuner's
- * choice, else MFMA for M >= 128; one-dimensional formats always direct). The work list is copied into the workspace on `stream`. */
+ * M >= 128 and dim >= 2 for 32x32 tiles, or a format that the per-sample
+ * 4x4 shape serves) or MDGMI_PATH_AUTO (per instance: the autotuner's
+ * choice, else the 4x4 shape where it serves M, else MFMA tiles for
+ * M >= 128, else direct). The work list is copied into the workspace on
+ * `stream`. */
 int mdgmi_gmi_batched(const mdgmi_instance* inst_host, int32_t n_inst, int32_t path, double* out, void* ws,
                       size_t ws_bytes, void* stream);
 

@@ -31,7 +31,7 @@ FLAGS = [
 # Per-file flags. The 4x4-block MFMA shape keeps its accumulators in
 # ordinary VGPRs: the exponentials read every MFMA result, and AGPR results
 # would cost one extra v_accvgpr_read per (sample, point).
-EXTRA_FLAGS = {"exact_mfma4.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+EXTRA_FLAGS = {name: ["-mllvm", "-amdgpu-mfma-vgpr-form"] for name in ("exact_mfma4.hip", "batch_small.hip")}
 
 
 def sources():

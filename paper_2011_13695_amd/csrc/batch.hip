@@ -7,7 +7,8 @@
 // constellations first within each. One persistent grid per kind pulls items
 // from its own atomic counter; for each item a block
 // dispatches on the instance's (dim, M) to the very device functions the
-// per-SNR kernels run (mfma_core.h / direct_core.h), staging the
+// per-SNR kernels run (mfma_core.h / direct_core.h; the 4x4-shape kind in
+// batch_small.hip with small_core.h), staging the
 // instance's MFMA A image in LDS when it fits and keeping it there while the
 // block stays on that instance. Every item writes its own FP64 partials, and
 // one block per instance adds its items' partials in item order, so the
@@ -21,6 +22,7 @@
 #include "batch.h"
 #include "direct_core.h"
 #include "mfma_core.h"
+#include "small_core.h"
 
 namespace mdgmi {
 
@@ -152,6 +154,16 @@ __global__ void k_batch_images(const BatchImg* __restrict__ imgs, int n_inst, in
             mfma::image_slot<4>(I.X64, I.M, I.ntiles, I.s64, slot, dst);
         else
             mfma::image_slot<8>(I.X64, I.M, I.ntiles, I.s64, slot, dst);
+    } else if (I.kind == kKindSmall) {
+        uint2* dst = (uint2*)(base + I.img_off);
+        if (I.dim == 1)
+            small::image_slot<1>(I.X64, I.s64, slot, dst + (size_t)slot * small::Nk4<1>::value);
+        else if (I.dim == 2)
+            small::image_slot<2>(I.X64, I.s64, slot, dst + (size_t)slot * small::Nk4<2>::value);
+        else if (I.dim == 4)
+            small::image_slot<4>(I.X64, I.s64, slot, dst + (size_t)slot * small::Nk4<4>::value);
+        else
+            small::image_slot<8>(I.X64, I.s64, slot, dst + (size_t)slot * small::Nk4<8>::value);
     } else {
         const int rec = ((I.dim + 1 + 3) / 4) * 4;
         direct::direct_record(I.X64, I.dim, rec, I.s64, slot, (float*)(base + I.img_off) + (size_t)slot * rec);
@@ -159,7 +171,7 @@ __global__ void k_batch_images(const BatchImg* __restrict__ imgs, int n_inst, in
 }
 
 __global__ void k_zero_counters(unsigned* c) {
-    if (blockIdx.x == 0 && threadIdx.x < 2) c[threadIdx.x] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < 3) c[threadIdx.x] = 0u;
 }
 
 int direct_variant(int m) { return m <= 1 ? 0 : m == 2 ? 1 : m == 3 ? 2 : m == 4 ? 3 : m == 5 ? 4 : 5; }
@@ -169,14 +181,17 @@ size_t al(size_t v) { return (v + 255) / 256 * 256; }
 }  // namespace
 
 int batch_kind_for(const mdgmi_format* f, double s, int path) {
-    // one-dimensional formats run on the direct kernel in a batch
+    // the 32 x 32 shape takes M >= 128 in a batch (one-dimensional formats
+    // excepted); the 4x4 shape the formats it serves, where the per-SNR
+    // fp16-split path would run them on it
     const bool mfma_ok = f->dim != 1 && f->M >= 128 && mfma_supported(f, s);
+    const bool small_ok = small_shape_fits(f) && mfma_supported(f, s) && prefers_small(f);
     if (path == MDGMI_PATH_F32_DIRECT) return kKindDirect;
-    if (path == MDGMI_PATH_F32_MFMA_F16SPLIT) return mfma_ok ? kKindMfma : -1;
+    if (path == MDGMI_PATH_F32_MFMA_F16SPLIT) return small_ok ? kKindSmall : (mfma_ok ? kKindMfma : -1);
     // AUTO: the tuned choice for this (dim, M) where one exists
     int tuned = tuned_batch_kind(f->dim, f->M);
-    if (tuned == kKindMfma && mfma_ok) return kKindMfma;
     if (tuned == kKindDirect) return kKindDirect;
+    if (small_ok) return kKindSmall;
     return mfma_ok ? kKindMfma : kKindDirect;
 }
 
@@ -208,6 +223,9 @@ int plan_batch(const mdgmi_instance* inst, int n_inst, int path, int64_t item_pa
         if (kind[q] == kKindMfma) {
             bytes = (size_t)I.ntiles * (f->dim == 8 ? 2 : 1) * 64 * 16;
             slots += (int64_t)I.ntiles * 32;
+        } else if (kind[q] == kKindSmall) {
+            bytes = (size_t)f->M * ((3 * f->dim + 2 + 3) / 4) * 8;
+            slots += f->M;
         } else {
             bytes = (size_t)f->M * (((f->dim + 1 + 3) / 4) * 4) * sizeof(float);
             slots += f->M;
@@ -215,13 +233,14 @@ int plan_batch(const mdgmi_instance* inst, int n_inst, int path, int64_t item_pa
         img_bytes += al(bytes);
     }
     P.total_slots = slots;
-    // MFMA instances first, then direct ones (each kind has its own kernel);
-    // within a kind, decreasing M (then input order) so the cheap ones form
-    // the tail
+    // MFMA instances first, then 4x4-shape ones, then direct ones (each kind
+    // has its own kernel); within a kind, decreasing M (then input order) so
+    // the cheap ones form the tail
+    auto rank = [&](int q) { return kind[q] == kKindMfma ? 0 : (kind[q] == kKindSmall ? 1 : 2); };
     std::vector<int> order(n_inst);
     for (int q = 0; q < n_inst; q++) order[q] = q;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        if (kind[a] != kind[b]) return kind[a] == kKindMfma;
+        if (kind[a] != kind[b]) return rank(a) < rank(b);
         return inst[a].fmt->M > inst[b].fmt->M;
     });
     P.insts.resize(n_inst);
@@ -232,7 +251,8 @@ int plan_batch(const mdgmi_instance* inst, int n_inst, int path, int64_t item_pa
         const int q = order[oi];
         const mdgmi_format* f = inst[q].fmt;
         const int64_t n = inst[q].n;
-        const int align = kind[q] == kKindMfma ? 32 * kMfmaWaves : 64 * kDirectWaves;
+        const int align = kind[q] == kKindMfma ? 32 * kMfmaWaves
+                                               : (kind[q] == kKindSmall ? kSmallItemAlign : 64 * kDirectWaves);
         int64_t per = item_pairs / f->M;
         per = std::max<int64_t>(align, per / align * align);
         first_of[q] = (int32_t)P.items.size();
@@ -246,9 +266,11 @@ int plan_batch(const mdgmi_instance* inst, int n_inst, int path, int64_t item_pa
         }
         count_of[q] = (int32_t)P.items.size() - first_of[q];
     }
-    P.n_mfma_items = 0;
-    for (const BatchItem& it : P.items)
+    P.n_mfma_items = P.n_small_items = 0;
+    for (const BatchItem& it : P.items) {
         if (kind[it.inst] == kKindMfma) P.n_mfma_items++;
+        if (kind[it.inst] == kKindSmall) P.n_small_items++;
+    }
     P.item_range.resize(2 * (size_t)n_inst);
     for (int q = 0; q < n_inst; q++) {
         P.item_range[2 * q] = first_of[q];
@@ -289,7 +311,7 @@ int plan_batch(const mdgmi_instance* inst, int n_inst, int path, int64_t item_pa
     P.off_part = o;
     o += al(sizeof(double) * kNPart * P.items.size());
     P.off_counter = o;
-    o += al(2 * sizeof(unsigned));
+    o += al(3 * sizeof(unsigned));
     P.off_images = o;
     o += img_bytes;
     P.bytes = o;
@@ -385,10 +407,15 @@ hipError_t launch_batch(const BatchPlan& P, double* out, hipStream_t st) {
         hipLaunchKernelGGL(k_batch<kKindMfma>, dim3(grid), dim3(kMfmaWaves * 64), lds, st, insts, items, 0, n_mfma,
                            counter, part);
     }
-    if (n_items > n_mfma) {
-        const int grid = std::max(1, std::min(n_items - n_mfma, device_cu_count() * 2));
-        hipLaunchKernelGGL(k_batch<kKindDirect>, dim3(grid), dim3(kDirectWaves * 64), 0, st, insts, items, n_mfma,
-                           n_items, counter + 1, part);
+    const int n_small = P.n_small_items, d0 = n_mfma + n_small;
+    if (n_small > 0) {
+        const hipError_t e = launch_batch_small(insts, items, n_mfma, d0, counter + 1, part, st);
+        if (e != hipSuccess) return e;
+    }
+    if (n_items > d0) {
+        const int grid = std::max(1, std::min(n_items - d0, device_cu_count() * 2));
+        hipLaunchKernelGGL(k_batch<kKindDirect>, dim3(grid), dim3(kDirectWaves * 64), 0, st, insts, items, d0,
+                           n_items, counter + 2, part);
     }
     hipLaunchKernelGGL(k_batch_reduce_ranges, dim3(P.n_inst), dim3(256), 0, st, (const double*)(P.base + P.off_part),
                        (const int32_t*)(P.base + P.off_range), (const BatchInst*)(P.base + P.off_insts), out);

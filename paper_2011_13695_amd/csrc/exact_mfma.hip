@@ -333,6 +333,8 @@ hipError_t image_and_fixed(const mdgmi_format* f, const float* y, const uint32_t
     }
 }
 
+bool prefers_small(const mdgmi_format* f) { return use_small(f, kSplitF16); }
+
 hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
                        const SnrArgs& sa, int mode, float* llr, double* part, void* image,
                        LaunchCfg cfg, hipStream_t st, int split) {

@@ -78,6 +78,8 @@ hipError_t launch_direct(const mdgmi_format* f, const float* y, const uint32_t* 
 // Per-sample 4x4-block shape of the fp16-split path for 4 <= M <= 256
 // (8-D: M <= 64), exact_mfma4.hip; used by launch_mfma where it applies.
 bool small_shape_fits(const mdgmi_format* f);
+// whether the fp16-split path runs f on that shape (tuning table, override)
+bool prefers_small(const mdgmi_format* f);
 size_t small_image_bytes(const mdgmi_format* f, int n_snr);
 LaunchCfg small_cfg(const mdgmi_format* f, int64_t n, int n_snr);
 hipError_t launch_small(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n, const SnrArgs& sa,

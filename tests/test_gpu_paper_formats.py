@@ -6,8 +6,9 @@ MFMA image layout and generator case) and Gray square QAM-4/16/64.
 * exact and max-log LLRs within 1e-3 max(|lambda|, 1) nats (FP64 1e-9);
 * hard-decision error counts within the decisions near their thresholds;
 * the device generator against the host generator for a 1-D format;
-* one-dimensional instances in a ragged batch (direct kernel) against
-  per-instance calls, and the autotuner on a 1-D format.
+* one-dimensional instances in a ragged batch (the per-sample 4x4 MFMA
+  kind from M = 4, the direct kernel for M = 2) against per-instance calls
+  that take the same kernels, and the autotuner on a 1-D format.
 """
 import sys
 
@@ -114,6 +115,7 @@ def test_generator_one_dimensional():
 
 
 def test_one_dimensional_instances_in_a_batch():
+    mdgmi.mdgmi_tune_clear()
     items, refs = [], []
     for k, name in enumerate(["2-PAM", "4-PAM", "16-PAM", "64-QAM"]):
         f = FORMATS[name]
@@ -123,7 +125,7 @@ def test_one_dimensional_instances_in_a_batch():
         yd = dev(y.astype(np.float32), torch.float32)
         td = dev_u32(tx)
         items.append((gf, yd, td, s2))
-        refs.append(mdgmi.mdgmi_gmi(gf, yd[None], td[None], [s2], path="direct").cpu().numpy()[0])
+        refs.append(mdgmi.mdgmi_gmi(gf, yd[None], td[None], [s2], path="auto").cpu().numpy()[0])
     out = mdgmi.mdgmi_gmi_batched(mdgmi.instances(items), path="auto").cpu().numpy()
     ref = np.array(refs)
     np.testing.assert_array_equal(out[:, 4], ref[:, 4])

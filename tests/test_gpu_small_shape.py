@@ -12,7 +12,10 @@ C ABI, against the FP64 oracle on the same samples, in every mode:
   (the lane's FP32 per-class path);
 * samples far from every point, non-finite samples, samples beyond the fp16
   range of the operand split, and sent rows out of range;
-* the shape against the 32 x 32 shape of the same path on the same samples.
+* the shape against the 32 x 32 shape of the same path on the same samples;
+* small instances of a ragged batch (their own 4x4-shape kind) against
+  per-instance calls: the same per-sample arithmetic, so GMI/MI agree to
+  FP64 summation order.
 """
 import sys
 
@@ -231,3 +234,34 @@ def test_small_shape_is_the_default_and_can_be_declined(shape):
     np.testing.assert_array_equal(auto, small)
     np.testing.assert_array_equal(small, small2)
     assert np.max(np.abs(small[:, :2] - big[:, :2])) <= 1e-6
+
+
+@pytest.mark.parametrize("path", ["mfma", "auto"])
+def test_small_instances_in_a_batch(shape, path):
+    """Ragged sample counts (1, below and above one item alignment of 256,
+    large), every dimension, M = 4 .. 256, in one batch; each row against
+    mdgmi_gmi on the same samples."""
+    shape(-1)
+    mdgmi.mdgmi_tune_clear()
+    specs = [(1, 4, 1), (1, 64, 255), (2, 16, 257), (2, 256, 70001), (4, 64, 4099), (4, 128, 600),
+             (8, 8, 63), (8, 64, 9000), (2, 4, 1000), (4, 256, 20000)]
+    items, refs = [], []
+    for k, (dim, M, n) in enumerate(specs):
+        f = fmt(dim, M)
+        gf = mdgmi.Format.of(f)
+        s2 = float(w.sigma2_from_snr_db(4.0 + 2.0 * k, dim))
+        y, tx = w.channel_samples(f, s2, seed=50 + k, snr_slot=k, n=n)
+        yd, td = dev(y), dev_u32(tx)
+        items.append((gf, yd, td, s2))
+        refs.append(mdgmi.mdgmi_gmi(gf, yd[None], td[None], [s2], path="mfma").cpu().numpy()[0])
+    out = mdgmi.mdgmi_gmi_batched(mdgmi.instances(items), path=path).cpu().numpy()
+    ref = np.array(refs)
+    np.testing.assert_array_equal(out[:, 4:6], ref[:, 4:6])
+    assert np.max(np.abs(out[:, :2] - ref[:, :2])) <= 1e-12
+    plan = mdgmi.Batch(items, path=path)
+    a = plan.run(use_graph=True).cpu().numpy()
+    b = plan.run(use_graph=True).cpu().numpy()
+    plan.close()
+    np.testing.assert_array_equal(a, b)
+    assert np.max(np.abs(a[:, :2] - ref[:, :2])) <= 1e-12
+    say(f"[small batch] {path}: max dGMI vs per-instance {np.max(np.abs(out[:, 0] - ref[:, 0])):.1e}")
