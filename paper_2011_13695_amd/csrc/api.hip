@@ -140,6 +140,12 @@ int gmi_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, int32_
     if (path == MDGMI_PATH_AUTO)
         pl.total = std::max({pl.total, plan_gmi(fmt, n, n_snr, MDGMI_PATH_F32_DIRECT, mode).total,
                              plan_gmi(fmt, n, n_snr, MDGMI_PATH_F32_MFMA_BF16SPLIT, mode).total});
+    // mdgmi_gmi_maxlog shares mdgmi_gmi's size: its launch shape may differ
+    if (mode == kModeGmi) {
+        size_t ml = 0;
+        gmi_workspace_size(fmt, n, n_snr, path, kModeMlGmi, &ml);
+        pl.total = std::max(pl.total, ml);
+    }
     *bytes = pl.total;
     return MDGMI_OK;
 }
