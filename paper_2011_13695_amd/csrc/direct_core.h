@@ -49,7 +49,7 @@ __device__ __forceinline__ void direct_sample(const float* __restrict__ im, cons
                                               const uint32_t* __restrict__ txs, int64_t i, int M, int m,
                                               float s, const float* __restrict__ X32,
                                               const uint32_t* __restrict__ labels, float* __restrict__ llr,
-                                              CostAcc& acc, HdAcc* hd = nullptr) {
+                                              CostAcc& acc, HdAcc* hd = nullptr, float guard = 0.0f) {
     constexpr bool LLR = MODE == kModeLlr;
     constexpr int CH = 1 << CHB;
     constexpr int REC = DirectRec<DIM>::value;
@@ -130,12 +130,24 @@ __device__ __forceinline__ void direct_sample(const float* __restrict__ im, cons
         }
     }
     if (LLR) {
-        if (smin >= ex2(kFarLog2)) {
+        float lam[MDGMI_MAX_BITS];
+        bool ok = smin >= ex2(kFarLog2);
+#pragma unroll
+        for (int k = 0; k < MDGMI_MAX_BITS; k++) {
+            lam[k] = 0.0f;
+            if (k < m) {
+                lam[k] = log2_ratio(S1[k], S0[k], ls1[k], ls0[k]);
+                // an LLR near zero at a large s: recompute from differences
+                ok = ok && !(fabsf(lam[k]) < guard);
+            }
+        }
+        if (ok) {
 #pragma unroll
             for (int k = 0; k < MDGMI_MAX_BITS; k++)
-                if (k < m) llr[i * m + k] = log2_ratio(S1[k], S0[k], ls1[k], ls0[k]) * (float)kLn2;
+                if (k < m) llr[i * m + k] = lam[k] * (float)kLn2;
         } else {
-            // a class lies too far for the common offset (or y is not finite)
+            // a class lies too far for the common offset (or y is not finite,
+            // or the guard above fired)
             float ltot, ti;
             exact_classes_f32<DIM>(yv, X32, M, m, s, -1, ls0, ls1, ltot, ti);
 #pragma unroll
@@ -208,7 +220,7 @@ __device__ __forceinline__ void direct_sample_ml(const float* __restrict__ im, c
                                                  const uint32_t* __restrict__ txs, int64_t i, int M, int m,
                                                  float s, const float* __restrict__ X32,
                                                  const uint32_t* __restrict__ labels, float* __restrict__ llr,
-                                                 CostAcc& acc) {
+                                                 CostAcc& acc, float guard = 0.0f) {
     constexpr int CH = 1 << CHB;
     constexpr int REC = DirectRec<DIM>::value;
     constexpr int MAXHI = MDGMI_MAX_BITS - CHB;
@@ -285,7 +297,13 @@ __device__ __forceinline__ void direct_sample_ml(const float* __restrict__ im, c
     bool finite = true;
 #pragma unroll
     for (int q = 0; q < DIM; q++) finite = finite && __builtin_isfinite(yv[q]);
-    if (!(best >= kFarLog2) || !finite) class_max_u_f32<DIM>(yv, X32, M, m, s, u0, u1);
+    bool redo = !(best >= kFarLog2) || !finite;
+    if (MODE == kModeMlLlr) {
+#pragma unroll
+        for (int k = 0; k < MDGMI_MAX_BITS; k++)
+            if (k < m) redo = redo || fabsf(u1[k] - u0[k]) < guard;
+    }
+    if (redo) class_max_u_f32<DIM>(yv, X32, M, m, s, u0, u1);
     if (MODE == kModeMlLlr) {
 #pragma unroll
         for (int k = 0; k < MDGMI_MAX_BITS; k++)

@@ -14,7 +14,7 @@ template <int DIM, int CHB, int G, int MODE>
 __global__ __launch_bounds__(kDirectThreads) void k_direct(
     const float* __restrict__ y, const uint32_t* __restrict__ tx, const float* __restrict__ img,
     const float* __restrict__ X32, const uint32_t* __restrict__ labels, int64_t n, int M, int m, SnrArgs sa,
-    float* __restrict__ llr, double* __restrict__ part) {
+    float max_n2, float* __restrict__ llr, double* __restrict__ part) {
     constexpr int REC = DirectRec<DIM>::value;
     const int q_snr = blockIdx.y;
     const float s = sa.s32[q_snr];
@@ -24,12 +24,13 @@ __global__ __launch_bounds__(kDirectThreads) void k_direct(
     const uint32_t* txs = mode_is_llr(MODE) ? nullptr : tx + snr * n;
     CostAcc acc;
     HdAcc hd;
+    const float guard = mode_is_llr(MODE) ? llr_guard(s, max_n2) : 0.0f;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         if constexpr (mode_is_ml(MODE))
-            direct_sample_ml<DIM, CHB, G, MODE>(im, ys, txs, i, M, m, s, X32, labels, llr, acc);
+            direct_sample_ml<DIM, CHB, G, MODE>(im, ys, txs, i, M, m, s, X32, labels, llr, acc, guard);
         else
-            direct_sample<DIM, CHB, G, MODE>(im, ys, txs, i, M, m, s, X32, labels, llr, acc, &hd);
+            direct_sample<DIM, CHB, G, MODE>(im, ys, txs, i, M, m, s, X32, labels, llr, acc, &hd, guard);
     }
     double* dst = part + ((int64_t)q_snr * gridDim.x + blockIdx.x) * (MODE == kModeHd ? kNPartHd : kNPart);
     if (MODE == kModeGmi || MODE == kModeMlGmi) block_reduce_store(acc, dst);
@@ -52,19 +53,19 @@ hipError_t launch_direct_t(const mdgmi_format* f, const float* y, const uint32_t
     dim3 grid(cfg.blocks_per_snr, sa.n_snr), block(cfg.threads);
     if (mode == kModeLlr)
         hipLaunchKernelGGL((k_direct<DIM, CHB, G, kModeLlr>), grid, block, 0, st, y, tx, image, f->d_X32,
-                           f->d_labels, n, f->M, f->m, sa, llr, part);
+                           f->d_labels, n, f->M, f->m, sa, (float)f->max_norm2, llr, part);
     else if (mode == kModeMlLlr)
         hipLaunchKernelGGL((k_direct<DIM, CHB, G, kModeMlLlr>), grid, block, 0, st, y, tx, image, f->d_X32,
-                           f->d_labels, n, f->M, f->m, sa, llr, part);
+                           f->d_labels, n, f->M, f->m, sa, (float)f->max_norm2, llr, part);
     else if (mode == kModeMlGmi)
         hipLaunchKernelGGL((k_direct<DIM, CHB, G, kModeMlGmi>), grid, block, 0, st, y, tx, image, f->d_X32,
-                           f->d_labels, n, f->M, f->m, sa, llr, part);
+                           f->d_labels, n, f->M, f->m, sa, (float)f->max_norm2, llr, part);
     else if (mode == kModeHd)
         hipLaunchKernelGGL((k_direct<DIM, CHB, G, kModeHd>), grid, block, 0, st, y, tx, image, f->d_X32,
-                           f->d_labels, n, f->M, f->m, sa, llr, part);
+                           f->d_labels, n, f->M, f->m, sa, (float)f->max_norm2, llr, part);
     else
         hipLaunchKernelGGL((k_direct<DIM, CHB, G, kModeGmi>), grid, block, 0, st, y, tx, image, f->d_X32,
-                           f->d_labels, n, f->M, f->m, sa, llr, part);
+                           f->d_labels, n, f->M, f->m, sa, (float)f->max_norm2, llr, part);
     return hipGetLastError();
 }
 

@@ -22,7 +22,8 @@ template <int DIM, int NG, int MODE>
 __global__ __launch_bounds__(kSmallThreads) void k_small(const float* __restrict__ y, const uint32_t* __restrict__ tx,
                                                          const uint2* __restrict__ img, const float* __restrict__ X32,
                                                          const uint32_t* __restrict__ labels, int64_t n, SnrArgs sa,
-                                                         float* __restrict__ llr, double* __restrict__ part) {
+                                                         float max_n2, float* __restrict__ llr,
+                                                         double* __restrict__ part) {
     constexpr int NK = Nk4<DIM>::value;
     constexpr int M = 4 * NG;
     // the wave index is uniform: keep the batch loop on the scalar unit
@@ -37,11 +38,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_small(const float* __restrict
     load_image<DIM, NG>(gimg, M, a);
     CostAcc acc;
     HdAcc hd;
+    const float guard = mode_is_llr(MODE) ? llr_guard(s, max_n2) : 0.0f;
     const int waves = kSmallThreads / 64;
     const int64_t nbat = (n + 63) / 64;
     // wave-uniform loop over batches of 64 consecutive samples
     for (int64_t b = (int64_t)blockIdx.x * waves + wave; b < nbat; b += (int64_t)gridDim.x * waves)
-        small_sample<DIM, NG, MODE>(a, gimg, ys, txs, b * 64 + lane, n, s, X32, labels, llr, acc, hd);
+        small_sample<DIM, NG, MODE>(a, gimg, ys, txs, b * 64 + lane, n, s, X32, labels, llr, acc, hd, guard);
     double* dst = part + ((int64_t)q_snr * gridDim.x + blockIdx.x) * (MODE == kModeHd ? kNPartHd : kNPart);
     if (MODE == kModeGmi || MODE == kModeMlGmi) block_reduce_store(acc, dst);
     if (MODE == kModeHd) block_reduce_store_hd(acc, hd, dst);
@@ -53,7 +55,7 @@ hipError_t launch_small_t(const mdgmi_format* f, const float* y, const uint32_t*
     const dim3 grid(blocks, sa.n_snr), block(kSmallThreads);
 #define MDGMI_SMALL(MD)                                                                                      \
     hipLaunchKernelGGL((k_small<DIM, NG, MD>), grid, block, 0, st, y, tx, img, f->d_X32, f->d_labels, n, sa, \
-                       llr, part);                                                                           \
+                       (float)f->max_norm2, llr, part);                                                      \
     break;
     switch (mode) {
         case kModeLlr:

@@ -44,6 +44,19 @@ constexpr int kMaxSnrPerLaunch = 32;
 // 2 * kBias of y is summed without underflow.
 constexpr float kBias = 100.0f;
 constexpr float kFarLog2 = -100.0f;  // class sums below 2^-100 take the per-class path
+// LLR outputs at large s max||x||^2: u = K - s||x||^2 + <2 s x, y> cancels
+// terms of that size, so an LLR carries an absolute error of up to about
+// 2.3e-7 s max||x||^2 nats (fp16 split; FP32 rounding alone is a quarter of
+// that). Above kLlrGuardS the LLR modes of the per-lane kernels recompute a
+// sample on the per-class path (distances from differences) when one of
+// its LLRs is below llr_guard() (log2 units), which keeps that error under
+// half of the 1e-3 max(|lambda|, 1) bar: |lambda| > 4.6e-4 s max||x||^2
+// nats, i.e. 6.6e-4 s max||x||^2 log2 units, and at least 3.
+constexpr float kLlrGuardS = 1000.0f;
+__host__ __device__ inline float llr_guard(float s, float max_n2) {
+    const float sn = s * max_n2;
+    return sn > kLlrGuardS ? fmaxf(3.0f, 6.6e-4f * sn) : 0.0f;
+}
 constexpr double kLog2e = 1.4426950408889634;
 constexpr double kLn2 = 0.6931471805599453;
 

@@ -202,7 +202,7 @@ __device__ __forceinline__ void small_sample(const half4 (&a)[Sets<NG>::value][N
                                              const float* __restrict__ ys, const uint32_t* __restrict__ txs,
                                              int64_t i, int64_t n, float s, const float* __restrict__ X32,
                                              const uint32_t* __restrict__ labels, float* __restrict__ llr,
-                                             CostAcc& acc, HdAcc& hd) {
+                                             CostAcc& acc, HdAcc& hd, float guard = 0.0f) {
     constexpr int NK = Nk4<DIM>::value;
     constexpr int M = 4 * NG, m = ilog2(M);
     constexpr int CH = M < 16 ? M : 16, CHB = ilog2(CH), NC = M / CH, GPC = CH / 4;
@@ -322,7 +322,12 @@ __device__ __forceinline__ void small_sample(const half4 (&a)[Sets<NG>::value][N
             u0[k] = S0[k];
             u1[k] = S1[k];
         }
-        if (!(best >= kFarLog2) || ybad) class_max_u_f32<DIM>(yv, X32, M, m, s, u0, u1);
+        bool redo = !(best >= kFarLog2) || ybad;
+        if (MODE == kModeMlLlr) {
+#pragma unroll
+            for (int k = 0; k < m; k++) redo = redo || fabsf(u1[k] - u0[k]) < guard;
+        }
+        if (redo) class_max_u_f32<DIM>(yv, X32, M, m, s, u0, u1);
         if (!valid) return;
         if (MODE == kModeMlLlr) {
 #pragma unroll
@@ -349,8 +354,12 @@ __device__ __forceinline__ void small_sample(const half4 (&a)[Sets<NG>::value][N
             smin = fminf(smin, fminf(S0[k], S1[k]));
             out[k] = log2_ratio_fast(S1[k], S0[k]);
         }
-        // a class too far for the common offset, or y out of range
-        if (!(smin >= ex2(kFarLog2)) || ybad) {
+        // a class too far for the common offset, y out of range, or (guard)
+        // an LLR near zero at a large s
+        bool redo = !(smin >= ex2(kFarLog2)) || ybad;
+#pragma unroll
+        for (int k = 0; k < m; k++) redo = redo || fabsf(out[k]) < guard;
+        if (redo) {
             float ls0[MDGMI_MAX_BITS], ls1[MDGMI_MAX_BITS], ltot, ti;
             exact_classes_f32<DIM>(yv, X32, M, m, s, -1, ls0, ls1, ltot, ti);
 #pragma unroll

@@ -265,3 +265,31 @@ def test_small_instances_in_a_batch(shape, path):
     np.testing.assert_array_equal(a, b)
     assert np.max(np.abs(a[:, :2] - ref[:, :2])) <= 1e-12
     say(f"[small batch] {path}: max dGMI vs per-instance {np.max(np.abs(out[:, 0] - ref[:, 0])):.1e}")
+
+
+@pytest.mark.parametrize("name", ["64-PAM", "16-QAM"])
+@pytest.mark.parametrize("path", ["mfma", "direct"])
+def test_llr_near_zero_at_large_s(orc, shape, name, path):
+    """At s max||x||^2 = 1.3e4 (inside the fp16 range of the split) the
+    expanded distance form cancels terms of that size; LLRs near zero are
+    recomputed on the per-class path, so exact and max-log LLRs meet the
+    1e-3 max(|lambda|, 1) bar there too."""
+    shape(-1)
+    f = w.pam(6) if name == "64-PAM" else w.square_qam(4)
+    gf = mdgmi.Format.of(f)
+    max_n2 = float((f.X ** 2).sum(1).max())
+    s = 1.3e4 / max_n2
+    s2 = float(np.log2(np.e) / (2.0 * s))
+    n = 20000
+    # y spread over the constellation's extent: at this noise level channel
+    # samples would hardly ever sit near a decision boundary
+    lim = float(np.abs(f.X).max()) + 0.1
+    y = np.random.default_rng(71).uniform(-lim, lim, size=(n, f.dim)).astype(np.float32).astype(np.float64)
+    lam = mdgmi.mdgmi_llr(gf, dev(y), s2, path=path).cpu().numpy().astype(np.float64)
+    ref = orc.llr(y, f.X, f.labels, s2)
+    near = int(np.count_nonzero(np.abs(ref) < 2.0))    # 34 (16-QAM) to 4192 (64-PAM) of 1.2e5
+    assert near > 20 and ratio(lam, ref) <= 1.0, (near, ratio(lam, ref))
+    lml = mdgmi.mdgmi_llr_maxlog(gf, dev(y), s2, path=path).cpu().numpy().astype(np.float64)
+    rml = orc.llr_maxlog(y, f.X, f.labels, s2)
+    assert ratio(lml, rml) <= 1.0, ratio(lml, rml)
+    say(f"[large s] {name} {path}: {near} LLRs below 2 nats, worst {ratio(lam, ref):.2f} / {ratio(lml, rml):.2f} of the bar")
