@@ -26,7 +26,8 @@ template <int DIM, int NCOL, int WAVES, int G, bool LDS_IMG, int MODE, int S = k
 __global__ __launch_bounds__(WAVES * 64) void k_mfma(
     const float* __restrict__ y, const uint32_t* __restrict__ tx, const uint4* __restrict__ img,
     const float* __restrict__ X32, const float* __restrict__ n32, const uint32_t* __restrict__ labels,
-    int64_t n, int M, int m, int ntiles, SnrArgs sa, float* __restrict__ llr, double* __restrict__ part) {
+    int64_t n, int M, int m, int ntiles, SnrArgs sa, float max_n2, float* __restrict__ llr,
+    double* __restrict__ part) {
     constexpr int NB = Blk<DIM, S>::value;
     extern __shared__ uint4 lds_img[];
     const int q_snr = blockIdx.y;
@@ -44,12 +45,15 @@ __global__ __launch_bounds__(WAVES * 64) void k_mfma(
     const uint32_t* txs = mode_is_llr(MODE) ? nullptr : tx + snr * n;
     CostAcc acc;
     HdAcc hd;
+    const float guard = mode_is_llr(MODE) ? llr_guard(s, max_n2) : 0.0f;
     const int64_t ncoltiles = (n + 32 * NCOL - 1) / (32 * NCOL);
     for (int64_t ct = (int64_t)blockIdx.x * WAVES + wave; ct < ncoltiles; ct += (int64_t)gridDim.x * WAVES) {
         if constexpr (mode_is_ml(MODE))
-            mfma_coltile_ml<DIM, NCOL, G, MODE, S>(A, ys, txs, n, ct, M, m, ntiles, s, X32, labels, llr, acc);
+            mfma_coltile_ml<DIM, NCOL, G, MODE, S>(A, ys, txs, n, ct, M, m, ntiles, s, X32, labels, llr, acc,
+                                                   guard);
         else
-            mfma_coltile<DIM, NCOL, G, MODE, S>(A, ys, txs, n, ct, M, m, ntiles, s, X32, labels, llr, acc, &hd);
+            mfma_coltile<DIM, NCOL, G, MODE, S>(A, ys, txs, n, ct, M, m, ntiles, s, X32, labels, llr, acc, &hd,
+                                                guard);
     }
     (void)n32;
     double* dst = part + ((int64_t)q_snr * gridDim.x + blockIdx.x) * (MODE == kModeHd ? kNPartHd : kNPart);
@@ -77,7 +81,7 @@ hipError_t launch_vm(const mdgmi_format* f, const float* y, const uint32_t* tx, 
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_mfma<DIM, NCOL, WAVES, G, LDS, MODE, S>), grid, block, lds, st, y, tx, img, f->d_X32,
-                       f->d_n32, f->d_labels, n, f->M, f->m, ntiles, sa, llr, part);
+                       f->d_n32, f->d_labels, n, f->M, f->m, ntiles, sa, (float)f->max_norm2, llr, part);
     return hipGetLastError();
 }
 

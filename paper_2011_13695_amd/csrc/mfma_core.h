@@ -612,7 +612,7 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
                                              const uint32_t* __restrict__ txs, int64_t n, int64_t ct, int M,
                                              int m, int ntiles, float s, const float* __restrict__ X32,
                                              const uint32_t* __restrict__ labels, float* __restrict__ llr,
-                                             CostAcc& acc, HdAcc* hd = nullptr) {
+                                             CostAcc& acc, HdAcc* hd = nullptr, float guard = 0.0f) {
     constexpr bool LLR = MODE == kModeLlr;
     constexpr bool HD = MODE == kModeHd;
     constexpr int NB = Blk<DIM, S>::value;
@@ -670,8 +670,12 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
                 llr_far_pass<DIM, G, MAXHI, S>(A, ys, n, i, M, m, ntiles, s, X32, llr, p0, p1);
                 continue;
             }
+            constexpr int NJ = (MDGMI_MAX_BITS + 1) / 2;
+            float lam[NJ];
+            bool near0 = false;
 #pragma unroll
-            for (int j = 0; j < (MDGMI_MAX_BITS + 1) / 2; j++) {
+            for (int j = 0; j < NJ; j++) {
+                lam[j] = 0.0f;
                 if (2 * j < m) {  // uniform
                     const int ke = 2 * j, ko = ke + 1 < MDGMI_MAX_BITS ? ke + 1 : ke;
                     float S0e, S1e, S0o = 1.0f, S1o = 1.0f;
@@ -684,8 +688,29 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
                     if (ko < m) full_sums(p0, p1, ko, S0o, S1o);
                     const int k = ke + h;
                     const float s0 = h ? S0o : S0e, s1 = h ? S1o : S1e;
-                    if (k < m && i < n) llr[i * m + k] = log2_ratio_fast(s1, s0) * (float)kLn2;
+                    lam[j] = log2_ratio_fast(s1, s0);
+                    if (k < m) near0 = near0 || fabsf(lam[j]) < guard;
                 }
+            }
+            // an LLR near zero at a large s (either half's bits): the whole
+            // sample is recomputed on the per-class path by lane half 0
+            const Halves hz = halves(near0 ? 1.0f : 0.0f);
+            const bool redo = hz.lo + hz.hi > 0.0f;
+            if (i >= n) continue;
+            if (!redo) {
+#pragma unroll
+                for (int j = 0; j < NJ; j++) {
+                    const int k = 2 * j + h;
+                    if (k < m) llr[i * m + k] = lam[j] * (float)kLn2;
+                }
+            } else if (h == 0) {
+                float yc[DIM], ls0[MDGMI_MAX_BITS], ls1[MDGMI_MAX_BITS], ltot, ti;
+#pragma unroll
+                for (int d = 0; d < DIM; d++) yc[d] = ys[i * DIM + d];
+                exact_classes_f32<DIM>(yc, X32, M, m, s, -1, ls0, ls1, ltot, ti);
+#pragma unroll
+                for (int k = 0; k < MDGMI_MAX_BITS; k++)
+                    if (k < m) llr[i * m + k] = (ls1[k] - ls0[k]) * (float)kLn2;
             }
             continue;
         }
@@ -884,7 +909,7 @@ __device__ __forceinline__ void mfma_coltile_ml(const uint4* __restrict__ A, con
                                                 const uint32_t* __restrict__ txs, int64_t n, int64_t ct, int M,
                                                 int m, int ntiles, float s, const float* __restrict__ X32,
                                                 const uint32_t* __restrict__ labels, float* __restrict__ llr,
-                                                CostAcc& acc) {
+                                                CostAcc& acc, float guard = 0.0f) {
     constexpr int NB = Blk<DIM, S>::value;
     constexpr int MAXHI = MDGMI_MAX_BITS - 5;
     const int lane = threadIdx.x & 63;
@@ -920,6 +945,7 @@ __device__ __forceinline__ void mfma_coltile_ml(const uint4* __restrict__ A, con
         full_max(p0, p1, 2, B0, B1);
         const float best = fmaxf(B0, B1);
         bool far = !(best >= kFarLog2) || !fin[c];
+        bool near0 = false;  // an LLR near zero at a large s (LLR output)
         float cg = 0.0f;
         constexpr int NJ = (MDGMI_MAX_BITS + 1) / 2;
         float lam[NJ];
@@ -939,6 +965,7 @@ __device__ __forceinline__ void mfma_coltile_ml(const uint4* __restrict__ A, con
                 const int k = ke + h;
                 const float u0 = h ? U0o : U0e, u1 = h ? U1o : U1e;
                 lam[j] = u1 - u0;  // log2 units
+                if (MODE == kModeMlLlr && k < m) near0 = near0 || fabsf(lam[j]) < guard;
                 if (MODE == kModeMlGmi && k < m) {
                     const uint32_t row = i < n ? txs[i] : 0u;
                     const uint32_t slot = labels[row < (uint32_t)M ? row : 0u];
@@ -947,6 +974,11 @@ __device__ __forceinline__ void mfma_coltile_ml(const uint4* __restrict__ A, con
             }
         }
         if (MODE == kModeMlGmi) cg = half_sum(cg);
+        if (MODE == kModeMlLlr) {
+            // either half's bits: both halves take the per-class path together
+            const Halves hz = halves(near0 ? 1.0f : 0.0f);
+            far = far || hz.lo + hz.hi > 0.0f;
+        }
         if (i >= n) continue;
         if (!far) {
             if (MODE == kModeMlLlr) {

@@ -268,13 +268,14 @@ def test_small_instances_in_a_batch(shape, path):
 
 
 @pytest.mark.parametrize("name", ["64-PAM", "16-QAM"])
-@pytest.mark.parametrize("path", ["mfma", "direct"])
+@pytest.mark.parametrize("path", ["mfma", "mfma32", "direct"])
 def test_llr_near_zero_at_large_s(orc, shape, name, path):
     """At s max||x||^2 = 1.3e4 (inside the fp16 range of the split) the
     expanded distance form cancels terms of that size; LLRs near zero are
     recomputed on the per-class path, so exact and max-log LLRs meet the
-    1e-3 max(|lambda|, 1) bar there too."""
-    shape(-1)
+    1e-3 max(|lambda|, 1) bar there too: 4x4 shape, 32 x 32 shape, direct."""
+    shape(BIG if path == "mfma32" else -1)
+    path = "mfma" if path == "mfma32" else path
     f = w.pam(6) if name == "64-PAM" else w.square_qam(4)
     gf = mdgmi.Format.of(f)
     max_n2 = float((f.X ** 2).sum(1).max())
