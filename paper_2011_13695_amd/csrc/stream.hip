@@ -34,7 +34,9 @@ struct mdgmi_stream {
     std::vector<hipEvent_t> ev_ring;          // per result slot: its accumulation has run
     std::vector<void*> d_y, d_tx, d_ws;      // per lane: input buffers, workspace (partials + image)
     std::vector<int> lane_blocks;            // blocks of the lane's last launch
-    size_t part_bytes = 0;
+    size_t part_bytes = 0;                   // partials region of a lane workspace
+    size_t ws_bytes = 0;                     // whole lane workspace (partials + image)
+    int max_blocks = 0;                      // blocks per launch the partials region holds
     double* d_results = nullptr;  // [ring][MDGMI_NFIELDS]
     double* d_total = nullptr;    // [kNPart + 1]: running sums and sample count
 };
@@ -130,6 +132,8 @@ int mdgmi_stream_create(const mdgmi_format* fmt, double sigma2, int64_t buffer_n
     s->sa = snr_args(&sigma2, 0, 1);
     const GmiPlan pl = plan_gmi(fmt, buffer_n, 1, p);
     s->part_bytes = align_up(pl.part_bytes);
+    s->ws_bytes = pl.total;
+    s->max_blocks = pl.cfg.blocks_per_snr;
     const size_t ybytes = (size_t)buffer_n * fmt->dim * (p == MDGMI_PATH_F64 ? sizeof(double) : sizeof(float));
     bool ok = hipStreamCreateWithFlags(&s->acc_stream, hipStreamNonBlocking) == hipSuccess;
     s->lane.assign(n_lanes, nullptr);
@@ -171,6 +175,12 @@ int mdgmi_stream_push(mdgmi_stream* s, const void* y, const uint32_t* tx_idx, in
     if (from_host != 0 && from_host != 1) return MDGMI_E_ARG;
     int rc = check_device(s->fmt);
     if (rc != MDGMI_OK) return rc;
+    // the plan of this buffer (as mdgmi_gmi would launch it), held to the
+    // workspace sized at create: a tuning change since then could ask for
+    // more blocks or a larger image
+    GmiPlan pl = plan_gmi(s->fmt, n, 1, s->path);
+    if (pl.cfg.blocks_per_snr > s->max_blocks) pl.cfg.blocks_per_snr = s->max_blocks;
+    if (align_up(pl.image_bytes) > s->ws_bytes - s->part_bytes) return MDGMI_E_WORKSPACE;
     const int64_t b = s->pushed;
     const int k = (int)(b % s->n_lanes);
     hipStream_t st = s->lane[k];
@@ -186,7 +196,6 @@ int mdgmi_stream_push(mdgmi_stream* s, const void* y, const uint32_t* tx_idx, in
     }
     // the lane's partials are free once its previous buffer was accumulated
     if (b >= s->n_lanes && hipStreamWaitEvent(st, s->ev_acc[k], 0) != hipSuccess) return MDGMI_E_HIP;
-    const GmiPlan pl = plan_gmi(s->fmt, n, 1, s->path);
     double* part = (double*)s->d_ws[k];
     void* image = (char*)s->d_ws[k] + s->part_bytes;
     if (launch_exact(s->fmt, s->path, yd, td, n, s->sa, kModeGmi, nullptr, part, image, pl.cfg, st) != hipSuccess)

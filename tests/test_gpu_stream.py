@@ -5,7 +5,9 @@
 * the running total equals the sample-weighted combination of the buffers
   (1e-12) and the oracle over all samples (1e-4), and is bit-identical for
   1, 3 and 8 lanes and for host (pinned and pageable) and device inputs;
-* the result ring, reset, wait semantics and argument errors.
+* the result ring, reset, wait semantics and argument errors;
+* a launch-shape change between create and push (tuning) stays within the
+  workspace sized at create and gives the same GMI/MI.
 """
 import sys
 
@@ -175,3 +177,30 @@ def test_benchmark_configuration(orc, name):
     se_g = np.std(cg, ddof=1) / np.sqrt(len(cg))
     assert abs((f.m - cg.mean()) - rows[2, 0]) <= 5 * se_g + 1e-9
     say(f"[stream] {name} 2^22 x 3 on 4 lanes: GMI {tot[0]:.5f}")
+
+
+def test_shape_change_between_create_and_push(orc):
+    """The 16-QAM format runs on the per-sample 4x4 shape by default and on
+    32 x 32 tiles under variant 4; the two launch different block counts.
+    Streams created under one and pushed under the other stay within their
+    workspaces and agree with the oracle."""
+    f = w.format_16qam()
+    gf = mdgmi.Format.of(f)
+    s2 = float(w.sigma2_from_snr_db(8.0, 2))
+    bufs = buffers(f, s2, [4096, 4096, 1500], seed=13)
+    ref = orc.gmi(np.concatenate([b[0] for b in bufs]).astype(np.float64), np.concatenate([b[1] for b in bufs]),
+                  f.X, f.labels, s2)
+    try:
+        for first, then in ((-1, 4), (4, -1)):
+            mdgmi.mdgmi_set_tuning(first)
+            st = mdgmi.Stream(gf, s2, 4096, n_lanes=2, path="mfma")
+            mdgmi.mdgmi_set_tuning(then)
+            for y, tx in bufs:
+                st.push(torch.from_numpy(y).cuda(), torch.from_numpy(tx.view(np.int32)).cuda())
+            tot = st.total()
+            st.close()
+            assert tot[4] == sum(len(b[0]) for b in bufs) and tot[5] == 0
+            assert np.max(np.abs(tot[:2] - ref[:2])) <= 1e-4
+            say(f"[stream] shape {first} -> {then}: GMI {tot[0]:.6f} vs oracle {ref[0]:.6f}")
+    finally:
+        mdgmi.mdgmi_set_tuning(-1)
