@@ -135,7 +135,12 @@ int mdgmi_llr_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t path, s
 /* Exact per-bit LLRs of n samples at one noise variance.
  *   y    device [n][dim] (double for MDGMI_PATH_F64, else float)
  *   llr  device [n][m]   (same element type), nats, column k = label bit k
- *   ws   device workspace of at least mdgmi_llr_workspace_size bytes. */
+ *   ws   device workspace of at least mdgmi_llr_workspace_size bytes.
+ * FP32 paths: within about 1e-3 max(|llr|, 1) nats of the exact values.
+ * Classes far from y take a per-class path; where s max||x||^2 > 1000
+ * (s = log2(e) / (2 sigma2)) a sample with an LLR near zero is recomputed
+ * there too, since the expanded distance form loses absolute accuracy in
+ * proportion to s. Non-finite samples give NaN LLRs. */
 int mdgmi_llr(const mdgmi_format* fmt, const void* y, int64_t n, double sigma2, void* llr,
               int32_t path, void* ws, size_t ws_bytes, void* stream);
 
