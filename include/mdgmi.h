@@ -62,8 +62,8 @@ typedef enum {
     MDGMI_PATH_F32_MFMA_F16SPLIT = 2,/* distance term on MFMA, fp16 hi+lo split,  */
                                      /* FP32 accumulate; log-sum-exp in FP32;     */
                                      /* needs 2s max|x| and s max||x||^2 < 3e4;   */
-                                     /* 32x32 tiles, or for 4 <= M <= 256 (8-D:   */
-                                     /* M <= 64) one sample per lane on 4x4 blocks */
+                                     /* 32x32 tiles, or for 4 <= M <= 512 (8-D:   */
+                                     /* M <= 256) one sample per lane on 4x4 blocks */
     MDGMI_PATH_F32_MFMA_BF16SPLIT = 3,/* distance term on MFMA, bf16 three-part  */
                                      /* split (six products per coordinate,       */
                                      /* ~24 bits), FP32 accumulate: any SNR; one  */
@@ -407,7 +407,7 @@ int mdgmi_mlp_load(mdgmi_mlp* net, const char* path);
  * 0..7 selects 32x32 tiles with (sample columns per wave, waves per block) =
  * (1,4), (2,4), (1,8), (2,8), (1,16), (1,12) with the operand image in LDS,
  * and (1,16), (1,8) reading it from L2; v = 8 the per-sample 4x4-block shape
- * (formats with 4 <= M <= 256, 8-D M <= 64; others keep their default);
+ * (formats with 4 <= M <= 512, 8-D M <= 256; others keep their default);
  * v < 0 restores the built-in choice (the autotuner's, else the 4x4 shape
  * where it serves M, else a default). Process-wide; affects workspace sizes,
  * so set it before sizing workspaces. Always MDGMI_OK. */

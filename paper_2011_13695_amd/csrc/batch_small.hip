@@ -37,13 +37,10 @@ __device__ __forceinline__ void run_small_dim(const BatchInst& D, int64_t s0, in
         case 16: run_small_item<DIM, 4>(D, s0, s1, acc); break;
         case 32: run_small_item<DIM, 8>(D, s0, s1, acc); break;
         case 64: run_small_item<DIM, 16>(D, s0, s1, acc); break;
+        case 128: run_small_item<DIM, 32>(D, s0, s1, acc); break;
+        case 256: run_small_item<DIM, 64>(D, s0, s1, acc); break;
         default:
-            if constexpr (DIM < 8) {
-                if (D.M == 128)
-                    run_small_item<DIM, 32>(D, s0, s1, acc);
-                else
-                    run_small_item<DIM, 64>(D, s0, s1, acc);
-            }
+            if constexpr (DIM < 8) run_small_item<DIM, 128>(D, s0, s1, acc);
             break;
     }
 }

@@ -88,8 +88,8 @@ hipError_t launch_direct(const mdgmi_format* f, const float* y, const uint32_t* 
                          const SnrArgs& sa, int mode, float* llr, double* part, float* image,
                          LaunchCfg cfg, hipStream_t st);
 
-// Per-sample 4x4-block shape of the fp16-split path for 4 <= M <= 256
-// (8-D: M <= 64), exact_mfma4.hip; used by launch_mfma where it applies.
+// Per-sample 4x4-block shape of the fp16-split path for 4 <= M <= 512
+// (8-D: M <= 256), exact_mfma4.hip; used by launch_mfma where it applies.
 bool small_shape_fits(const mdgmi_format* f);
 // whether the fp16-split path runs f on that shape (tuning table, override)
 bool prefers_small(const mdgmi_format* f);

@@ -3,8 +3,8 @@
 // ragged persistent batch (batch.hip).
 #pragma once
 
-// The FP32 exact demapper for small constellations (4 <= M <= 256; 8-D up to
-// M = 64) with the distance term on the matrix cores and one sample per lane.
+// The FP32 exact demapper for small constellations (4 <= M <= 512; 8-D up to
+// M = 256) with the distance term on the matrix cores and one sample per lane.
 //
 // v_mfma_f32_4x4x4_16b_f16 evaluates 16 independent 4 x 4 blocks with K = 4:
 // lane 4b + i supplies row i of block b's A operand (four halves), lane

@@ -1,5 +1,5 @@
-"""The per-sample 4x4-block shape of the fp16-split MFMA path (4 <= M <= 256,
-8-D up to M = 64; one sample per lane, v_mfma_f32_4x4x4_16b_f16 with the
+"""The per-sample 4x4-block shape of the fp16-split MFMA path (4 <= M <= 512,
+8-D up to M = 256; one sample per lane, v_mfma_f32_4x4x4_16b_f16 with the
 point operands broadcast from one block to all sixteen) through the
 C ABI, against the FP64 oracle on the same samples, in every mode:
 * GMI/MI within 1e-4 bit with exact sample counts; exact LLRs within
@@ -73,8 +73,8 @@ def fmt(dim, M):
 
 
 CASES = [(1, 4), (1, 16), (1, 64), (1, 256), (2, 4), (2, 8), (2, 16), (2, 32), (2, 64), (2, 128),
-         (2, 256), (4, 4), (4, 16), (4, 32), (4, 64), (4, 128), (4, 256), (8, 4), (8, 8), (8, 16),
-         (8, 32), (8, 64)]
+         (2, 256), (2, 512), (4, 4), (4, 16), (4, 32), (4, 64), (4, 128), (4, 256), (4, 512), (8, 4),
+         (8, 8), (8, 16), (8, 32), (8, 64), (8, 128), (8, 256)]
 
 
 def sigma2s_for(f):
@@ -244,7 +244,7 @@ def test_small_instances_in_a_batch(shape, path):
     shape(-1)
     mdgmi.mdgmi_tune_clear()
     specs = [(1, 4, 1), (1, 64, 255), (2, 16, 257), (2, 256, 70001), (4, 64, 4099), (4, 128, 600),
-             (8, 8, 63), (8, 64, 9000), (2, 4, 1000), (4, 256, 20000)]
+             (8, 8, 63), (8, 64, 9000), (2, 4, 1000), (4, 256, 20000), (4, 512, 3000), (8, 256, 2000)]
     items, refs = [], []
     for k, (dim, M, n) in enumerate(specs):
         f = fmt(dim, M)
