@@ -266,11 +266,14 @@ int oracle_llr_maxlog(const double* y, int64_t n, int dim, const double* X, cons
  * Hard decisions (FP64). Two decisions per received sample:
  *   bitwise MAP   b_hat_k = 1 if lambda_k > 0, else 0   (the sign of the
  *                 exact LLR: the hard decision of bit-metric decoding)
- *   nearest point j_hat = argmin_j ||y - x_j||^2; a tie that includes the
- *                 sent point i is decided for i (measure zero for continuous
- *                 noise; the choice fixes coincident-point formats)
+ *   nearest point j_hat = argmin_j ||y - x_j||^2; among points at the same
+ *                 smallest distance the one with the lowest label is decided
+ *                 (a fixed rule a receiver can apply: it does not know the
+ *                 sent point; ties have probability zero under continuous
+ *                 noise except where two labels share one point)
  * Per sample: errs[s] = number of k with b_hat_k != b_k(i) (0..m) and
- * sym[s] = 1 if some j has ||y - x_j|| < ||y - x_i||, else 0. The estimates are
+ * sym[s] = 1 if j_hat != i, i.e. some j has ||y - x_j|| < ||y - x_i||, or
+ * ||y - x_j|| = ||y - x_i|| with label(j) < label(i); else 0. The estimates are
  *   BER = sum errs / (n m),  SER = sum sym / n.
  * Non-finite samples count as errors and are reported separately.
  * ---------------------------------------------------------------------- */
@@ -286,11 +289,11 @@ static void hd_one(const double* y, int dim, const double* X, const uint32_t* la
         if (!(lam == lam)) bhat = -1; /* NaN: an error for either bit value */
         if (bhat != (int)((lab >> k) & 1u)) e++;
     }
-    /* nearest-point decision: wrong iff some other point is strictly nearer
-     * than the sent one (an exact tie is decided in favour of the sent point) */
+    /* nearest-point decision, ties to the lowest label: wrong iff another
+     * point is strictly nearer, or as near with a lower label */
     int wrong = !(t[row] == t[row]);
     for (int j = 0; j < M; j++)
-        if (t[j] < t[row]) wrong = 1;
+        if (t[j] < t[row] || (t[j] == t[row] && labels[j] < lab)) wrong = 1;
     *errs = e;
     *sym = wrong;
 }

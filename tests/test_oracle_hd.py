@@ -87,23 +87,34 @@ def test_nonfinite_samples_are_errors(orc):
     assert r[3] == 1 and r[1] >= 0.5 and r[0] >= 0.5
 
 
-def test_exact_ties_go_to_the_sent_point(orc):
-    """A sample exactly half-way between two points, or on a point that two
-    labels share, is no symbol error for either of them; moved off the
-    bisector towards the other point, it is one."""
+def test_exact_ties_go_to_the_lowest_label(orc):
+    """A sample exactly half-way between two points is decided for the one
+    with the lower label: a symbol error only when the other was sent; moved
+    off the bisector, the nearer point wins whatever its label. Where two
+    labels share one point, the lower label is always decided, so sending
+    the higher one is always a symbol error (its bit decisions are unaffected:
+    they come from the LLR signs)."""
     f = w.square_qam(2)
     a, b = 0, 1
     if np.count_nonzero(f.X[a] != f.X[b]) != 1:   # want neighbours on one axis
         b = 2
     mid = 0.5 * (f.X[a] + f.X[b])
-    for sent in (a, b):
-        r = orc.hd(mid[None], np.array([sent], np.uint32), f.X, f.labels, 0.1)
-        assert r[1] == 0.0
+    d = ((mid[None] - f.X[[a, b]]) ** 2).sum(1)
+    assert d[0] == d[1]                           # an exact tie in FP64
+    lo, hi = (a, b) if f.labels[a] < f.labels[b] else (b, a)
+    assert orc.hd(mid[None], np.array([lo], np.uint32), f.X, f.labels, 0.1)[1] == 0.0
+    assert orc.hd(mid[None], np.array([hi], np.uint32), f.X, f.labels, 0.1)[1] == 1.0
     off = mid + 1e-3 * (f.X[b] - f.X[a])
     assert orc.hd(off[None], np.array([a], np.uint32), f.X, f.labels, 0.1)[1] == 1.0
     assert orc.hd(off[None], np.array([b], np.uint32), f.X, f.labels, 0.1)[1] == 0.0
     X = f.X.copy()
     X[3] = X[2]                                  # two labels on one point
     g = w.Format("dup-qpsk", X, f.labels.copy())
-    for sent in (2, 3):
-        assert orc.hd(X[2][None] + 0.01, np.array([sent], np.uint32), g.X, g.labels, 0.1)[1] == 0.0
+    lo, hi = (2, 3) if g.labels[2] < g.labels[3] else (3, 2)
+    assert orc.hd(X[2][None] + 0.01, np.array([lo], np.uint32), g.X, g.labels, 0.1)[1] == 0.0
+    assert orc.hd(X[2][None] + 0.01, np.array([hi], np.uint32), g.X, g.labels, 0.1)[1] == 1.0
+    # the rule follows labels, not rows: swap the two rows' labels
+    lab = g.labels.copy()
+    lab[2], lab[3] = lab[3], lab[2]
+    assert orc.hd(X[2][None] + 0.01, np.array([hi], np.uint32), g.X, lab, 0.1)[1] == 0.0
+    assert orc.hd(X[2][None] + 0.01, np.array([lo], np.uint32), g.X, lab, 0.1)[1] == 1.0
