@@ -167,9 +167,14 @@ int mdgmi_gmi(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, in
  * computes, plus per SNR point:
  *   MDGMI_F_BER  fraction of (sample, bit) pairs whose bitwise MAP decision
  *                (bit k = 1 iff lambda_k > 0) differs from the sent bit;
- *   MDGMI_F_SER  fraction of samples for which some other point is strictly
- *                nearer to y than the sent one (nearest-point decision;
- *                an exact tie with the sent point counts as correct).
+ *   MDGMI_F_SER  fraction of samples whose nearest-point decision is not
+ *                the sent point; among points at the same distance the
+ *                lowest label is decided (a fixed rule, as a receiver that
+ *                does not know the sent point must use). A point that
+ *                shares its coordinates with a lower label is therefore
+ *                never decided. The FP32 paths decide from rounded
+ *                metrics: near-ties between distinct points go either way
+ *                within that rounding.
  * A sample with non-finite y counts m bit errors and one symbol error.
  *   out  device [n_snr][MDGMI_NFIELDS_HD] double.
  * Paths as for mdgmi_gmi (the MFMA path runs its 16-wave single-column

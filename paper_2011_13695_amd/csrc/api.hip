@@ -274,16 +274,36 @@ int mdgmi_format_create(const double* X_host, const uint32_t* labels_host, int32
         n32[slot] = (float)n2;
         f->max_norm2 = std::max(f->max_norm2, n2);
     }
+    // Rows sharing their coordinates with a lower label: sort rows by
+    // (coordinates, label); within a run of equal points all but the first
+    // carry kTwinBit.
+    std::vector<uint32_t> lab_hd(labels_host, labels_host + M), order((size_t)M);
+    for (int32_t r = 0; r < M; r++) order[r] = (uint32_t)r;
+    auto pt = [&](uint32_t r, int d) { return X_host[(size_t)r * dim + d]; };
+    auto same = [&](uint32_t a, uint32_t b) {
+        for (int d = 0; d < dim; d++)
+            if (!(pt(a, d) == pt(b, d))) return false;
+        return true;
+    };
+    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        for (int d = 0; d < dim; d++)
+            if (pt(a, d) != pt(b, d)) return pt(a, d) < pt(b, d);
+        return labels_host[a] < labels_host[b];
+    });
+    for (int32_t k = 1; k < M; k++)
+        if (same(order[k - 1], order[k])) lab_hd[order[k]] |= kTwinBit;
     f->h_X64 = new double[(size_t)M * dim];
     std::memcpy(f->h_X64, X64.data(), sizeof(double) * X64.size());
     bool ok = hipMalloc(&f->d_X64, sizeof(double) * X64.size()) == hipSuccess &&
               hipMalloc(&f->d_X32, sizeof(float) * X32.size()) == hipSuccess &&
               hipMalloc(&f->d_n32, sizeof(float) * n32.size()) == hipSuccess &&
-              hipMalloc(&f->d_labels, sizeof(uint32_t) * (size_t)M) == hipSuccess;
+              hipMalloc(&f->d_labels, sizeof(uint32_t) * (size_t)M) == hipSuccess &&
+              hipMalloc(&f->d_labels_hd, sizeof(uint32_t) * (size_t)M) == hipSuccess;
     ok = ok && hipMemcpy(f->d_X64, X64.data(), sizeof(double) * X64.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(f->d_X32, X32.data(), sizeof(float) * X32.size(), hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(f->d_n32, n32.data(), sizeof(float) * n32.size(), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(f->d_labels, labels_host, sizeof(uint32_t) * (size_t)M, hipMemcpyHostToDevice) == hipSuccess;
+         hipMemcpy(f->d_labels, labels_host, sizeof(uint32_t) * (size_t)M, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(f->d_labels_hd, lab_hd.data(), sizeof(uint32_t) * (size_t)M, hipMemcpyHostToDevice) == hipSuccess;
     if (!ok) {
         mdgmi_format_destroy(f);
         return MDGMI_E_HIP;
@@ -298,6 +318,7 @@ int mdgmi_format_destroy(mdgmi_format* f) {
     if (f->d_X32) (void)hipFree(f->d_X32);
     if (f->d_n32) (void)hipFree(f->d_n32);
     if (f->d_labels) (void)hipFree(f->d_labels);
+    if (f->d_labels_hd) (void)hipFree(f->d_labels_hd);
     delete[] f->h_X64;
     delete f;
     return MDGMI_OK;

@@ -158,7 +158,8 @@ __device__ __forceinline__ void direct_sample(const float* __restrict__ im, cons
         // a sent row outside [0, M) gives a NaN cost instead of a stray read
         const uint32_t row = txs[i];
         const bool row_ok = row < (uint32_t)M;
-        const uint32_t slot = labels[row_ok ? row : 0u];
+        const uint32_t lw = labels[row_ok ? row : 0u];
+        const uint32_t slot = lw & kLabelMask;
         const float* ri = im + (size_t)slot * REC;
         float ui = K - ri[DIM];
 #pragma unroll
@@ -204,7 +205,10 @@ __device__ __forceinline__ void direct_sample(const float* __restrict__ im, cons
                 if (k < m) be += (S1[k] > S0[k] ? 1 : 0) != (int)((slot >> k) & 1u);
             const bool finite = cg == cg && cm == cm && ui == ui;
             hd->be += finite ? (double)be : (double)m;
-            hd->se += (finite && !(umax > ui)) ? 0.0 : 1.0;
+            // another point strictly nearer, or the sent point's coordinates
+            // shared with a lower label (ties go to the lowest label)
+            const bool twin = (lw & kTwinBit) != 0u;
+            hd->se += (finite && !(umax > ui) && !twin) ? 0.0 : 1.0;
         }
     }
 }

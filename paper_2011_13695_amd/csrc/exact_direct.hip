@@ -62,7 +62,7 @@ hipError_t launch_direct_t(const mdgmi_format* f, const float* y, const uint32_t
                            f->d_labels, n, f->M, f->m, sa, (float)f->max_norm2, llr, part);
     else if (mode == kModeHd)
         hipLaunchKernelGGL((k_direct<DIM, CHB, G, kModeHd>), grid, block, 0, st, y, tx, image, f->d_X32,
-                           f->d_labels, n, f->M, f->m, sa, (float)f->max_norm2, llr, part);
+                           f->d_labels_hd, n, f->M, f->m, sa, (float)f->max_norm2, llr, part);
     else
         hipLaunchKernelGGL((k_direct<DIM, CHB, G, kModeGmi>), grid, block, 0, st, y, tx, image, f->d_X32,
                            f->d_labels, n, f->M, f->m, sa, (float)f->max_norm2, llr, part);

@@ -114,7 +114,8 @@ __global__ __launch_bounds__(kF64Threads) void k_exact_f64(const double* __restr
             // a sent row outside [0, M) gives a NaN cost instead of a stray read
             const uint32_t row = txs[i];
             const bool row_ok = row < (uint32_t)M;
-            const uint32_t slot = labels[row_ok ? row : 0u];
+            const uint32_t lw = labels[row_ok ? row : 0u];
+            const uint32_t slot = lw & kLabelMask;
             double cg = 0.0;
 #pragma unroll
             for (int k = 0; k < MDGMI_MAX_BITS; k++) {
@@ -131,7 +132,9 @@ __global__ __launch_bounds__(kF64Threads) void k_exact_f64(const double* __restr
             acc.add(cg * kLog2e, cm * kLog2e);
             if (MODE == kModeHd) {
                 // bitwise MAP decisions (sign of the LLR) and the nearest
-                // point (some other point strictly nearer than the sent one)
+                // point (some other point strictly nearer than the sent one,
+                // or its coordinates shared with a lower label: ties go to
+                // the lowest label)
                 int be = 0;
 #pragma unroll
                 for (int k = 0; k < MDGMI_MAX_BITS; k++) {
@@ -143,7 +146,8 @@ __global__ __launch_bounds__(kF64Threads) void k_exact_f64(const double* __restr
                 }
                 const bool finite = cg == cg && cm == cm;
                 hd.be += finite ? (double)be : (double)m;
-                hd.se += (finite && !(tmin < ti)) ? 0.0 : 1.0;
+                const bool twin = (lw & kTwinBit) != 0u;
+                hd.se += (finite && !(tmin < ti) && !twin) ? 0.0 : 1.0;
             }
         }
     }
@@ -176,7 +180,7 @@ hipError_t launch_f64(const mdgmi_format* f, const double* y, const uint32_t* tx
                                f->d_labels, n, f->M, f->m, sa, llr, part);                             \
         else if (mode == kModeHd)                                                                      \
             hipLaunchKernelGGL((k_exact_f64<D, kModeHd>), grid, block, 0, st, y, tx, f->d_X64,        \
-                               f->d_labels, n, f->M, f->m, sa, llr, part);                             \
+                               f->d_labels_hd, n, f->M, f->m, sa, llr, part);                          \
         else if (mode == kModeMlLlr)                                                                   \
             hipLaunchKernelGGL((k_exact_f64<D, kModeMlLlr>), grid, block, 0, st, y, tx, f->d_X64,     \
                                f->d_labels, n, f->M, f->m, sa, llr, part);                             \

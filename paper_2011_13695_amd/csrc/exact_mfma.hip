@@ -81,7 +81,8 @@ hipError_t launch_vm(const mdgmi_format* f, const float* y, const uint32_t* tx, 
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_mfma<DIM, NCOL, WAVES, G, LDS, MODE, S>), grid, block, lds, st, y, tx, img, f->d_X32,
-                       f->d_n32, f->d_labels, n, f->M, f->m, ntiles, sa, (float)f->max_norm2, llr, part);
+                       f->d_n32, MODE == kModeHd ? f->d_labels_hd : f->d_labels, n, f->M, f->m, ntiles, sa,
+                       (float)f->max_norm2, llr, part);
     return hipGetLastError();
 }
 

@@ -59,8 +59,8 @@ hipError_t launch_small_t(const mdgmi_format* f, const float* y, const uint32_t*
                           int mode, float* llr, double* part, const uint2* img, int blocks, hipStream_t st) {
     const dim3 grid(blocks, sa.n_snr), block(kSmallThreads);
 #define MDGMI_SMALL(MD)                                                                                      \
-    hipLaunchKernelGGL((k_small<DIM, NG, MD>), grid, block, 0, st, y, tx, img, f->d_X32, f->d_labels, n, sa, \
-                       (float)f->max_norm2, llr, part);                                                      \
+    hipLaunchKernelGGL((k_small<DIM, NG, MD>), grid, block, 0, st, y, tx, img, f->d_X32,                    \
+                       MD == kModeHd ? f->d_labels_hd : f->d_labels, n, sa, (float)f->max_norm2, llr, part); \
     break;
     switch (mode) {
         case kModeLlr:

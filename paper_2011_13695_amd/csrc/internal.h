@@ -17,6 +17,10 @@ struct mdgmi_format {
     float* d_X32 = nullptr;       // [M][dim]
     float* d_n32 = nullptr;       // [M] ||x||^2
     uint32_t* d_labels = nullptr; // [M] caller row -> label (= slot)
+    // [M] as d_labels, with kTwinBit set on rows whose point has the same
+    // coordinates as a point with a lower label (hard-decision launches read
+    // this copy: the nearest-point decision goes to the lowest label)
+    uint32_t* d_labels_hd = nullptr;
     double max_abs = 0.0;         // max_j,d |x_jd|
     double max_norm2 = 0.0;       // max_j ||x_j||^2
     double* h_X64 = nullptr;      // host copy, label-ordered [M][dim]
@@ -38,6 +42,8 @@ __host__ __device__ constexpr bool mode_is_ml(int mode) { return mode == kModeMl
 // what the final reduction writes: GMI/MI, + hard decisions, or GMI only
 constexpr int kReduceGmi = 0, kReduceHd = 1, kReduceMl = 2;
 constexpr int kMaxSnrPerLaunch = 32;
+constexpr uint32_t kTwinBit = 1u << 16;   // in d_labels_hd; labels are < 2^12
+constexpr uint32_t kLabelMask = kTwinBit - 1u;
 // Exponents are taken relative to a fixed offset: e_j = 2^(kBias - t_j) with
 // t_j = ||y - x_j||^2 / (2 sigma2) * log2(e) >= 0, so no term can overflow
 // (M * 2^kBias < 2^128) and any class whose nearest point lies within

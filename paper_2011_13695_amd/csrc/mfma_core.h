@@ -717,7 +717,9 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
         // a sent row outside [0, M) gives a NaN cost instead of a stray read
         const uint32_t row = i < n ? txs[i] : 0u;
         const bool row_ok = row < (uint32_t)M;
-        const uint32_t slot = labels[row_ok ? row : 0u];
+        const uint32_t lw = labels[row_ok ? row : 0u];
+        const uint32_t slot = lw & kLabelMask;
+        const bool twin = HD && (lw & kTwinBit) != 0u;  // a lower label shares the sent point
         // u of the sent point by the matrix cores themselves: one more MFMA
         // whose row r is the sent point of sample r puts u_i(y) on the
         // diagonal, bit-identical to the value inside the class sums, so the
@@ -761,7 +763,9 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
         if (HD) {
             be = half_sum(be);
             const Halves um = halves(umax[c]);
-            sym = fmaxf(um.lo, um.hi) > ui ? 1.0f : 0.0f;  // another point strictly nearer
+            // another point strictly nearer, or the sent point's coordinates
+            // shared with a lower label (ties go to the lowest label)
+            sym = fmaxf(um.lo, um.hi) > ui || twin ? 1.0f : 0.0f;
         }
         if (h != 0 || i >= n) continue;
         float cm;
@@ -777,7 +781,7 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
             be = 0.0f;
             // the split factors may be out of range here: decide the symbol
             // from the FP32 distances as well
-            if (HD) sym = tmin < ti ? 1.0f : 0.0f;
+            if (HD) sym = tmin < ti || twin ? 1.0f : 0.0f;
 #pragma unroll
             for (int k = 0; k < MDGMI_MAX_BITS; k++) {
                 if (k < m) {

@@ -252,10 +252,13 @@ __device__ __forceinline__ void small_sample(const half4 (&a)[Sets<NG>::value][N
     // exponentials
     constexpr bool SENT = !mode_is_llr(MODE) && !ML;
     uint32_t row = 0u, slot = 0u;
+    bool twin = false;  // hard decisions: a lower label shares the sent point
     if (SENT) {
         const uint32_t r = txs[ic];
         row = valid ? r : 0u;
-        slot = labels[row < (uint32_t)M ? row : 0u];
+        const uint32_t lw = labels[row < (uint32_t)M ? row : 0u];
+        slot = lw & kLabelMask;
+        twin = HD && (lw & kTwinBit) != 0u;
     }
     half4 ad[NK];
     // Kc = {K, K, K, K}, passed through an empty asm after each group so that
@@ -391,7 +394,9 @@ __device__ __forceinline__ void small_sample(const half4 (&a)[Sets<NG>::value][N
         cg += bit_cost_sum2(S0[k] + S1[k], bk ? S1[k] : S0[k]);
         if (HD) be += (S1[k] > S0[k]) != bk ? 1.0f : 0.0f;  // bitwise MAP decision
     }
-    sym = umax > ui ? 1.0f : 0.0f;  // another point strictly nearer
+    // another point strictly nearer, or the sent point's coordinates shared
+    // with a lower label (ties go to the lowest label)
+    sym = umax > ui || twin ? 1.0f : 0.0f;
     if (ui >= kFarLog2 && !ybad) {
         cm = mi_cost2(tot, ui);
     } else {
@@ -400,7 +405,7 @@ __device__ __forceinline__ void small_sample(const half4 (&a)[Sets<NG>::value][N
         exact_classes_f32<DIM>(yv, X32, M, m, s, (int)slot, ls0, ls1, ltot, ti, HD ? &tmin : nullptr);
         cg = 0.0f;
         be = 0.0f;
-        if (HD) sym = tmin < ti ? 1.0f : 0.0f;
+        if (HD) sym = tmin < ti || twin ? 1.0f : 0.0f;
 #pragma unroll
         for (int k = 0; k < m; k++) {
             const bool bk = (slot >> k) & 1;

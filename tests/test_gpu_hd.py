@@ -11,7 +11,10 @@ Such decisions are counted from the oracle's own values (LLRs with
 |lambda| <= 2e-3 max(|lambda|, 1), distance margins within 5e-3 + 1e-5 of
 the log2 metric), and the counts must agree to within them; every other
 decision must agree exactly. The FP64 path uses 1e-9 for both.
-Edge cases: coincident points (exact ties go to the sent point), non-finite
+Exact ties between points that share their coordinates are no rounding
+question: both sides decide them for the lowest label, so they are not
+counted as ambiguous and must agree exactly.
+Edge cases: coincident points (ties go to the lowest label), non-finite
 samples (m bit errors, one symbol error), noiseless 30 dB, and samples
 received far from their sent point (the per-class path of the FP32 kernels).
 """
@@ -65,6 +68,8 @@ def ambiguous(orc, y, tx, X, labels, s2, path):
     rows = np.arange(len(tx))
     di = d[rows, tx]
     d[rows, tx] = np.inf
+    # points with the sent point's coordinates tie exactly: decided by label
+    d[np.all(X[None, :, :] == X[tx][:, None, :], axis=2)] = np.inf
     margin = s * (d.min(axis=1) - di)
     if path == "f64":
         tol = 1e-9 * np.maximum(s * di, 1.0)
@@ -124,10 +129,15 @@ def test_hd_parity(orc, name, path):
 
 @pytest.mark.parametrize("path", PATHS)
 def test_hd_coincident_points(orc, path):
+    """Rows 5 and 9 share one point (labels 5 and 9): the nearest-point
+    decision goes to the lower label, so every sample sent on row 9 and
+    received next to it is a symbol error and every such sample sent on
+    row 5 is none; the kernels must count exactly those."""
     f = w.random_shells(4, 16, 77)
     X = f.X.copy()
     X[5] = X[9]
     g = w.Format("dup4d-16", X, f.labels.copy())
+    assert g.labels[5] < g.labels[9]
     s2 = float(w.sigma2_from_snr_db(14.0, 4))
     y, tx = w.channel_samples(g, s2, seed=5, snr_slot=0, n=3001)
     rng = np.random.default_rng(55)
@@ -137,6 +147,12 @@ def test_hd_coincident_points(orc, path):
     if path != "f64":
         y = y.astype(np.float32).astype(np.float64)
     check_hd(orc, g, y[None], tx[None], np.array([s2]), path, "coincident")
+    gf = mdgmi.Format.of(g)
+    for k0, j, want in ((0, 5, 0.0), (3, 9, 1.0)):
+        ys, ts = y[k0::7], tx[k0::7]
+        assert orc.hd(ys, ts, g.X, g.labels, s2)[1] == want
+        out = mdgmi.mdgmi_gmi_hd(gf, dev(ys[None], dt(path)), dev_u32(ts[None]), [s2], path=path).cpu().numpy()
+        assert out[0, 7] == want, (j, out[0, 7])
 
 
 @pytest.mark.parametrize("path", PATHS)
