@@ -44,7 +44,7 @@ HBM_PEAK = 8.0e12
 # Reported only while the kernel sources hash to the value they were taken on.
 TRAFFIC = {"sources_sha1": "025f95dfe1f9e4b59ef0321bf45fe28d27455efc", "fetch_kib": 2831192.1875, "write_kib": 3088.0,
            "fetch_scale": 2.0, "write_scale": 1.0}
-KERNEL_SOURCES = ("mfma_core.h", "device_common.h", "internal.h", "exact_mfma.hip")
+KERNEL_SOURCES = ("mfma_core.h", "mfma_kernels.h", "device_common.h", "internal.h", "exact_mfma_d8_f16.hip")
 
 
 def kernel_sources_sha1() -> str:

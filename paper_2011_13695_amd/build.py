@@ -38,8 +38,12 @@ def sources():
     return sorted(CSRC.glob("*.hip"))
 
 
-def _compile(src: Path) -> Path:
+def _compile(src: Path, incremental: bool = False) -> Path:
     obj = BUILD / (src.stem + ".o")
+    if incremental and obj.exists():
+        newest = max(p.stat().st_mtime for p in [src, *CSRC.glob("*.h"), ROOT / "include" / "mdgmi.h"])
+        if obj.stat().st_mtime > newest:
+            return obj
     cmd = [HIPCC, *FLAGS, *EXTRA_FLAGS.get(src.name, []), "-c", str(src), "-o", str(obj)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -51,12 +55,14 @@ def _compile(src: Path) -> Path:
     return obj
 
 
-def build(jobs: int | None = None) -> Path:
+def build(jobs: int | None = None, incremental: bool = False) -> Path:
+    """Compile every source (incremental: only those older than their object
+    file's inputs, for development) and link the library."""
     BUILD.mkdir(parents=True, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     with ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda s: _compile(s, incremental), srcs))
     tmp = LIB.with_name(LIB.name + ".tmp")
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *map(str, objs), "-o", str(tmp)]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -67,4 +73,4 @@ def build(jobs: int | None = None) -> Path:
 
 
 if __name__ == "__main__":
-    print(build())
+    print(build(incremental="-i" in sys.argv[1:]))
