@@ -72,7 +72,7 @@ def fmt(dim, M):
     return w.random_shells(dim, M, 100 + 7 * dim + M)
 
 
-CASES = [(1, 4), (1, 16), (1, 64), (1, 256), (2, 4), (2, 8), (2, 16), (2, 32), (2, 64), (2, 128),
+CASES = [(1, 4), (1, 16), (1, 64), (1, 256), (1, 512), (2, 4), (2, 8), (2, 16), (2, 32), (2, 64), (2, 128),
          (2, 256), (2, 512), (4, 4), (4, 16), (4, 32), (4, 64), (4, 128), (4, 256), (4, 512), (8, 4),
          (8, 8), (8, 16), (8, 32), (8, 64), (8, 128), (8, 256)]
 
@@ -244,7 +244,8 @@ def test_small_instances_in_a_batch(shape, path):
     shape(-1)
     mdgmi.mdgmi_tune_clear()
     specs = [(1, 4, 1), (1, 64, 255), (2, 16, 257), (2, 256, 70001), (4, 64, 4099), (4, 128, 600),
-             (8, 8, 63), (8, 64, 9000), (2, 4, 1000), (4, 256, 20000), (4, 512, 3000), (8, 256, 2000)]
+             (8, 8, 63), (8, 64, 9000), (2, 4, 1000), (4, 256, 20000), (4, 512, 3000), (8, 256, 2000),
+             (1, 512, 30011)]
     items, refs = [], []
     for k, (dim, M, n) in enumerate(specs):
         f = fmt(dim, M)
