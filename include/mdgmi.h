@@ -68,6 +68,12 @@ typedef enum {
                                      /* split (six products per coordinate,       */
                                      /* ~24 bits), FP32 accumulate: any SNR; one  */
                                      /* launch shape; not in ragged batches       */
+    MDGMI_PATH_LEARNED_BF16 = 4,     /* mdgmi_gmi / mdgmi_llr only: the MLP       */
+                                     /* demapper attached by                      */
+                                     /* mdgmi_learned_calibrate (bf16 MFMA, FP32  */
+                                     /* accumulate) at the SNR points calibration */
+                                     /* routed to it, the exact fallback path     */
+                                     /* everywhere else; float y / LLRs           */
     MDGMI_PATH_AUTO = 5              /* fastest FP32 exact path for the shape:    */
                                      /* the autotuner's choice for (dim, M), else */
                                      /* the fp16 split where its 4x4 shape serves */
@@ -404,6 +410,50 @@ int mdgmi_mlp_gmi(const mdgmi_mlp* net, const mdgmi_format* fmt, const float* y,
  * fused kernel (activations in registers, weights staged in LDS), 0 for the
  * layer-by-layer GEMM path. Process-wide; returns MDGMI_E_ARG otherwise. */
 int mdgmi_mlp_set_fused(int waves);
+/* One training step in one call: features [y, (snr_db - 9.5) / 4.5] from
+ * y [n][dim] and the per-sample SNR snr_db [n] (device float, dB), then
+ * forward, BCE loss and backward as mdgmi_mlp_loss_grad, then an Adam step
+ * (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr. The network's
+ * input width is dim + 1. loss: device double (mean BCE over samples, nats).
+ * ws: mdgmi_mlp_train_workspace_size bytes. */
+int mdgmi_mlp_train_workspace_size(const mdgmi_mlp* net, int64_t n, size_t* bytes);
+int mdgmi_mlp_train_step(mdgmi_mlp* net, const float* y, const float* snr_db, const float* llr_target, int64_t n,
+                         float lr, double* loss, void* ws, size_t ws_bytes, void* stream);
+/* The network's logits read as LLRs: llr [n][out] (device float, nats) of
+ * y [n][dim] at per-sample SNRs snr_db [n] (device float, dB). Networks of
+ * the fused shape [<= 16, 256, 256, 256, <= 32] run the fused kernel and
+ * need no workspace (size 0; ws may be NULL), others the layer-by-layer
+ * GEMMs in a workspace of mdgmi_mlp_llr_workspace_size bytes. */
+int mdgmi_mlp_llr_workspace_size(const mdgmi_mlp* net, int64_t n, size_t* bytes);
+int mdgmi_mlp_llr(const mdgmi_mlp* net, const float* y, const float* snr_db, int64_t n, float* llr, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* ---- learned demapper as a path, with per-SNR fallback -------------------
+ * mdgmi_learned_calibrate attaches a network of the fused shape with
+ * dim + 1 inputs and log2(M) outputs to a format and decides, per noise
+ * variance, which demapper MDGMI_PATH_LEARNED_BF16 uses: on the given
+ * held-out samples y [n_snr][n][dim] (float) with sent rows tx_idx, the
+ * exact GMI on exact_path (an FP32 path or AUTO) and the network's GMI are
+ * computed on the same samples; where the paired loss GMI_exact - GMI_learned
+ * is at most max_loss (and both are finite) that sigma2 is routed to the
+ * network, elsewhere to exact_path. result_host [n_snr][4] receives
+ * GMI_exact, GMI_learned, the loss and the route (1 learned, 0 exact).
+ * The network's SNR feature is 10 log10(E||x||^2 / (dim sigma2)) dB.
+ * Synchronous (waits for `stream`); replaces an earlier calibration of the
+ * format; the network must stay alive while the format uses it.
+ * MDGMI_PATH_LEARNED_BF16 in mdgmi_gmi: SNR points routed to the network
+ * give its GMI and SE (MI fields NaN: bit metrics only); every other point,
+ * including noise variances never calibrated (matched to 1e-12 relative),
+ * gives exactly what mdgmi_gmi on exact_path gives. In mdgmi_llr: the
+ * network's LLRs or the exact ones, by the same rule. Workspaces: from
+ * mdgmi_gmi_workspace_size / mdgmi_llr_workspace_size with this path (after
+ * calibration; MDGMI_E_UNSUPPORTED before). */
+int mdgmi_learned_calibrate_workspace_size(const mdgmi_format* fmt, int32_t exact_path, int64_t n, int32_t n_snr,
+                                           size_t* bytes);
+int mdgmi_learned_calibrate(mdgmi_format* fmt, const mdgmi_mlp* net, int32_t exact_path, double max_loss,
+                            const float* y, const uint32_t* tx_idx, int64_t n, const double* sigma2_host,
+                            int32_t n_snr, double* result_host, void* ws, size_t ws_bytes, void* stream);
+
 /* Checkpoint: widths, step, masters and both Adam moments (binary). */
 int mdgmi_mlp_save(const mdgmi_mlp* net, const char* path);
 int mdgmi_mlp_load(mdgmi_mlp* net, const char* path);

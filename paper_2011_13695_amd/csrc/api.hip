@@ -206,6 +206,14 @@ int run_llr(const mdgmi_format* fmt, const void* y, int64_t n, double sigma2, vo
     return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
 }
 }  // namespace
+
+int gmi_with_workspace(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int64_t n,
+                       const double* sigma2_host, int32_t n_snr, int32_t path, double* out, void* ws, size_t ws_bytes,
+                       void* stream) {
+    if (path == MDGMI_PATH_LEARNED_BF16)
+        return learned_gmi(fmt, (const float*)y, tx_idx, n, sigma2_host, n_snr, out, ws, ws_bytes, stream);
+    return run_gmi(fmt, y, tx_idx, n, sigma2_host, n_snr, path, kModeGmi, out, ws, ws_bytes, stream);
+}
 }  // namespace mdgmi
 
 using namespace mdgmi;
@@ -273,6 +281,7 @@ int mdgmi_format_create(const double* X_host, const uint32_t* labels_host, int32
         }
         n32[slot] = (float)n2;
         f->max_norm2 = std::max(f->max_norm2, n2);
+        f->energy += n2 / M;
     }
     // Rows sharing their coordinates with a lower label: sort rows by
     // (coordinates, label); within a run of equal points all but the first
@@ -319,6 +328,7 @@ int mdgmi_format_destroy(mdgmi_format* f) {
     if (f->d_n32) (void)hipFree(f->d_n32);
     if (f->d_labels) (void)hipFree(f->d_labels);
     if (f->d_labels_hd) (void)hipFree(f->d_labels_hd);
+    learned_free(f);
     delete[] f->h_X64;
     delete f;
     return MDGMI_OK;
@@ -341,6 +351,7 @@ int mdgmi_generate(const mdgmi_format* fmt, uint64_t seed, const double* sigma2_
 int mdgmi_llr_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t path, size_t* bytes) {
     if (!fmt || !bytes) return MDGMI_E_NULL;
     if (n < 1) return MDGMI_E_SHAPE;
+    if (path == MDGMI_PATH_LEARNED_BF16) return learned_llr_workspace_size(fmt, n, bytes);
     int p = path == MDGMI_PATH_AUTO ? (fmt->M >= 32 ? MDGMI_PATH_F32_MFMA_F16SPLIT : MDGMI_PATH_F32_DIRECT) : path;
     if (p == MDGMI_PATH_F64)
         *bytes = 0;
@@ -358,6 +369,7 @@ int mdgmi_llr_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t path, s
 
 int mdgmi_llr(const mdgmi_format* fmt, const void* y, int64_t n, double sigma2, void* llr, int32_t path, void* ws,
               size_t ws_bytes, void* stream) {
+    if (path == MDGMI_PATH_LEARNED_BF16) return learned_llr(fmt, (const float*)y, n, sigma2, (float*)llr, ws, ws_bytes, stream);
     return run_llr(fmt, y, n, sigma2, llr, path, kModeLlr, ws, ws_bytes, stream);
 }
 
@@ -367,12 +379,16 @@ int mdgmi_llr_maxlog(const mdgmi_format* fmt, const void* y, int64_t n, double s
 }
 
 int mdgmi_gmi_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, int32_t path, size_t* bytes) {
+    if (path == MDGMI_PATH_LEARNED_BF16) {
+        if (!fmt || !bytes) return MDGMI_E_NULL;
+        return learned_gmi_workspace_size(fmt, n, n_snr, bytes);
+    }
     return gmi_workspace_size(fmt, n, n_snr, path, kModeGmi, bytes);
 }
 
 int mdgmi_gmi(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int64_t n, const double* sigma2_host,
               int32_t n_snr, int32_t path, double* out, void* ws, size_t ws_bytes, void* stream) {
-    return run_gmi(fmt, y, tx_idx, n, sigma2_host, n_snr, path, kModeGmi, out, ws, ws_bytes, stream);
+    return gmi_with_workspace(fmt, y, tx_idx, n, sigma2_host, n_snr, path, out, ws, ws_bytes, stream);
 }
 
 int mdgmi_gmi_hd_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, int32_t path, size_t* bytes) {

@@ -21,6 +21,9 @@ struct mdgmi_format {
     // coordinates as a point with a lower label (hard-decision launches read
     // this copy: the nearest-point decision goes to the lowest label)
     uint32_t* d_labels_hd = nullptr;
+    double energy = 0.0;          // mean_j ||x_j||^2 (SNR = energy / (dim sigma2))
+    // learned demapper attached by mdgmi_learned_calibrate (mlp.hip)
+    struct LearnedBinding* learned = nullptr;
     double max_abs = 0.0;         // max_j,d |x_jd|
     double max_norm2 = 0.0;       // max_j ||x_j||^2
     double* h_X64 = nullptr;      // host copy, label-ordered [M][dim]
@@ -143,6 +146,23 @@ hipError_t launch_reduce(const double* part, int n_snr, int blocks_per_snr, int6
                          double* out, hipStream_t st, int kind = kReduceGmi);
 
 int device_cu_count();
+
+// MDGMI_PATH_LEARNED_BF16 in mdgmi_gmi / mdgmi_llr and their workspace
+// sizes (mlp.hip): the attached network where calibration routed the SNR
+// point to it, the exact fallback path elsewhere.
+int learned_gmi_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, size_t* bytes);
+int learned_gmi(const mdgmi_format* fmt, const float* y, const uint32_t* tx_idx, int64_t n, const double* sigma2_host,
+                int32_t n_snr, double* out, void* ws, size_t ws_bytes, void* stream);
+int learned_llr_workspace_size(const mdgmi_format* fmt, int64_t n, size_t* bytes);
+int learned_llr(const mdgmi_format* fmt, const float* y, int64_t n, double sigma2, float* llr, void* ws,
+                size_t ws_bytes, void* stream);
+void learned_free(mdgmi_format* fmt);
+
+// mdgmi_gmi on a given workspace (the no-allocation entry point passes its
+// static scratch array here)
+int gmi_with_workspace(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int64_t n,
+                       const double* sigma2_host, int32_t n_snr, int32_t path, double* out, void* ws, size_t ws_bytes,
+                       void* stream);
 
 // autotuner table (autotune.hip); -1 where (dim, M) is untuned
 int tuned_path(int dim, int M);

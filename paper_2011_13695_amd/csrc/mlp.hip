@@ -652,3 +652,306 @@ int mdgmi_mlp_gmi(const mdgmi_mlp* net, const mdgmi_format* fmt, const float* y,
 }
 
 }  // extern "C"
+
+// ------------------------------------------ training step, LLRs, learned path
+namespace mdgmi {
+
+hipError_t launch_mlp_llr_fused(__bf16* const* wf, const float* const* bias, int in_dim, int out_dim, const float* y,
+                                int dim, int64_t n, const float* snr_db, float snr_feat, float* llr, int grid,
+                                hipStream_t st);
+
+namespace {
+
+// x [n][dim + 1] = [y, (snr_db[i] - 9.5) / 4.5] (snr_db per sample), or the
+// scalar feature when snr_db is null.
+__global__ void k_features_snr(const float* __restrict__ y, int64_t n, int dim, const float* __restrict__ snr_db,
+                               float snr_feat, float* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int d = 0; d < dim; d++) x[i * (dim + 1) + d] = y[i * dim + d];
+    // in FP64 like the host-side scalar feature, so both agree exactly
+    x[i * (dim + 1) + dim] = snr_db ? (float)(((double)snr_db[i] - 9.5) / 4.5) : snr_feat;
+}
+
+hipError_t features(const float* y, int64_t n, int dim, const float* snr_db, float snr_feat, float* x,
+                    hipStream_t st) {
+    hipLaunchKernelGGL(k_features_snr, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, y, n, dim, snr_db,
+                       snr_feat, x);
+    return hipGetLastError();
+}
+
+// SNR feature of a noise variance: SNR = E||x||^2 / (dim sigma2) in dB.
+float snr_feature(const mdgmi_format* f, double sigma2) {
+    const double snr_db = 10.0 * std::log10(f->energy / (f->dim * sigma2));
+    return (float)((snr_db - 9.5) / 4.5);
+}
+
+void fused_biases(const mdgmi_mlp* net, const float* (&bias)[4]) {
+    for (int l = 0; l < 4; l++) bias[l] = net->d_params + net->boff[l];
+}
+
+}  // namespace
+}  // namespace mdgmi
+
+// A learned demapper attached to a format, with the per-SNR route found by
+// calibration (noise variances and whether each uses the network).
+struct LearnedBinding {
+    const mdgmi_mlp* net = nullptr;
+    int exact_path = MDGMI_PATH_AUTO;
+    double max_loss = 0.01;
+    std::vector<double> s2;
+    std::vector<uint8_t> route;
+};
+
+namespace mdgmi {
+namespace {
+
+// 1 if sigma2 was calibrated to the network, else 0 (exact fallback).
+int routed(const LearnedBinding* b, double sigma2) {
+    for (size_t k = 0; k < b->s2.size(); k++)
+        if (std::fabs(b->s2[k] - sigma2) <= 1e-12 * sigma2) return b->route[k];
+    return 0;
+}
+
+size_t learned_part_bytes() { return (size_t)al((int64_t)fused_grid() * kNPart * 8); }
+
+int check_net_for(const mdgmi_format* f, const mdgmi_mlp* net) {
+    if (!net->fused) return MDGMI_E_UNSUPPORTED;
+    if (net->sizes[0] != f->dim + 1 || net->sizes[net->L] != f->m) return MDGMI_E_SHAPE;
+    return MDGMI_OK;
+}
+
+// Learned GMI of SNR point q (one fused launch + finish) into out_row.
+hipError_t learned_gmi_one(const mdgmi_format* fmt, const mdgmi_mlp* net, const float* yq, const uint32_t* tq,
+                           int64_t n, double sigma2, double* part, double* out_row, hipStream_t st) {
+    const float* bias[4];
+    fused_biases(net, bias);
+    const int grid = fused_grid();
+    hipError_t e = launch_mlp_gmi_fused(net->d_wf, bias, net->sizes[0], net->sizes[4], yq, fmt->dim, tq,
+                                        fmt->d_labels, fmt->M, n, snr_feature(fmt, sigma2), part, grid, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_learned_finish, dim3(1), dim3(64), 0, st, part, grid, n, fmt->m, out_row);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int learned_gmi_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr, size_t* bytes) {
+    const LearnedBinding* b = fmt->learned;
+    if (!b) return MDGMI_E_UNSUPPORTED;
+    size_t ex = 0;
+    const int rc = mdgmi_gmi_workspace_size(fmt, n, n_snr, b->exact_path, &ex);
+    if (rc != MDGMI_OK) return rc;
+    *bytes = std::max(ex, learned_part_bytes());
+    return MDGMI_OK;
+}
+
+int learned_gmi(const mdgmi_format* fmt, const float* y, const uint32_t* tx_idx, int64_t n, const double* sigma2_host,
+                int32_t n_snr, double* out, void* ws, size_t ws_bytes, void* stream) {
+    if (!fmt || !y || !tx_idx || !sigma2_host || !out) return MDGMI_E_NULL;
+    if (n < 1 || n_snr < 1) return MDGMI_E_SHAPE;
+    const LearnedBinding* b = fmt->learned;
+    if (!b) return MDGMI_E_UNSUPPORTED;
+    double max_s = 0.0;
+    bool any_exact = false;
+    for (int q = 0; q < n_snr; q++) {
+        if (!finite_pos(sigma2_host[q])) return MDGMI_E_SIGMA2;
+        if (!routed(b, sigma2_host[q])) {
+            any_exact = true;
+            max_s = std::max(max_s, s_of(sigma2_host[q]));
+        }
+    }
+    int p = 0;
+    if (any_exact) {
+        const int rc = resolve_path(fmt, b->exact_path, max_s, &p);
+        if (rc != MDGMI_OK) return rc;
+    }
+    size_t need = 0;
+    int rc = learned_gmi_workspace_size(fmt, n, n_snr, &need);
+    if (rc != MDGMI_OK) return rc;
+    if (!ws || ws_bytes < need) return MDGMI_E_WORKSPACE;
+    if ((rc = check_device(fmt)) != MDGMI_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int dim = fmt->dim;
+    // maximal runs of SNR points with the same route, in order
+    for (int q0 = 0; q0 < n_snr;) {
+        const int r = routed(b, sigma2_host[q0]);
+        int q1 = q0 + 1;
+        while (q1 < n_snr && routed(b, sigma2_host[q1]) == r) q1++;
+        if (r) {
+            for (int q = q0; q < q1; q++)
+                if (learned_gmi_one(fmt, b->net, y + (size_t)q * n * dim, tx_idx + (size_t)q * n, n, sigma2_host[q],
+                                    (double*)ws, out + (size_t)q * MDGMI_NFIELDS, st) != hipSuccess)
+                    return MDGMI_E_HIP;
+        } else {
+            rc = gmi_with_workspace(fmt, y + (size_t)q0 * n * dim, tx_idx + (size_t)q0 * n, n, sigma2_host + q0,
+                                    q1 - q0, b->exact_path, out + (size_t)q0 * MDGMI_NFIELDS, ws, ws_bytes, stream);
+            if (rc != MDGMI_OK) return rc;
+        }
+        q0 = q1;
+    }
+    return MDGMI_OK;
+}
+
+int learned_llr_workspace_size(const mdgmi_format* fmt, int64_t n, size_t* bytes) {
+    const LearnedBinding* b = fmt->learned;
+    if (!b) return MDGMI_E_UNSUPPORTED;
+    return mdgmi_llr_workspace_size(fmt, n, b->exact_path, bytes);
+}
+
+int learned_llr(const mdgmi_format* fmt, const float* y, int64_t n, double sigma2, float* llr, void* ws,
+                size_t ws_bytes, void* stream) {
+    if (!fmt || !y || !llr) return MDGMI_E_NULL;
+    if (n < 1) return MDGMI_E_SHAPE;
+    if (!finite_pos(sigma2)) return MDGMI_E_SIGMA2;
+    const LearnedBinding* b = fmt->learned;
+    if (!b) return MDGMI_E_UNSUPPORTED;
+    if (!routed(b, sigma2)) return mdgmi_llr(fmt, y, n, sigma2, llr, b->exact_path, ws, ws_bytes, stream);
+    int rc = check_device(fmt);
+    if (rc != MDGMI_OK) return rc;
+    const float* bias[4];
+    fused_biases(b->net, bias);
+    const hipError_t e = launch_mlp_llr_fused(b->net->d_wf, bias, b->net->sizes[0], b->net->sizes[4], y, fmt->dim, n,
+                                              nullptr, snr_feature(fmt, sigma2), llr, fused_grid(),
+                                              (hipStream_t)stream);
+    return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
+}
+
+void learned_free(mdgmi_format* fmt) {
+    delete fmt->learned;
+    fmt->learned = nullptr;
+}
+
+}  // namespace mdgmi
+
+extern "C" {
+
+int mdgmi_mlp_train_workspace_size(const mdgmi_mlp* net, int64_t n, size_t* bytes) {
+    if (!net || !bytes) return MDGMI_E_NULL;
+    if (n < 1 || n > (int64_t)1 << 30) return MDGMI_E_SHAPE;
+    *bytes = (size_t)(al(n * net->sizes[0] * 4) + mlp_ws(net, n).total);
+    return MDGMI_OK;
+}
+
+int mdgmi_mlp_train_step(mdgmi_mlp* net, const float* y, const float* snr_db, const float* llr_target, int64_t n,
+                         float lr, double* loss, void* ws, size_t ws_bytes, void* stream) {
+    if (!net || !y || !snr_db || !llr_target || !loss || !ws) return MDGMI_E_NULL;
+    if (n < 1 || n > (int64_t)1 << 30) return MDGMI_E_SHAPE;
+    if (!(lr >= 0.0f) || !std::isfinite(lr)) return MDGMI_E_ARG;
+    size_t need = 0;
+    mdgmi_mlp_train_workspace_size(net, n, &need);
+    if (ws_bytes < need) return MDGMI_E_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    float* x = (float*)ws;
+    char* mws = (char*)ws + al(n * net->sizes[0] * 4);
+    if (features(y, n, net->sizes[0] - 1, snr_db, 0.0f, x, st) != hipSuccess) return MDGMI_E_HIP;
+    int rc = mdgmi_mlp_loss_grad(net, x, llr_target, n, loss, mws, (size_t)mlp_ws(net, n).total, stream);
+    if (rc != MDGMI_OK) return rc;
+    return mdgmi_mlp_adam_step(net, lr, 0.9f, 0.999f, 1e-8f, stream);
+}
+
+int mdgmi_mlp_llr_workspace_size(const mdgmi_mlp* net, int64_t n, size_t* bytes) {
+    if (!net || !bytes) return MDGMI_E_NULL;
+    if (n < 1 || n > (int64_t)1 << 30) return MDGMI_E_SHAPE;
+    *bytes = net->fused && g_fused_waves != 0 ? 0 : (size_t)(al(n * net->sizes[0] * 4) + mlp_ws(net, n).total);
+    return MDGMI_OK;
+}
+
+int mdgmi_mlp_llr(const mdgmi_mlp* net, const float* y, const float* snr_db, int64_t n, float* llr, void* ws,
+                  size_t ws_bytes, void* stream) {
+    if (!net || !y || !snr_db || !llr) return MDGMI_E_NULL;
+    if (n < 1 || n > (int64_t)1 << 30) return MDGMI_E_SHAPE;
+    size_t need = 0;
+    mdgmi_mlp_llr_workspace_size(net, n, &need);
+    if (need > 0 && (!ws || ws_bytes < need)) return MDGMI_E_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const int dim = net->sizes[0] - 1, out = net->sizes[net->L];
+    if (need == 0) {
+        const float* bias[4];
+        fused_biases(net, bias);
+        return launch_mlp_llr_fused(net->d_wf, bias, net->sizes[0], out, y, dim, n, snr_db, 0.0f, llr, fused_grid(),
+                                    st) == hipSuccess
+                   ? MDGMI_OK
+                   : MDGMI_E_HIP;
+    }
+    float* x = (float*)ws;
+    char* mws = (char*)ws + al(n * net->sizes[0] * 4);
+    const MlpWs w = mlp_ws(net, n);
+    if (features(y, n, dim, snr_db, 0.0f, x, st) != hipSuccess) return MDGMI_E_HIP;
+    if (forward(net, x, n, mws, w, st) != hipSuccess) return MDGMI_E_HIP;
+    return hipMemcpyAsync(llr, mws + w.logits, sizeof(float) * n * out, hipMemcpyDeviceToDevice, st) == hipSuccess
+               ? MDGMI_OK
+               : MDGMI_E_HIP;
+}
+
+int mdgmi_learned_calibrate_workspace_size(const mdgmi_format* fmt, int32_t exact_path, int64_t n, int32_t n_snr,
+                                           size_t* bytes) {
+    if (!fmt || !bytes) return MDGMI_E_NULL;
+    if (n < 1 || n_snr < 1) return MDGMI_E_SHAPE;
+    size_t ex = 0;
+    const int rc = mdgmi_gmi_workspace_size(fmt, n, n_snr, exact_path, &ex);
+    if (rc != MDGMI_OK) return rc;
+    *bytes = al(2 * (int64_t)n_snr * MDGMI_NFIELDS * 8) + std::max(ex, learned_part_bytes());
+    return MDGMI_OK;
+}
+
+int mdgmi_learned_calibrate(mdgmi_format* fmt, const mdgmi_mlp* net, int32_t exact_path, double max_loss,
+                            const float* y, const uint32_t* tx_idx, int64_t n, const double* sigma2_host,
+                            int32_t n_snr, double* result_host, void* ws, size_t ws_bytes, void* stream) {
+    if (!fmt || !net || !y || !tx_idx || !sigma2_host || !result_host) return MDGMI_E_NULL;
+    if (n < 1 || n_snr < 1) return MDGMI_E_SHAPE;
+    if (!(max_loss >= 0.0) || !std::isfinite(max_loss)) return MDGMI_E_ARG;
+    if (exact_path != MDGMI_PATH_F32_DIRECT && exact_path != MDGMI_PATH_F32_MFMA_F16SPLIT &&
+        exact_path != MDGMI_PATH_F32_MFMA_BF16SPLIT && exact_path != MDGMI_PATH_AUTO)
+        return MDGMI_E_ARG;
+    int rc = check_net_for(fmt, net);
+    if (rc != MDGMI_OK) return rc;
+    double max_s = 0.0;
+    for (int q = 0; q < n_snr; q++) {
+        if (!finite_pos(sigma2_host[q])) return MDGMI_E_SIGMA2;
+        max_s = std::max(max_s, s_of(sigma2_host[q]));
+    }
+    int p = 0;
+    if ((rc = resolve_path(fmt, exact_path, max_s, &p)) != MDGMI_OK) return rc;
+    size_t need = 0;
+    if ((rc = mdgmi_learned_calibrate_workspace_size(fmt, exact_path, n, n_snr, &need)) != MDGMI_OK) return rc;
+    if (!ws || ws_bytes < need) return MDGMI_E_WORKSPACE;
+    if ((rc = check_device(fmt)) != MDGMI_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    double* rows = (double*)ws;  // [2][n_snr][MDGMI_NFIELDS]: exact, learned
+    char* rest = (char*)ws + al(2 * (int64_t)n_snr * MDGMI_NFIELDS * 8);
+    const size_t rest_bytes = ws_bytes - (size_t)al(2 * (int64_t)n_snr * MDGMI_NFIELDS * 8);
+    rc = gmi_with_workspace(fmt, y, tx_idx, n, sigma2_host, n_snr, exact_path, rows, rest, rest_bytes, stream);
+    if (rc != MDGMI_OK) return rc;
+    double* lrows = rows + (size_t)n_snr * MDGMI_NFIELDS;
+    for (int q = 0; q < n_snr; q++)
+        if (learned_gmi_one(fmt, net, y + (size_t)q * n * fmt->dim, tx_idx + (size_t)q * n, n, sigma2_host[q],
+                            (double*)rest, lrows + (size_t)q * MDGMI_NFIELDS, st) != hipSuccess)
+            return MDGMI_E_HIP;
+    std::vector<double> h((size_t)2 * n_snr * MDGMI_NFIELDS);
+    if (hipMemcpyAsync(h.data(), rows, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return MDGMI_E_HIP;
+    LearnedBinding* b = new LearnedBinding();
+    b->net = net;
+    b->exact_path = exact_path;
+    b->max_loss = max_loss;
+    for (int q = 0; q < n_snr; q++) {
+        const double ge = h[(size_t)q * MDGMI_NFIELDS + MDGMI_F_GMI];
+        const double gl = h[((size_t)n_snr + q) * MDGMI_NFIELDS + MDGMI_F_GMI];
+        const double loss = ge - gl;
+        // paired loss on the same samples; a non-finite estimate keeps the exact path
+        const uint8_t r = std::isfinite(ge) && std::isfinite(gl) && loss <= max_loss ? 1 : 0;
+        b->s2.push_back(sigma2_host[q]);
+        b->route.push_back(r);
+        result_host[4 * q + 0] = ge;
+        result_host[4 * q + 1] = gl;
+        result_host[4 * q + 2] = loss;
+        result_host[4 * q + 3] = r;
+    }
+    learned_free(fmt);
+    fmt->learned = b;
+    return MDGMI_OK;
+}
+
+}  // extern "C"

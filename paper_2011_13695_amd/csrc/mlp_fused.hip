@@ -1,4 +1,5 @@
-// Fused inference of the MLP demapper with the GMI cost of its logits.
+// Fused inference of the MLP demapper: its logits (LLRs) or the GMI cost of
+// those logits.
 //
 // Shape served: [in <= 16, 256, 256, 256, out <= 32]. Every layer is computed
 // transposed, H_l^T = W_l H_(l-1)^T, on v_mfma_f32_32x32x16_bf16 with the
@@ -13,8 +14,9 @@
 // LDS: W_1 (8 KiB), W_4 (16 KiB) and all biases stay resident; W_2 and W_3
 // (128 KiB each) are staged in turn into one buffer, once per block of
 // 32 samples per wave (8 waves by default: two per SIMD, so one wave's
-// GELUs overlap the other's MFMAs). The logits are turned into the per-sample GMI cost
-// in the kernel; only FP64 block partials are written.
+// GELUs overlap the other's MFMAs). In GMI mode the logits are turned into
+// the per-sample GMI cost in the kernel and only FP64 block partials are
+// written; in LLR mode the logits are stored, [n][out] FP32.
 #include <algorithm>
 #include <cmath>
 
@@ -126,13 +128,16 @@ __device__ __forceinline__ void hidden_layer(const uint4* __restrict__ Wl, const
     }
 }
 
-template <int kWaves>
-__global__ __launch_bounds__(kWaves * 64) void k_mlp_gmi_fused(
+// LLR: store the logits (llr [n][out_dim]); else the GMI cost into part.
+// The SNR feature of sample i is (snr_db[i] - 9.5) / 4.5 when snr_db is
+// given, else snr_feat.
+template <int kWaves, bool LLR>
+__global__ __launch_bounds__(kWaves * 64) void k_mlp_fused(
     const uint4* __restrict__ w1f, const uint4* __restrict__ w2f, const uint4* __restrict__ w3f,
     const uint4* __restrict__ w4f, const float* __restrict__ b1, const float* __restrict__ b2,
     const float* __restrict__ b3, const float* __restrict__ b4, int in_dim, int out_dim, const float* __restrict__ y,
-    int dim, const uint32_t* __restrict__ tx, const uint32_t* __restrict__ labels, int M, int64_t n, float snr_feat,
-    double* __restrict__ part) {
+    int dim, const uint32_t* __restrict__ tx, const uint32_t* __restrict__ labels, int M, int64_t n,
+    const float* __restrict__ snr_db, float snr_feat, float* __restrict__ llr, double* __restrict__ part) {
     constexpr int kThreads = kWaves * 64;
     extern __shared__ uint4 lds[];
     uint4* sW1 = lds;
@@ -162,6 +167,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp_gmi_fused(
         // ---- layer 1: B operand = features in natural order, lane half h holds 8h..8h+7
         bf16x8 xin;
         {
+            const float feat = snr_db != nullptr && valid ? (float)(((double)snr_db[i] - 9.5) / 4.5) : snr_feat;
             P8 p;
 #pragma unroll
             for (int q = 0; q < 8; q++) {
@@ -171,7 +177,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp_gmi_fused(
                     if (f < dim)
                         v = y[i * dim + f];
                     else if (f == dim)
-                        v = snr_feat;
+                        v = feat;
                 }
                 p.h[q] = (__bf16)v;
             }
@@ -216,6 +222,17 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp_gmi_fused(
             a.u = sW4[kb * 64 + lane];
             zo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, actA[kb >> 1][kb & 1], zo, 0, 0, 0);
         }
+        if constexpr (LLR) {
+            // register r of lane half h is logit row 8 (r >> 2) + 4 h + (r & 3)
+            if (valid) {
+#pragma unroll
+                for (int r = 0; r < 16; r++) {
+                    const int row = 8 * (r >> 2) + 4 * h + (r & 3);
+                    if (row < out_dim) llr[i * out_dim + row] = zo[r];
+                }
+            }
+            continue;
+        }
         // ---- per-sample GMI cost of the logits (bits), both lane halves.
         // Rows >= out_dim have zero weights and bias, so their logit is
         // exactly 0 and their cost exactly softplus2(0); every row is costed
@@ -236,7 +253,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp_gmi_fused(
         c -= (double)(32 - out_dim) * pad_cost;
         if (h == 0 && valid) acc.add(row_ok ? c : NAN, 0.0);
     }
-    block_reduce_store(acc, part + (size_t)blockIdx.x * kNPart);
+    if constexpr (!LLR) block_reduce_store(acc, part + (size_t)blockIdx.x * kNPart);
 }
 
 constexpr size_t kLdsBytes = (size_t)(kW1U + kW4U) * 16 + (size_t)kBiasF * 4 + (size_t)kWHU * 16;
@@ -266,21 +283,21 @@ int fused_grid() { return device_cu_count(); }
 
 int g_fused_waves = 8;  // 8: two waves per SIMD (256 VGPRs, output tiles in pairs); 4: one, whole register file
 
-template <int W>
+template <int W, bool LLR>
 hipError_t launch_fused_w(__bf16* const* wf, const float* const* bias, int in_dim, int out_dim, const float* y, int dim,
-                          const uint32_t* tx, const uint32_t* labels, int M, int64_t n, float snr_feat, double* part,
-                          int grid, hipStream_t st) {
+                          const uint32_t* tx, const uint32_t* labels, int M, int64_t n, const float* snr_db,
+                          float snr_feat, float* llr, double* part, int grid, hipStream_t st) {
     using namespace fused;
     static bool attr = false;
     if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_mlp_gmi_fused<W>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)kLdsBytes);
+        hipError_t e = hipFuncSetAttribute((const void*)k_mlp_fused<W, LLR>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
         if (e != hipSuccess) return e;
         attr = true;
     }
-    hipLaunchKernelGGL((k_mlp_gmi_fused<W>), dim3(grid), dim3(W * 64), kLdsBytes, st, (const uint4*)wf[0],
+    hipLaunchKernelGGL((k_mlp_fused<W, LLR>), dim3(grid), dim3(W * 64), kLdsBytes, st, (const uint4*)wf[0],
                        (const uint4*)wf[1], (const uint4*)wf[2], (const uint4*)wf[3], bias[0], bias[1], bias[2],
-                       bias[3], in_dim, out_dim, y, dim, tx, labels, M, n, snr_feat, part);
+                       bias[3], in_dim, out_dim, y, dim, tx, labels, M, n, snr_db, snr_feat, llr, part);
     return hipGetLastError();
 }
 
@@ -288,8 +305,20 @@ hipError_t launch_mlp_gmi_fused(__bf16* const* wf, const float* const* bias, int
                                 int dim, const uint32_t* tx, const uint32_t* labels, int M, int64_t n, float snr_feat,
                                 double* part, int grid, hipStream_t st) {
     if (g_fused_waves == 8)
-        return launch_fused_w<8>(wf, bias, in_dim, out_dim, y, dim, tx, labels, M, n, snr_feat, part, grid, st);
-    return launch_fused_w<4>(wf, bias, in_dim, out_dim, y, dim, tx, labels, M, n, snr_feat, part, grid, st);
+        return launch_fused_w<8, false>(wf, bias, in_dim, out_dim, y, dim, tx, labels, M, n, nullptr, snr_feat,
+                                        nullptr, part, grid, st);
+    return launch_fused_w<4, false>(wf, bias, in_dim, out_dim, y, dim, tx, labels, M, n, nullptr, snr_feat, nullptr,
+                                    part, grid, st);
+}
+
+hipError_t launch_mlp_llr_fused(__bf16* const* wf, const float* const* bias, int in_dim, int out_dim, const float* y,
+                                int dim, int64_t n, const float* snr_db, float snr_feat, float* llr, int grid,
+                                hipStream_t st) {
+    if (g_fused_waves == 4)
+        return launch_fused_w<4, true>(wf, bias, in_dim, out_dim, y, dim, nullptr, nullptr, 0, n, snr_db, snr_feat,
+                                       llr, nullptr, grid, st);
+    return launch_fused_w<8, true>(wf, bias, in_dim, out_dim, y, dim, nullptr, nullptr, 0, n, snr_db, snr_feat, llr,
+                                   nullptr, grid, st);
 }
 
 }  // namespace mdgmi

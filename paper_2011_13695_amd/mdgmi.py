@@ -31,10 +31,11 @@ MDGMI_PATH_F64 = 0
 MDGMI_PATH_F32_DIRECT = 1
 MDGMI_PATH_F32_MFMA_F16SPLIT = 2
 MDGMI_PATH_F32_MFMA_BF16SPLIT = 3
+MDGMI_PATH_LEARNED_BF16 = 4
 MDGMI_PATH_AUTO = 5
 PATHS = {"f64": MDGMI_PATH_F64, "direct": MDGMI_PATH_F32_DIRECT,
          "mfma": MDGMI_PATH_F32_MFMA_F16SPLIT, "mfma_bf16": MDGMI_PATH_F32_MFMA_BF16SPLIT,
-         "auto": MDGMI_PATH_AUTO}
+         "learned": MDGMI_PATH_LEARNED_BF16, "auto": MDGMI_PATH_AUTO}
 
 MDGMI_NFIELDS = 6
 FIELDS = ("gmi", "mi", "se_gmi", "se_mi", "n", "n_nonfinite")
@@ -594,6 +595,14 @@ def _mlp_sigs():
     L.mdgmi_mlp_adam_step.argtypes = [_P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]
     L.mdgmi_mlp_save.argtypes = [_P, ctypes.c_char_p]
     L.mdgmi_mlp_load.argtypes = [_P, ctypes.c_char_p]
+    L.mdgmi_mlp_train_workspace_size.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
+    L.mdgmi_mlp_train_step.argtypes = [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_float, _P, _P, ctypes.c_size_t, _P]
+    L.mdgmi_mlp_llr_workspace_size.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
+    L.mdgmi_mlp_llr.argtypes = [_P, _P, _P, ctypes.c_int64, _P, _P, ctypes.c_size_t, _P]
+    L.mdgmi_learned_calibrate_workspace_size.argtypes = [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                                         ctypes.POINTER(ctypes.c_size_t)]
+    L.mdgmi_learned_calibrate.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P, ctypes.c_int64, _P,
+                                          ctypes.c_int32, _P, _P, ctypes.c_size_t, _P]
     L._mlp_sigs = True
     return L
 
@@ -676,6 +685,40 @@ class MLP:
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         _check("mdgmi_mlp_adam_step", lib().mdgmi_mlp_adam_step(self.handle, lr, beta1, beta2, eps, _stream(stream)))
 
+    def train_step(self, y, snr_db, target_llr, lr, loss=None, ws=None, stream=None):
+        """mdgmi_mlp_train_step: features from y [n, dim] and per-sample SNRs
+        snr_db [n] (dB), BCE forward/backward and one Adam step."""
+        import torch
+        L = _mlp_sigs()
+        n = y.shape[0]
+        assert y.is_contiguous() and snr_db.is_contiguous() and target_llr.is_contiguous()
+        assert y.dtype == snr_db.dtype == target_llr.dtype == torch.float32 and snr_db.numel() == n
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float64, device="cuda")
+        if ws is None:
+            b = ctypes.c_size_t()
+            _check("mdgmi_mlp_train_workspace_size", L.mdgmi_mlp_train_workspace_size(self.handle, n, ctypes.byref(b)))
+            ws = workspace(b.value)
+        _check("mdgmi_mlp_train_step", L.mdgmi_mlp_train_step(self.handle, _dptr(y), _dptr(snr_db), _dptr(target_llr),
+                                                              n, float(lr), _dptr(loss), _dptr(ws), ws.numel(),
+                                                              _stream(stream)))
+        return loss
+
+    def llr(self, y, snr_db, out=None, stream=None):
+        """mdgmi_mlp_llr: logits [n, out] of y [n, dim] at per-sample SNRs snr_db [n] (dB)."""
+        import torch
+        L = _mlp_sigs()
+        n = y.shape[0]
+        assert y.is_contiguous() and snr_db.is_contiguous() and snr_db.numel() == n
+        if out is None:
+            out = torch.empty((n, self.sizes[-1]), dtype=torch.float32, device="cuda")
+        b = ctypes.c_size_t()
+        _check("mdgmi_mlp_llr_workspace_size", L.mdgmi_mlp_llr_workspace_size(self.handle, n, ctypes.byref(b)))
+        ws = workspace(b.value) if b.value else None
+        _check("mdgmi_mlp_llr", L.mdgmi_mlp_llr(self.handle, _dptr(y), _dptr(snr_db), n, _dptr(out),
+                                                _dptr(ws) if ws is not None else None, b.value, _stream(stream)))
+        return out
+
     def save(self, path):
         _check("mdgmi_mlp_save", lib().mdgmi_mlp_save(self.handle, str(path).encode()))
 
@@ -726,6 +769,29 @@ def mdgmi_mlp_gmi(net: "MLP", fmt: Format, y, tx_idx, snr_db, chunk: int = 1 << 
     _check("mdgmi_mlp_gmi", L.mdgmi_mlp_gmi(net.handle, fmt.handle, _dptr(y), _dptr(tx_idx), n, snr.ctypes.data_as(_P),
                                             n_snr, chunk, _dptr(out), _dptr(ws), ws.numel(), _stream(stream)))
     return out
+
+
+def mdgmi_learned_calibrate(fmt: Format, net: "MLP", y, tx_idx, sigma2, exact_path="auto", max_loss=0.01,
+                            stream=None):
+    """Attach net to fmt and route each sigma2 (paired GMI loss on these
+    held-out samples <= max_loss -> the network). Returns [n_snr, 4]:
+    GMI_exact, GMI_learned, loss, route (1 learned)."""
+    L = _mlp_sigs()
+    s2 = np.ascontiguousarray(np.atleast_1d(sigma2), dtype=np.float64)
+    n_snr = s2.size
+    n = y.numel() // (fmt.dim * n_snr)
+    p = _path(exact_path)
+    b = ctypes.c_size_t()
+    _check("mdgmi_learned_calibrate_workspace_size",
+           L.mdgmi_learned_calibrate_workspace_size(fmt.handle, p, n, n_snr, ctypes.byref(b)))
+    ws = workspace(b.value)
+    res = np.empty((n_snr, 4), dtype=np.float64)
+    _check("mdgmi_learned_calibrate", L.mdgmi_learned_calibrate(fmt.handle, net.handle, p, float(max_loss), _dptr(y),
+                                                                _dptr(tx_idx), n, s2.ctypes.data_as(_P), n_snr,
+                                                                res.ctypes.data_as(_P), _dptr(ws), ws.numel(),
+                                                                _stream(stream)))
+    fmt._learned_net = net   # keep the network alive while the format uses it
+    return res
 
 
 def mdgmi_mlp_set_fused(waves: int) -> None:
