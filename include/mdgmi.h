@@ -300,6 +300,28 @@ int mdgmi_stream_destroy(mdgmi_stream* s);
  * GPU needed; +inf for ber = 0, -inf for ber = 0.5, NaN outside [0, 0.5]. */
 double mdgmi_q_factor_db(double ber);
 
+/* ---- no device allocation -------------------------------------------------
+ * For callers that cannot allocate device memory (code being captured into
+ * a HIP graph, tight serving loops, hosts that forbid hipMalloc):
+ * mdgmi_gmi_static computes exactly what mdgmi_gmi computes (same arguments,
+ * paths, launches and results, bit for bit), with its scratch memory (the
+ * per-block FP64 partials and the per-SNR operand images) taken from a
+ * static device array of MDGMI_STATIC_SCRATCH_BYTES that the library holds
+ * on every device it runs on until the process ends. It calls no allocator.
+ *  - MDGMI_E_WORKSPACE if the call needs more scratch than the array holds,
+ *    i.e. mdgmi_gmi_workspace_size(fmt, n, n_snr, path) exceeds
+ *    MDGMI_STATIC_SCRATCH_BYTES (16 MiB covers 32 SNR points per launch of
+ *    any format on every path; very many SNR points in one call may not
+ *    fit); nothing is launched then.
+ *  - Every call on one device uses the same array, which keeps the last
+ *    call's contents: calls that overlap on a device (other streams or host
+ *    threads) race and must be ordered by the caller. No part of the array
+ *    needs to start at zero: every launch writes what it later reads.
+ *  - The first call on a device looks up the array's device address. */
+#define MDGMI_STATIC_SCRATCH_BYTES (16u << 20)
+int mdgmi_gmi_static(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int64_t n,
+                     const double* sigma2_host, int32_t n_snr, int32_t path, double* out, void* stream);
+
 /* ---- ragged batches ------------------------------------------------------
  * Many (format, SNR, sample count) instances evaluated by one persistent
  * kernel: the samples of every instance are cut into items of about 2^22

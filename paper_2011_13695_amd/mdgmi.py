@@ -76,6 +76,7 @@ def lib():
         L.mdgmi_gmi.argtypes = [_P, _P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int32, _P, _P,
                                 ctypes.c_size_t, _P]
         L.mdgmi_gmi_hd_workspace_size.argtypes = L.mdgmi_gmi_workspace_size.argtypes
+        L.mdgmi_gmi_static.argtypes = [_P, _P, _P, ctypes.c_int64, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]
         L.mdgmi_gmi_hd.argtypes = L.mdgmi_gmi.argtypes
         L.mdgmi_llr_maxlog.argtypes = L.mdgmi_llr.argtypes
         L.mdgmi_gmi_maxlog.argtypes = L.mdgmi_gmi.argtypes
@@ -240,6 +241,27 @@ def mdgmi_gmi(fmt: Format, y, tx_idx, sigma2, path="auto", out=None, ws=None, st
         ws = workspace(mdgmi_gmi_workspace_size(fmt, n, n_snr, p))
     _check("mdgmi_gmi", lib().mdgmi_gmi(fmt.handle, _dptr(y), _dptr(tx_idx), n, s2.ctypes.data_as(_P), n_snr, p,
                                         _dptr(out), _dptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+MDGMI_STATIC_SCRATCH_BYTES = 16 << 20
+
+
+def mdgmi_gmi_static(fmt: Format, y, tx_idx, sigma2, path="auto", out=None, stream=None):
+    """mdgmi_gmi with the library's static scratch array instead of a
+    workspace (no allocation inside the call; `out` may be preallocated)."""
+    import torch
+    s2 = np.ascontiguousarray(np.atleast_1d(sigma2), dtype=np.float64)
+    n_snr = s2.size
+    assert y.is_cuda and y.is_contiguous() and tx_idx.is_contiguous()
+    n = y.numel() // (fmt.dim * n_snr)
+    assert y.numel() == n_snr * n * fmt.dim and tx_idx.numel() == n_snr * n
+    p = _path(path)
+    _check_y(y, p, tx_idx)
+    if out is None:
+        out = torch.empty((n_snr, MDGMI_NFIELDS), dtype=torch.float64, device=y.device)
+    _check("mdgmi_gmi_static", lib().mdgmi_gmi_static(fmt.handle, _dptr(y), _dptr(tx_idx), n,
+                                                      s2.ctypes.data_as(_P), n_snr, p, _dptr(out), _stream(stream)))
     return out
 
 
