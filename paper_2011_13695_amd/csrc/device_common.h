@@ -235,35 +235,69 @@ __device__ inline void block_reduce_store_hd(CostAcc a, HdAcc h, double* dst) {
     block_reduce_vals<kNPartHd>(v, dst);
 }
 
+// Distance terms relative to a reference point, from the factored difference
+//   ||y - x_j||^2 - ||y - x_r||^2 = (x_r - x_j) . (2y - x_r - x_j),
+// whose error is relative to the difference itself: a difference of two
+// squared distances of size ||y||^2 loses everything once ||y|| is large
+// (|y| ~ 5e4: ||y||^2 ~ 1e10, FP32 spacing ~ 1e3), the factored form keeps
+// about 1e-7 of each term. y2 = 2y.
+template <int DIM>
+__device__ inline float rel_dist(const float* y2, const float* __restrict__ xr, const float* __restrict__ xj) {
+#pragma clang fp contract(off)
+    float d = 0.0f;
+#pragma unroll
+    for (int q = 0; q < DIM; q++) d = fmaf(xr[q] - xj[q], (y2[q] - xr[q]) - xj[q], d);
+    return d;
+}
+
+// Label slot of the point nearest to y (FP32; ties and near-ties within
+// rounding go to either point).
+template <int DIM>
+__device__ inline int nearest_slot(const float* y2, const float* __restrict__ X32, int M) {
+    int r = 0;
+    float best = 0.0f;  // relative to slot 0
+#pragma unroll 2
+    for (int j = 1; j < M; j++) {
+        const float d = rel_dist<DIM>(y2, X32, X32 + j * DIM);
+        if (d < best) {
+            best = d;
+            r = j;
+        }
+    }
+    return r;
+}
+
 // Exact per-class evaluation of one sample in FP32, used when a class sum
 // taken relative to the common offset could have lost terms to underflow
 // (a class more than about 2*kBias log2-units away from y) or when the sent
 // point itself is that far. Each class gets its own reference: its nearest
-// point. t_j = s * ||y - x_j||^2 in log2 units, computed directly.
+// point. t_j = s (||y - x_j||^2 - ||y - x_r||^2) in log2 units relative to
+// the point r nearest to y, from the factored difference (rel_dist), so an
+// LLR (the difference of two class minima, one of them t_r = 0) keeps FP32
+// relative accuracy at any distance of y. Every output is relative to t_r;
+// callers use differences only.
 // Outputs: lsb[k] = log2 sum_{j in class(k,b)} 2^-t_j  (k < m, b = 0, 1),
-//          ltot = log2 sum_j 2^-t_j,  ti = t of slot `sent` (if sent >= 0).
+//          ltot = log2 sum_j 2^-t_j,  ti = t of slot `sent` (if sent >= 0),
+//          tmin = min_j t_j.
 // t_j must stay a rounded product: contracted into fma(-s, d, cmin),
 // cmin - t_j of the nearest point would be the product's rounding error
-// instead of 0, thousands of log2 units once t reaches 2^30. Contraction is
-// therefore off in these per-class paths.
+// instead of 0. Contraction is therefore off in these per-class paths.
 template <int DIM>
 __device__ inline void exact_classes_f32(const float* yv, const float* __restrict__ X32, int M, int m,
                                          float s, int sent, float* ls0, float* ls1, float& ltot, float& ti,
                                          float* tmin_out = nullptr) {
 #pragma clang fp contract(off)
+    float y2[DIM];
+#pragma unroll
+    for (int q = 0; q < DIM; q++) y2[q] = 2.0f * yv[q];
+    const float* xr = X32 + nearest_slot<DIM>(y2, X32, M) * DIM;
     float cmin0[MDGMI_MAX_BITS], cmin1[MDGMI_MAX_BITS];
     float tmin = INFINITY;
 #pragma unroll
     for (int k = 0; k < MDGMI_MAX_BITS; k++) cmin0[k] = cmin1[k] = INFINITY;
 #pragma unroll 2
     for (int j = 0; j < M; j++) {
-        float d = 0.0f;
-#pragma unroll
-        for (int q = 0; q < DIM; q++) {
-            float e = yv[q] - X32[j * DIM + q];
-            d = fmaf(e, e, d);
-        }
-        const float t = s * d;
+        const float t = s * rel_dist<DIM>(y2, xr, X32 + j * DIM);
         tmin = fminf(tmin, t);
 #pragma unroll
         for (int k = 0; k < MDGMI_MAX_BITS; k++) {
@@ -282,13 +316,7 @@ __device__ inline void exact_classes_f32(const float* yv, const float* __restric
     for (int k = 0; k < MDGMI_MAX_BITS; k++) S0[k] = S1[k] = 0.0f;
 #pragma unroll 2
     for (int j = 0; j < M; j++) {
-        float d = 0.0f;
-#pragma unroll
-        for (int q = 0; q < DIM; q++) {
-            float e = yv[q] - X32[j * DIM + q];
-            d = fmaf(e, e, d);
-        }
-        const float t = s * d;
+        const float t = s * rel_dist<DIM>(y2, xr, X32 + j * DIM);
         tot += ex2(tmin - t);
 #pragma unroll
         for (int k = 0; k < MDGMI_MAX_BITS; k++) {
@@ -313,23 +341,22 @@ __device__ inline void exact_classes_f32(const float* yv, const float* __restric
 
 // Max-log fallback in FP32 for one sample: per bit, the log2 metric of the
 // nearest point of each class, u0[k] = -min_{j: bit k = 0} t_j and
-// u1[k] = -min_{j: bit k = 1} t_j with t_j = s ||y - x_j||^2 from the
-// differences (exact at any distance; X32 in label order).
+// u1[k] = -min_{j: bit k = 1} t_j, with t_j relative to the point nearest
+// to y from the factored difference (accurate at any distance; X32 in label
+// order). Callers use differences only.
 template <int DIM>
 __device__ inline void class_max_u_f32(const float* yv, const float* __restrict__ X32, int M, int m, float s,
                                        float* u0, float* u1) {
 #pragma clang fp contract(off)
+    float y2[DIM];
+#pragma unroll
+    for (int q = 0; q < DIM; q++) y2[q] = 2.0f * yv[q];
+    const float* xr = X32 + nearest_slot<DIM>(y2, X32, M) * DIM;
 #pragma unroll
     for (int k = 0; k < MDGMI_MAX_BITS; k++) u0[k] = u1[k] = -INFINITY;
 #pragma unroll 2
     for (int j = 0; j < M; j++) {
-        float d = 0.0f;
-#pragma unroll
-        for (int q = 0; q < DIM; q++) {
-            const float e = yv[q] - X32[j * DIM + q];
-            d = fmaf(e, e, d);
-        }
-        const float u = -(s * d);
+        const float u = -(s * rel_dist<DIM>(y2, xr, X32 + j * DIM));
 #pragma unroll
         for (int k = 0; k < MDGMI_MAX_BITS; k++) {
             if (k < m) {

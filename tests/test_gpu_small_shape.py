@@ -181,22 +181,26 @@ def test_small_shape_edge_samples(orc, shape, dim, M):
     # per-sample costs of the far samples are large: compare relative to size
     assert abs(out[0, 0] - r[0]) <= 1e-4 * max(1.0, abs(r[0]))
     assert abs(out[0, 1] - r[1]) <= 1e-4 * max(1.0, abs(r[1]))
-    # |y| beyond the fp16 range of the split: such samples take the same
-    # FP32 per-class arithmetic as the vector-ALU path (whose accuracy at
-    # these magnitudes is that of FP32 distances), bit for bit
+    # |y| beyond the fp16 range of the split (and ||y||^2 far beyond FP32's
+    # resolution of a difference of squared distances): the per-class path
+    # forms distance differences in factored form, so the LLRs of every
+    # FP32 path meet the bar against the oracle, and so do GMI and MI
     yh = y.copy()
     yh[12] = 5.0e4
     yh[13, 0] = -3.0e5
-    a = mdgmi.mdgmi_llr(gf, dev(yh), s2, path="mfma").cpu().numpy()
-    b = mdgmi.mdgmi_llr(gf, dev(yh), s2, path="direct").cpu().numpy()
-    np.testing.assert_array_equal(a[12:14], b[12:14])
-    # FP32 distances this large can round two classes' nearest points to the
-    # same value (LLR 0); otherwise the sign is the oracle's
-    ro = np.sign(orc.llr(yh[12:14], f.X, f.labels, s2))
-    assert np.all(np.isfinite(a)) and np.all((a[12:14] == 0) | (np.sign(a[12:14]) == ro))
-    ga = mdgmi.mdgmi_gmi(gf, dev(yh[None]), dev_u32(tx[None]), [s2], path="mfma").cpu().numpy()
-    gb = mdgmi.mdgmi_gmi(gf, dev(yh[None]), dev_u32(tx[None]), [s2], path="direct").cpu().numpy()
-    assert ga[0, 5] == 0 and abs(ga[0, 0] - gb[0, 0]) <= 1e-6 * abs(gb[0, 0])
+    yh[14] = [(-1.0) ** q * 7.0e3 * (q + 1) for q in range(dim)]
+    ro = orc.llr(yh, f.X, f.labels, s2)
+    rg = orc.gmi(yh, tx, f.X, f.labels, s2)
+    for path in ("mfma", "direct", "mfma_bf16"):
+        a = mdgmi.mdgmi_llr(gf, dev(yh), s2, path=path).cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(a)), path
+        assert ratio(a, ro) <= 1.0, (path, ratio(a, ro))
+        ga = mdgmi.mdgmi_gmi(gf, dev(yh[None]), dev_u32(tx[None]), [s2], path=path).cpu().numpy()
+        assert ga[0, 5] == 0
+        assert abs(ga[0, 0] - rg[0]) <= 1e-4 * max(1.0, abs(rg[0])), (path, ga[0, 0], rg[0])
+        assert abs(ga[0, 1] - rg[1]) <= 1e-4 * max(1.0, abs(rg[1])), (path, ga[0, 1], rg[1])
+        lml = mdgmi.mdgmi_llr_maxlog(gf, dev(yh), s2, path=path).cpu().numpy().astype(np.float64)
+        assert ratio(lml, orc.llr_maxlog(yh, f.X, f.labels, s2)) <= 1.0, path
     # a NaN sample and a sent row out of range are counted as non-finite
     good = np.ones(n, bool)
     yb = y.copy()
