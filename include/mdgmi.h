@@ -26,8 +26,12 @@
  *    Launches are asynchronous on that stream; nothing synchronises it.
  *  - Every argument is checked on the host before anything is launched; a
  *    failed check returns a negative mdgmi_status and launches nothing.
- *  - No call allocates device memory except mdgmi_format_create and the
- *    MLP create/load calls. Scratch memory comes from the caller's workspace.
+ *  - Device memory is allocated only by mdgmi_format_create,
+ *    mdgmi_batch_create, mdgmi_stream_create, mdgmi_mlp_create and
+ *    mdgmi_autotune (its synthetic samples, freed before it returns);
+ *    mdgmi_batch_run instantiates a HIP graph on its first replay for an
+ *    output buffer. Every other call takes its scratch memory from the
+ *    caller's workspace (mdgmi_gmi_static: from a static device array).
  *  - Calls on distinct (stream, workspace, output) triples may overlap;
  *    calls sharing a workspace must be ordered by the caller.
  */
