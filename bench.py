@@ -76,6 +76,10 @@ def parse():
     ap.add_argument("--learned-samples", type=float, default=2e8,
                     help="training samples of the learned demapper (0 skips the learned leg)")
     ap.add_argument("--learned-eval", type=float, default=1e8, help="held-out samples over the 16 SNR points")
+    ap.add_argument("--learned-structured-samples", type=float, default=5e7,
+                    help="training samples of the network on the structured 8-D M=4096 format (0 skips)")
+    ap.add_argument("--learned-infer-only", action="store_true",
+                    help="time the fused inference kernel on a random-initialised network and skip training")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged-batch leg")
     ap.add_argument("--no-llr", action="store_true", help="skip timing the LLR-output mode")
     ap.add_argument("--no-hd", action="store_true", help="skip the hard-decision (BER/SER/Q) leg")
@@ -199,15 +203,83 @@ def copy_probe(nbytes: float):
     print(json.dumps({"copy_probe_bytes": n * 4, "launches": 3}))
 
 
-def learned_leg(gf, wl, args, log):
-    """Learned demapper on the same format: train on exact-LLR targets, then
-    time learned vs exact GMI on the same held-out samples and route each SNR
-    point (learned where the paired GMI loss is at most 0.01 bit)."""
+MLP_FLOPS_PER_SAMPLE = 2 * (9 * 256 + 256 * 256 + 256 * 256 + 256 * 11)   # 9 -> 256 -> 256 -> 256 -> 11
+GELUS_PER_SAMPLE = 3 * 256
+BF16_PEAK = 2.5e15
+
+
+def timed_ms(fn, reps=3):
+    """Mean device time of fn() over reps calls, HIP events on the current stream."""
+    import torch
+    stream = torch.cuda.current_stream()
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def learned_roofline(samples, ms):
+    """The fused inference kernel against the bf16 matrix-core peak
+    (algorithmic flops of the 9-256-256-256-11 network) and its GELU rate."""
+    flops = samples * MLP_FLOPS_PER_SAMPLE / (ms * 1e-3)
+    return {"bound": "mfma", "achieved": flops / 1e12, "peak": BF16_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": flops / BF16_PEAK, "gelu_per_s": samples * GELUS_PER_SAMPLE / (ms * 1e-3),
+            "kernel": "k_mlp_fused (bf16 MFMA, GELU on the vector ALU)", "kernel_ms": ms}
+
+
+def learned_route_leg(gf, fmt_name, snr, n_eval, net, log, train=None):
+    """Held-out evaluation of a trained network on one format: the library's
+    calibration (paired GMI loss per SNR point, route learned where <= 0.01
+    bit), then learned-only, exact and routed (MDGMI_PATH_LEARNED_BF16) GMI
+    timed on the same samples."""
     import numpy as np
     import torch
 
     from paper_2011_13695_amd import learned, mdgmi
-    cfg = learned.TrainConfig(steps=max(1, int(args.learned_samples) // 16384), log_every=250)
+    n_snr = snr.size
+    ev, y, tx = learned.evaluate(net, gf, snr, n_eval, sopt=True)
+    s2 = learned.sigma2_of(snr, gf.dim)
+    out = torch.empty((n_snr, mdgmi.MDGMI_NFIELDS), dtype=torch.float64, device="cuda")
+    lws = mdgmi.workspace(mdgmi.mdgmi_mlp_gmi_workspace_size(net, min(1 << 20, n_eval)))
+    ews = mdgmi.workspace(mdgmi.mdgmi_gmi_workspace_size(gf, n_eval, n_snr, "mfma"))
+    rws = mdgmi.workspace(mdgmi.mdgmi_gmi_workspace_size(gf, n_eval, n_snr, "learned"))
+    t_learned = timed_ms(lambda: mdgmi.mdgmi_mlp_gmi(net, gf, y, tx, snr, out=out, ws=lws))
+    t_exact = timed_ms(lambda: mdgmi.mdgmi_gmi(gf, y, tx, s2, path="mfma", out=out, ws=ews))
+    t_mixed = timed_ms(lambda: mdgmi.mdgmi_gmi(gf, y, tx, s2, path="learned", out=out, ws=rws))
+    routed = out.cpu().numpy()
+    pts = n_snr * n_eval * gf.M
+    n_learned = sum(r == "learned" for r in ev.route)
+    log(f"{fmt_name}: learned {t_learned:.1f} ms, exact {t_exact:.1f} ms, routed {t_mixed:.1f} ms, "
+        f"{n_learned}/{n_snr} SNR points learned, max loss {max(ev.loss):.4f}")
+    row = dict(train or {})
+    row.update({
+        "format": fmt_name, "eval_samples_per_snr": n_eval,
+        "learned_value": pts / (t_learned * 1e-3), "learned_ms": t_learned,
+        "exact_value_same_samples": pts / (t_exact * 1e-3), "exact_ms": t_exact,
+        "speedup_learned_vs_exact": t_exact / t_learned,
+        "mixed_value": pts / (t_mixed * 1e-3), "mixed_ms": t_mixed, "speedup_mixed_vs_exact": t_exact / t_mixed,
+        "snr_db": [float(v) for v in snr],
+        "gmi_exact": [float(v) for v in ev.gmi_exact], "gmi_learned": [float(v) for v in ev.gmi_learned],
+        "gmi_loss": [float(v) for v in ev.loss], "route": ev.route,
+        "gmi_routed": [float(v) for v in routed[:, 0]],
+        "s_opt_learned": [float(v) for v in ev.s_opt],
+        "gmi_loss_sopt": [float(a - b) for a, b in zip(ev.gmi_exact, ev.gmi_learned_sopt)],
+        "n_learned_snr": int(n_learned), "max_loss_bound": 0.01,
+        "roofline": learned_roofline(n_snr * n_eval, t_learned),
+    })
+    return row
+
+
+def train_net(gf, samples, log, **kw):
+    import torch
+    from paper_2011_13695_amd import learned
+    cfg = learned.TrainConfig(log_every=2000, **kw)
+    cfg.steps = max(1, int(samples) // cfg.batch)
     tr = learned.Trainer(gf, cfg)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -215,49 +287,63 @@ def learned_leg(gf, wl, args, log):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     log(f"trained {res.samples} samples in {train_s:.1f} s")
+    return tr.net, {"train_samples": res.samples, "train_seconds": train_s, "train_steps": res.steps,
+                    "batch": cfg.batch, "lr": cfg.lr,
+                    "train_flops_per_s": 3 * MLP_FLOPS_PER_SAMPLE * res.samples / train_s,
+                    "final_train_loss_nats": res.losses[-1][1] if res.losses else None}
+
+
+def learned_leg(gf, wl, args, log):
+    """Learned demapper on the timed format: train on exact-LLR targets, then
+    learned vs exact vs routed GMI on the same held-out samples."""
+    import numpy as np
+    net, tr = train_net(gf, args.learned_samples, log)
     snr = np.asarray(wl.snr_db, dtype=np.float64)
-    n_snr = snr.size
-    n_eval = max(1024, int(args.learned_eval) // n_snr)
-    ev, y, tx = learned.evaluate(tr.net, gf, snr, n_eval, sopt=True)
-    s2 = learned.sigma2_of(snr, gf.dim)
-    stream = torch.cuda.current_stream()
-    out = torch.empty((n_snr, mdgmi.MDGMI_NFIELDS), dtype=torch.float64, device="cuda")
+    n_eval = max(1024, int(args.learned_eval) // snr.size)
+    row = learned_route_leg(gf, wl.fmt.name, snr, n_eval, net, log, tr)
+    row["note"] = ("learned value counts n*M sample*points per sample demapped by the network; routed = "
+                   "MDGMI_PATH_LEARNED_BF16 (per-SNR route decided by mdgmi_learned_calibrate: learned where the "
+                   "paired GMI loss <= 0.01 bit, else exact)")
+    return row
 
-    def timed(fn, reps=3):
-        fn()
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        for _ in range(reps):
-            fn()
-        b.record(stream)
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / reps
 
-    lws = mdgmi.workspace(mdgmi.mdgmi_mlp_gmi_workspace_size(tr.net, min(1 << 20, n_eval)))
-    ews = mdgmi.workspace(mdgmi.mdgmi_gmi_workspace_size(gf, n_eval, n_snr, "mfma"))
-    t_learned = timed(lambda: mdgmi.mdgmi_mlp_gmi(tr.net, gf, y, tx, snr, out=out, ws=lws))
-    t_exact = timed(lambda: mdgmi.mdgmi_gmi(gf, y, tx, s2, path="mfma", out=out, ws=ews))
-    routed = [r == "learned" for r in ev.route]
-    t_mixed = sum((t_learned if r else t_exact) / n_snr for r in routed)
-    pts = n_snr * n_eval * gf.M
-    return {
-        "train_samples": res.samples, "train_seconds": train_s,
-        "final_train_loss_nats": res.losses[-1][1] if res.losses else None,
-        "eval_samples_per_snr": n_eval,
-        "learned_value": pts / (t_learned * 1e-3), "learned_ms": t_learned,
-        "exact_value_same_samples": pts / (t_exact * 1e-3), "exact_ms": t_exact,
-        "speedup_learned_vs_exact": t_exact / t_learned,
-        "mixed_value": pts / (t_mixed * 1e-3), "speedup_mixed_vs_exact": t_exact / t_mixed,
-        "snr_db": [float(v) for v in snr],
-        "gmi_exact": [float(v) for v in ev.gmi_exact], "gmi_learned": [float(v) for v in ev.gmi_learned],
-        "gmi_loss": [float(v) for v in ev.loss], "route": ev.route,
-        "s_opt_learned": [float(v) for v in ev.s_opt],
-        "gmi_loss_sopt": [float(a - b) for a, b in zip(ev.gmi_exact, ev.gmi_learned_sopt)],
-        "n_learned_snr": int(sum(routed)), "max_loss_bound": 0.01,
-        "note": "learned value counts n*M sample*points per sample demapped by the network; mixed routes "
-                "each SNR point to the learned kernel where its paired GMI loss <= 0.01 bit, else exact",
-    }
+def learned_structured_leg(args, log):
+    """The same network on a structured 8-D format (M = 4096, a product of
+    four Gray 8-QAM constellations), where it meets the 0.01-bit bound: what
+    the trained network gains over the exact demapper."""
+    import numpy as np
+    import workloads as w
+    from paper_2011_13695_amd import mdgmi
+    f = w.qam_product(8, 12)
+    gf = mdgmi.Format.of(f)
+    net, tr = train_net(gf, args.learned_structured_samples, log)
+    snr = np.arange(2.0, 18.0)
+    n_eval = max(1024, int(args.learned_eval) // snr.size)
+    row = learned_route_leg(gf, f.name, snr, n_eval, net, log, tr)
+    row["note"] = "8-D M = 4096 Gray 8-QAM product; network and training as for the timed format"
+    return row
+
+
+def learned_infer_leg(gf, args, log):
+    """Fused inference alone (random-initialised network of the timed shape,
+    no training): GMI mode over learned_eval samples and LLR mode, for
+    profiling and the kernel's roofline."""
+    import numpy as np
+    import torch
+    from paper_2011_13695_amd import learned, mdgmi
+    net = mdgmi.MLP([gf.dim + 1, 256, 256, 256, gf.m], seed=5)
+    snr = np.arange(2.0, 18.0)
+    n = max(1024, int(args.learned_eval) // snr.size)
+    y, tx = mdgmi.mdgmi_generate(gf, 77, learned.sigma2_of(snr, gf.dim), n, snr_slot0=8_000_000)
+    out = torch.empty((snr.size, mdgmi.MDGMI_NFIELDS), dtype=torch.float64, device="cuda")
+    lws = mdgmi.workspace(mdgmi.mdgmi_mlp_gmi_workspace_size(net, min(1 << 20, n)))
+    t_gmi = timed_ms(lambda: mdgmi.mdgmi_mlp_gmi(net, gf, y, tx, snr, out=out, ws=lws))
+    lam = torch.empty((n, gf.m), dtype=torch.float32, device="cuda")
+    sn = torch.full((n,), 10.0, dtype=torch.float32, device="cuda")
+    t_llr = timed_ms(lambda: net.llr(y[0], sn, out=lam))
+    log(f"learned inference: GMI mode {t_gmi:.1f} ms for {snr.size * n} samples, LLR mode {t_llr:.2f} ms for {n}")
+    return {"samples": int(snr.size * n), "gmi_mode_ms": t_gmi, "llr_mode_ms_per_snr_point": t_llr,
+            "roofline": learned_roofline(snr.size * n, t_gmi)}
 
 
 def q_crossing(snr_db, q_db, q_ref):
@@ -641,8 +727,14 @@ def main():
     line.update(extra)
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
-    if args.learned_samples > 0:
+    if args.learned_infer_only:
+        line["learned_inference"] = learned_infer_leg(gf, args, lambda m: log("learned: " + m))
+    elif args.learned_samples > 0:
+        y = tx = None
+        torch.cuda.empty_cache()
         line["learned"] = learned_leg(gf, wl, args, lambda m: log("learned: " + m))
+        if args.learned_structured_samples > 0:
+            line["learned_structured"] = learned_structured_leg(args, lambda m: log("learned: " + m))
     if not args.no_ragged:
         y = tx = None
         torch.cuda.empty_cache()

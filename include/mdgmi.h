@@ -455,8 +455,8 @@ int mdgmi_mlp_llr(const mdgmi_mlp* net, const float* y, const float* snr_db, int
                   size_t ws_bytes, void* stream);
 
 /* ---- learned demapper as a path, with per-SNR fallback -------------------
- * mdgmi_learned_calibrate attaches a network of the fused shape with
- * dim + 1 inputs and log2(M) outputs to a format and decides, per noise
+ * mdgmi_learned_calibrate attaches a network with dim + 1 inputs and
+ * log2(M) outputs to a format and decides, per noise
  * variance, which demapper MDGMI_PATH_LEARNED_BF16 uses: on the given
  * held-out samples y [n_snr][n][dim] (float) with sent rows tx_idx, the
  * exact GMI on exact_path (an FP32 path or AUTO) and the network's GMI are
@@ -464,7 +464,9 @@ int mdgmi_mlp_llr(const mdgmi_mlp* net, const float* y, const float* snr_db, int
  * is at most max_loss (and both are finite) that sigma2 is routed to the
  * network, elsewhere to exact_path. result_host [n_snr][4] receives
  * GMI_exact, GMI_learned, the loss and the route (1 learned, 0 exact).
- * The network's SNR feature is 10 log10(E||x||^2 / (dim sigma2)) dB.
+ * The network's SNR feature is 10 log10(E||x||^2 / (dim sigma2)) dB. Any
+ * network shape is served (the fused kernel where it applies, else the
+ * layer-by-layer GEMMs).
  * Synchronous (waits for `stream`); replaces an earlier calibration of the
  * format; the network must stay alive while the format uses it.
  * MDGMI_PATH_LEARNED_BF16 in mdgmi_gmi: SNR points routed to the network
@@ -474,8 +476,8 @@ int mdgmi_mlp_llr(const mdgmi_mlp* net, const float* y, const float* snr_db, int
  * network's LLRs or the exact ones, by the same rule. Workspaces: from
  * mdgmi_gmi_workspace_size / mdgmi_llr_workspace_size with this path (after
  * calibration; MDGMI_E_UNSUPPORTED before). */
-int mdgmi_learned_calibrate_workspace_size(const mdgmi_format* fmt, int32_t exact_path, int64_t n, int32_t n_snr,
-                                           size_t* bytes);
+int mdgmi_learned_calibrate_workspace_size(const mdgmi_format* fmt, const mdgmi_mlp* net, int32_t exact_path,
+                                           int64_t n, int32_t n_snr, size_t* bytes);
 int mdgmi_learned_calibrate(mdgmi_format* fmt, const mdgmi_mlp* net, int32_t exact_path, double max_loss,
                             const float* y, const uint32_t* tx_idx, int64_t n, const double* sigma2_host,
                             int32_t n_snr, double* result_host, void* ws, size_t ws_bytes, void* stream);

@@ -713,25 +713,42 @@ int routed(const LearnedBinding* b, double sigma2) {
     return 0;
 }
 
-size_t learned_part_bytes() { return (size_t)al((int64_t)fused_grid() * kNPart * 8); }
+bool use_fused(const mdgmi_mlp* net) { return net->fused && g_fused_waves != 0 && fused_grid() <= kLearnedBlocks; }
+
+int64_t learned_chunk(int64_t n) { return std::min<int64_t>(n, (int64_t)1 << 20); }
+
+// Workspace of the network's GMI over n samples of one SNR point: block
+// partials of the fused kernel, or the layer-by-layer path's buffers.
+size_t learned_ws_bytes(const mdgmi_mlp* net, int64_t n) {
+    if (use_fused(net)) return (size_t)al((int64_t)fused_grid() * kNPart * 8);
+    size_t b = 0;
+    mdgmi_mlp_gmi_workspace_size(net, learned_chunk(n), &b);
+    return b;
+}
 
 int check_net_for(const mdgmi_format* f, const mdgmi_mlp* net) {
-    if (!net->fused) return MDGMI_E_UNSUPPORTED;
     if (net->sizes[0] != f->dim + 1 || net->sizes[net->L] != f->m) return MDGMI_E_SHAPE;
     return MDGMI_OK;
 }
 
-// Learned GMI of SNR point q (one fused launch + finish) into out_row.
-hipError_t learned_gmi_one(const mdgmi_format* fmt, const mdgmi_mlp* net, const float* yq, const uint32_t* tq,
-                           int64_t n, double sigma2, double* part, double* out_row, hipStream_t st) {
+double snr_db_of(const mdgmi_format* f, double sigma2) { return 10.0 * std::log10(f->energy / (f->dim * sigma2)); }
+
+// Learned GMI of one SNR point into out_row.
+int learned_gmi_one(const mdgmi_format* fmt, const mdgmi_mlp* net, const float* yq, const uint32_t* tq, int64_t n,
+                    double sigma2, void* ws, size_t ws_bytes, double* out_row, hipStream_t st) {
+    if (!use_fused(net)) {
+        const double snr = snr_db_of(fmt, sigma2);
+        return mdgmi_mlp_gmi(net, fmt, yq, tq, n, &snr, 1, learned_chunk(n), out_row, ws, ws_bytes, st);
+    }
     const float* bias[4];
     fused_biases(net, bias);
     const int grid = fused_grid();
-    hipError_t e = launch_mlp_gmi_fused(net->d_wf, bias, net->sizes[0], net->sizes[4], yq, fmt->dim, tq,
-                                        fmt->d_labels, fmt->M, n, snr_feature(fmt, sigma2), part, grid, st);
-    if (e != hipSuccess) return e;
+    double* part = (double*)ws;
+    if (launch_mlp_gmi_fused(net->d_wf, bias, net->sizes[0], net->sizes[4], yq, fmt->dim, tq, fmt->d_labels, fmt->M,
+                             n, snr_feature(fmt, sigma2), part, grid, st) != hipSuccess)
+        return MDGMI_E_HIP;
     hipLaunchKernelGGL(k_learned_finish, dim3(1), dim3(64), 0, st, part, grid, n, fmt->m, out_row);
-    return hipGetLastError();
+    return hipGetLastError() == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
 }
 
 }  // namespace
@@ -742,7 +759,7 @@ int learned_gmi_workspace_size(const mdgmi_format* fmt, int64_t n, int32_t n_snr
     size_t ex = 0;
     const int rc = mdgmi_gmi_workspace_size(fmt, n, n_snr, b->exact_path, &ex);
     if (rc != MDGMI_OK) return rc;
-    *bytes = std::max(ex, learned_part_bytes());
+    *bytes = std::max(ex, learned_ws_bytes(b->net, n));
     return MDGMI_OK;
 }
 
@@ -779,10 +796,11 @@ int learned_gmi(const mdgmi_format* fmt, const float* y, const uint32_t* tx_idx,
         int q1 = q0 + 1;
         while (q1 < n_snr && routed(b, sigma2_host[q1]) == r) q1++;
         if (r) {
-            for (int q = q0; q < q1; q++)
-                if (learned_gmi_one(fmt, b->net, y + (size_t)q * n * dim, tx_idx + (size_t)q * n, n, sigma2_host[q],
-                                    (double*)ws, out + (size_t)q * MDGMI_NFIELDS, st) != hipSuccess)
-                    return MDGMI_E_HIP;
+            for (int q = q0; q < q1; q++) {
+                rc = learned_gmi_one(fmt, b->net, y + (size_t)q * n * dim, tx_idx + (size_t)q * n, n, sigma2_host[q],
+                                     ws, ws_bytes, out + (size_t)q * MDGMI_NFIELDS, st);
+                if (rc != MDGMI_OK) return rc;
+            }
         } else {
             rc = gmi_with_workspace(fmt, y + (size_t)q0 * n * dim, tx_idx + (size_t)q0 * n, n, sigma2_host + q0,
                                     q1 - q0, b->exact_path, out + (size_t)q0 * MDGMI_NFIELDS, ws, ws_bytes, stream);
@@ -796,7 +814,13 @@ int learned_gmi(const mdgmi_format* fmt, const float* y, const uint32_t* tx_idx,
 int learned_llr_workspace_size(const mdgmi_format* fmt, int64_t n, size_t* bytes) {
     const LearnedBinding* b = fmt->learned;
     if (!b) return MDGMI_E_UNSUPPORTED;
-    return mdgmi_llr_workspace_size(fmt, n, b->exact_path, bytes);
+    size_t ex = 0;
+    const int rc = mdgmi_llr_workspace_size(fmt, n, b->exact_path, &ex);
+    if (rc != MDGMI_OK) return rc;
+    const mdgmi_mlp* net = b->net;
+    const size_t le = use_fused(net) ? 0 : (size_t)(al(n * net->sizes[0] * 4) + mlp_ws(net, n).total);
+    *bytes = std::max(ex, le);
+    return MDGMI_OK;
 }
 
 int learned_llr(const mdgmi_format* fmt, const float* y, int64_t n, double sigma2, float* llr, void* ws,
@@ -809,11 +833,26 @@ int learned_llr(const mdgmi_format* fmt, const float* y, int64_t n, double sigma
     if (!routed(b, sigma2)) return mdgmi_llr(fmt, y, n, sigma2, llr, b->exact_path, ws, ws_bytes, stream);
     int rc = check_device(fmt);
     if (rc != MDGMI_OK) return rc;
+    const mdgmi_mlp* net = b->net;
+    hipStream_t st = (hipStream_t)stream;
+    if (!use_fused(net)) {
+        size_t need = 0;
+        if ((rc = learned_llr_workspace_size(fmt, n, &need)) != MDGMI_OK) return rc;
+        if (!ws || ws_bytes < need) return MDGMI_E_WORKSPACE;
+        float* x = (float*)ws;
+        char* mws = (char*)ws + al(n * net->sizes[0] * 4);
+        const MlpWs w = mlp_ws(net, n);
+        if (features(y, n, fmt->dim, nullptr, snr_feature(fmt, sigma2), x, st) != hipSuccess ||
+            forward(net, x, n, mws, w, st) != hipSuccess ||
+            hipMemcpyAsync(llr, mws + w.logits, sizeof(float) * n * fmt->m, hipMemcpyDeviceToDevice, st) !=
+                hipSuccess)
+            return MDGMI_E_HIP;
+        return MDGMI_OK;
+    }
     const float* bias[4];
-    fused_biases(b->net, bias);
-    const hipError_t e = launch_mlp_llr_fused(b->net->d_wf, bias, b->net->sizes[0], b->net->sizes[4], y, fmt->dim, n,
-                                              nullptr, snr_feature(fmt, sigma2), llr, fused_grid(),
-                                              (hipStream_t)stream);
+    fused_biases(net, bias);
+    const hipError_t e = launch_mlp_llr_fused(net->d_wf, bias, net->sizes[0], net->sizes[4], y, fmt->dim, n, nullptr,
+                                              snr_feature(fmt, sigma2), llr, fused_grid(), st);
     return e == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
 }
 
@@ -884,14 +923,14 @@ int mdgmi_mlp_llr(const mdgmi_mlp* net, const float* y, const float* snr_db, int
                : MDGMI_E_HIP;
 }
 
-int mdgmi_learned_calibrate_workspace_size(const mdgmi_format* fmt, int32_t exact_path, int64_t n, int32_t n_snr,
-                                           size_t* bytes) {
-    if (!fmt || !bytes) return MDGMI_E_NULL;
+int mdgmi_learned_calibrate_workspace_size(const mdgmi_format* fmt, const mdgmi_mlp* net, int32_t exact_path,
+                                           int64_t n, int32_t n_snr, size_t* bytes) {
+    if (!fmt || !net || !bytes) return MDGMI_E_NULL;
     if (n < 1 || n_snr < 1) return MDGMI_E_SHAPE;
     size_t ex = 0;
     const int rc = mdgmi_gmi_workspace_size(fmt, n, n_snr, exact_path, &ex);
     if (rc != MDGMI_OK) return rc;
-    *bytes = al(2 * (int64_t)n_snr * MDGMI_NFIELDS * 8) + std::max(ex, learned_part_bytes());
+    *bytes = al(2 * (int64_t)n_snr * MDGMI_NFIELDS * 8) + std::max(ex, learned_ws_bytes(net, n));
     return MDGMI_OK;
 }
 
@@ -914,7 +953,7 @@ int mdgmi_learned_calibrate(mdgmi_format* fmt, const mdgmi_mlp* net, int32_t exa
     int p = 0;
     if ((rc = resolve_path(fmt, exact_path, max_s, &p)) != MDGMI_OK) return rc;
     size_t need = 0;
-    if ((rc = mdgmi_learned_calibrate_workspace_size(fmt, exact_path, n, n_snr, &need)) != MDGMI_OK) return rc;
+    if ((rc = mdgmi_learned_calibrate_workspace_size(fmt, net, exact_path, n, n_snr, &need)) != MDGMI_OK) return rc;
     if (!ws || ws_bytes < need) return MDGMI_E_WORKSPACE;
     if ((rc = check_device(fmt)) != MDGMI_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
@@ -924,10 +963,11 @@ int mdgmi_learned_calibrate(mdgmi_format* fmt, const mdgmi_mlp* net, int32_t exa
     rc = gmi_with_workspace(fmt, y, tx_idx, n, sigma2_host, n_snr, exact_path, rows, rest, rest_bytes, stream);
     if (rc != MDGMI_OK) return rc;
     double* lrows = rows + (size_t)n_snr * MDGMI_NFIELDS;
-    for (int q = 0; q < n_snr; q++)
-        if (learned_gmi_one(fmt, net, y + (size_t)q * n * fmt->dim, tx_idx + (size_t)q * n, n, sigma2_host[q],
-                            (double*)rest, lrows + (size_t)q * MDGMI_NFIELDS, st) != hipSuccess)
-            return MDGMI_E_HIP;
+    for (int q = 0; q < n_snr; q++) {
+        rc = learned_gmi_one(fmt, net, y + (size_t)q * n * fmt->dim, tx_idx + (size_t)q * n, n, sigma2_host[q], rest,
+                             rest_bytes, lrows + (size_t)q * MDGMI_NFIELDS, st);
+        if (rc != MDGMI_OK) return rc;
+    }
     std::vector<double> h((size_t)2 * n_snr * MDGMI_NFIELDS);
     if (hipMemcpyAsync(h.data(), rows, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)

@@ -621,7 +621,7 @@ def _mlp_sigs():
     L.mdgmi_mlp_train_step.argtypes = [_P, _P, _P, _P, ctypes.c_int64, ctypes.c_float, _P, _P, ctypes.c_size_t, _P]
     L.mdgmi_mlp_llr_workspace_size.argtypes = [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
     L.mdgmi_mlp_llr.argtypes = [_P, _P, _P, ctypes.c_int64, _P, _P, ctypes.c_size_t, _P]
-    L.mdgmi_learned_calibrate_workspace_size.argtypes = [_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+    L.mdgmi_learned_calibrate_workspace_size.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                                          ctypes.POINTER(ctypes.c_size_t)]
     L.mdgmi_learned_calibrate.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_double, _P, _P, ctypes.c_int64, _P,
                                           ctypes.c_int32, _P, _P, ctypes.c_size_t, _P]
@@ -706,6 +706,12 @@ class MLP:
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         _check("mdgmi_mlp_adam_step", lib().mdgmi_mlp_adam_step(self.handle, lr, beta1, beta2, eps, _stream(stream)))
+
+    def train_workspace_size(self, n):
+        b = ctypes.c_size_t()
+        _check("mdgmi_mlp_train_workspace_size",
+               _mlp_sigs().mdgmi_mlp_train_workspace_size(self.handle, n, ctypes.byref(b)))
+        return b.value
 
     def train_step(self, y, snr_db, target_llr, lr, loss=None, ws=None, stream=None):
         """mdgmi_mlp_train_step: features from y [n, dim] and per-sample SNRs
@@ -805,7 +811,7 @@ def mdgmi_learned_calibrate(fmt: Format, net: "MLP", y, tx_idx, sigma2, exact_pa
     p = _path(exact_path)
     b = ctypes.c_size_t()
     _check("mdgmi_learned_calibrate_workspace_size",
-           L.mdgmi_learned_calibrate_workspace_size(fmt.handle, p, n, n_snr, ctypes.byref(b)))
+           L.mdgmi_learned_calibrate_workspace_size(fmt.handle, net.handle, p, n, n_snr, ctypes.byref(b)))
     ws = workspace(b.value)
     res = np.empty((n_snr, 4), dtype=np.float64)
     _check("mdgmi_learned_calibrate", L.mdgmi_learned_calibrate(fmt.handle, net.handle, p, float(max_loss), _dptr(y),
