@@ -193,6 +193,19 @@ struct CostAcc {
     }
 };
 
+// Sum over the bits of log2(T / S_k), the GMI cost of a sample (T the total
+// of all its terms, S_k the class sum of sent bit k), as -log2(prod_k S_k / T):
+// one reciprocal of T, one product per bit, one logarithm. Each factor is in
+// (0, 1] up to rounding; while the product stays at least 2^-120 (a cost
+// below 120 bits) it is a normal FP32 number and the result is exact to
+// rounding. Returns false (cost untouched) when it is not, or not finite:
+// the caller then takes the per-bit form.
+__device__ __forceinline__ bool cost_from_product(float prod, float& cost) {
+    const bool ok = prod >= 0x1p-120f;
+    if (ok) cost = fmaxf(-__builtin_amdgcn_logf(prod), 0.0f);
+    return ok;
+}
+
 // Per-lane hard-decision error counts (bits, symbols), kept as doubles.
 struct HdAcc {
     double be = 0.0, se = 0.0;

@@ -195,7 +195,7 @@ __device__ __forceinline__ void direct_sample(const float* __restrict__ im, cons
             }
         }
         if (!row_ok) cg = cm = NAN;
-        acc.add((double)cg, (double)cm);
+        acc.add(cg, cm);
         if (MODE == kModeHd) {
             // bitwise MAP decisions (S1 > S0 decides 1; log2 sums on the
             // exact path, same order) and the nearest point
@@ -325,7 +325,7 @@ __device__ __forceinline__ void direct_sample_ml(const float* __restrict__ im, c
             }
         }
         if (!row_ok || !finite) cg = NAN;
-        acc.add((double)cg, 0.0);
+        acc.add(cg, 0.0f);
     }
 }
 

@@ -735,26 +735,51 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
         for (int r = 0; r < 16; r++) dv = (r == q) ? ud[r] : dv;
         const Halves d = halves(dv);
         const float ui = ((col >> 2) & 1) ? d.hi : d.lo;
-        float cg = 0.0f, be = 0.0f;
+        // this half's class sums of its bit pair j (bit 2j + h)
+        auto own_sums = [&](int j, float& s0, float& s1) {
+            const int ke = 2 * j, ko = ke + 1 < MDGMI_MAX_BITS ? ke + 1 : ke;
+            float S0e, S1e, S0o = 1.0f, S1o = 1.0f;
+            if (ke == 2) {
+                S0e = S0t;
+                S1e = S1t;
+            } else {
+                full_sums(p0, p1, ke, S0e, S1e);
+            }
+            if (ko < m) full_sums(p0, p1, ko, S0o, S1o);
+            s0 = h ? S0o : S0e;
+            s1 = h ? S1o : S1e;
+        };
+        // GMI cost of this half's bits, sum_k log2(T / S_sent,k), as one
+        // logarithm of the product of S_sent,k / T (cost_from_product)
+        float cg = 0.0f, be = 0.0f, prod = 1.0f;
+        const float rT = __builtin_amdgcn_rcpf(tot);
 #pragma unroll
         for (int j = 0; j < (MDGMI_MAX_BITS + 1) / 2; j++) {
             if (2 * j < m) {  // uniform
-                const int ke = 2 * j, ko = ke + 1 < MDGMI_MAX_BITS ? ke + 1 : ke;
-                float S0e, S1e, S0o = 1.0f, S1o = 1.0f;
-                if (ke == 2) {
-                    S0e = S0t;
-                    S1e = S1t;
-                } else {
-                    full_sums(p0, p1, ke, S0e, S1e);
-                }
-                if (ko < m) full_sums(p0, p1, ko, S0o, S1o);
-                const int k = ke + h;
-                const float s0 = h ? S0o : S0e, s1 = h ? S1o : S1e;
+                float s0, s1;
+                own_sums(j, s0, s1);
+                const int k = 2 * j + h;
                 if (k < m) {
-                    // log2(1 + S_other / S_sent) = log2((S0 + S1) / S_sent)
                     const bool bk = (slot >> k) & 1;
-                    cg += bit_cost_sum2(s0 + s1, bk ? s1 : s0);
+                    prod *= (bk ? s1 : s0) * rT;
                     if (HD) be += (s1 > s0) != bk ? 1.0f : 0.0f;  // bitwise MAP decision
+                }
+            }
+        }
+        const bool fast = prod >= 0x1p-120f;
+        if (__ballot(!fast) == 0ull) {
+            cost_from_product(prod, cg);
+        } else {
+            // some sample of the wave has a cost beyond 120 bits or a
+            // non-finite sum: bit by bit, log2(1 + S_other / S_sent)
+            asm volatile("" ::: "memory");  // keeps the rare path a real branch
+#pragma unroll
+            for (int j = 0; j < (MDGMI_MAX_BITS + 1) / 2; j++) {
+                if (2 * j < m) {
+                    float s0, s1;
+                    own_sums(j, s0, s1);
+                    const int k = 2 * j + h;
+                    if (k < m) cg += bit_cost_sum2(s0 + s1, ((slot >> k) & 1) ? s1 : s0);
                 }
             }
         }
@@ -793,7 +818,7 @@ __device__ __forceinline__ void mfma_coltile(const uint4* __restrict__ A, const 
             cm = ltot + ti;
         }
         if (!row_ok) cg = cm = NAN;
-        acc.add((double)cg, (double)cm);
+        acc.add(cg, cm);
         if (HD) {
             const bool finite = cg == cg && cm == cm && ui == ui;
             hd->be += finite ? (double)be : (double)m;
@@ -993,7 +1018,7 @@ __device__ __forceinline__ void mfma_coltile_ml(const uint4* __restrict__ A, con
                 }
             } else if (h == 0) {
                 const uint32_t row = txs[i];
-                acc.add(row < (uint32_t)M ? (double)cg : (double)NAN, 0.0);
+                acc.add(row < (uint32_t)M ? cg : NAN, 0.0f);
             }
             continue;
         }
@@ -1014,7 +1039,7 @@ __device__ __forceinline__ void mfma_coltile_ml(const uint4* __restrict__ A, con
 #pragma unroll
             for (int k = 0; k < MDGMI_MAX_BITS; k++)
                 if (k < m) c2 += bit_cost2(((slot >> k) & 1) ? u0[k] - u1[k] : u1[k] - u0[k]);
-            acc.add(row_ok && fin[c] ? (double)c2 : (double)NAN, 0.0);
+            acc.add(row_ok && fin[c] ? c2 : NAN, 0.0f);
         }
     }
 }

@@ -348,7 +348,7 @@ __device__ __forceinline__ void small_sample(const half4 (&a)[Sets<NG>::value][N
                 const bool bk = (slot >> k) & 1;
                 cg += bit_cost2(bk ? u0[k] - u1[k] : u1[k] - u0[k]);
             }
-            acc.add(row_ok && finite ? (double)cg : (double)NAN, 0.0);
+            acc.add(row_ok && finite ? cg : NAN, 0.0f);
         }
         return;
     }
@@ -387,12 +387,23 @@ __device__ __forceinline__ void small_sample(const half4 (&a)[Sets<NG>::value][N
     const f32x4 ud = chain_own<NK>(ad, bo, Kc);
     const bool q1 = lane & 1, q2 = lane & 2;
     const float ui = q2 ? (q1 ? ud[3] : ud[2]) : (q1 ? ud[1] : ud[0]);
-    float cg = 0.0f, cm, be = 0.0f, sym;
+    // GMI cost sum_k log2(T / S_sent,k) as one logarithm of the product of
+    // S_sent,k / T (cost_from_product); bit by bit where a sample of the
+    // wave has a cost beyond 120 bits or a non-finite sum
+    float cg = 0.0f, cm, be = 0.0f, sym, prod = 1.0f;
+    const float rT = __builtin_amdgcn_rcpf(tot);
 #pragma unroll
     for (int k = 0; k < m; k++) {
         const bool bk = (slot >> k) & 1;
-        cg += bit_cost_sum2(S0[k] + S1[k], bk ? S1[k] : S0[k]);
+        prod *= (bk ? S1[k] : S0[k]) * rT;
         if (HD) be += (S1[k] > S0[k]) != bk ? 1.0f : 0.0f;  // bitwise MAP decision
+    }
+    if (__ballot(!(prod >= 0x1p-120f)) == 0ull) {
+        cost_from_product(prod, cg);
+    } else {
+        asm volatile("" ::: "memory");  // keeps the rare path a real branch
+#pragma unroll
+        for (int k = 0; k < m; k++) cg += bit_cost_sum2(S0[k] + S1[k], ((slot >> k) & 1) ? S1[k] : S0[k]);
     }
     // another point strictly nearer, or the sent point's coordinates shared
     // with a lower label (ties go to the lowest label)
@@ -416,7 +427,7 @@ __device__ __forceinline__ void small_sample(const half4 (&a)[Sets<NG>::value][N
     }
     if (!valid) return;
     if (!row_ok) cg = cm = NAN;
-    acc.add((double)cg, (double)cm);
+    acc.add(cg, cm);
     if (HD) {
         const bool finite = cg == cg && cm == cm && ui == ui;
         hd.be += finite ? (double)be : (double)m;
