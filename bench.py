@@ -90,6 +90,7 @@ def parse():
     ap.add_argument("--no-other-configs", action="store_true",
                     help="skip the 16-QAM FP64 and 4-D M=64 configurations")
     ap.add_argument("--ragged-scale", type=float, default=1.0, help="scale of the ragged sample counts")
+    ap.add_argument("--no-peak-probe", action="store_true", help="skip measuring the device's peak rates")
     ap.add_argument("--copy-probe", type=float, default=0,
                     help="only run a plain device copy of this many bytes (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -184,7 +185,14 @@ def cpu_baseline(wl, target_s: float):
         oracle.gmi(y, tx, f.X, f.labels, float(s2))
         elapsed += time.perf_counter() - t0
     pairs = n_cpu * len(wl.snr_db) * f.M
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fp:
+            model = next((l.split(":", 1)[1].strip() for l in fp if l.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": pairs / elapsed, "unit": "sample*points/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model,
             "sample": f"first {n_cpu} samples of each of the {len(wl.snr_db)} SNR points "
                       f"({pairs:.3g} sample*points, {elapsed:.1f} s, FP64, {threads} threads)"}
 
@@ -700,6 +708,7 @@ def main():
         torch.cuda.empty_cache()
         extra["other_configs"] = other_configs_leg()
     achieved = pairs / (kernel_ms * 1e-3)
+    peaks = None if args.no_peak_probe else mdgmi.mdgmi_probe_rates()
     line = {
         "metric": METRIC,
         "value": value,
@@ -720,7 +729,10 @@ def main():
                      "frac": achieved / EXP_PEAK, "traffic": measured_traffic(),
                      "traffic_unit": "bytes per launch",
                      "kernel": "k_mfma (demap + fused reduction); 1 v_exp_f32 per (sample, point)",
-                     "kernel_ms": kernel_ms},
+                     "kernel_ms": kernel_ms,
+                     "measured_peak": None if peaks is None else peaks["exp_per_s"] / 1e12,
+                     "frac_of_measured_peak": None if peaks is None else achieved / peaks["exp_per_s"]},
+        "measured_peaks": peaks,
         "gmi": [float(v) for v in out[:, 0]],
         "mi": [float(v) for v in out[:, 1]],
     }

@@ -486,6 +486,19 @@ int mdgmi_learned_calibrate(mdgmi_format* fmt, const mdgmi_mlp* net, int32_t exa
 int mdgmi_mlp_save(const mdgmi_mlp* net, const char* path);
 int mdgmi_mlp_load(mdgmi_mlp* net, const char* path);
 
+/* Measured peaks of the current device, behind the roofline figures (the
+ * demapper is bound by the exponential issue rate of the vector ALU, the
+ * learned demapper by the matrix cores): out_host [5] receives
+ *   [0] v_exp_f32 results per second over the whole device,
+ *   [1] the core clock during that probe (Hz, s_memtime cycles against the
+ *       constant reference clock),
+ *   [2] FP32 FMA lane-operations per second, [3] the clock during it,
+ *   [4] v_mfma_f32_32x32x16_bf16 flops per second.
+ * Each probe runs 8 waves per SIMD of independent dependency chains; it
+ * allocates and frees a few bytes of device memory and synchronises the
+ * device (a measurement call, not for hot loops). */
+int mdgmi_probe_rates(double* out_host);
+
 /* Launch-shape override of the MFMA path for tuning sweeps: variant v in
  * 0..7 selects 32x32 tiles with (sample columns per wave, waves per block) =
  * (1,4), (2,4), (1,8), (2,8), (1,16), (1,12) with the operand image in LDS,

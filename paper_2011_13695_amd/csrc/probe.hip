@@ -1,0 +1,123 @@
+// Rate probes of the vector ALU and the matrix cores on the current device:
+// the measured peaks behind the roofline figures of the demapper kernels.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "internal.h"
+
+namespace mdgmi {
+namespace {
+
+constexpr int kProbeThreads = 256;
+constexpr int kProbeChains = 8;  // independent dependency chains per lane
+
+// kIters x kProbeChains base-2 exponentials per lane (v_exp_f32,
+// v <- 2^-v: the negation is a source modifier, so the loop holds nothing
+// but exponentials); the values stay in [0.5, 1]. Cycle counts of the
+// core clock (s_memtime) and of the constant reference clock are recorded by
+// lane 0 of block 0.
+template <int OP>
+__global__ __launch_bounds__(kProbeThreads) void k_probe(int iters, float seed, float* __restrict__ sink,
+                                                         unsigned long long* __restrict__ clk) {
+    float v[kProbeChains];
+#pragma unroll
+    for (int c = 0; c < kProbeChains; c++) v[c] = seed * (float)(threadIdx.x + c + 1) * 1e-6f;
+    unsigned long long c0 = 0, w0 = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        c0 = clock64();
+        w0 = wall_clock64();
+    }
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int c = 0; c < kProbeChains; c++) {
+            if (OP == 0)
+                v[c] = __builtin_amdgcn_exp2f(-v[c]);
+            else
+                v[c] = fmaf(v[c], 0.999999f, 1.0e-7f);        // plain FP32 FMA
+        }
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kProbeChains; c++) s += v[c];
+    if (s == 12345.0f) sink[threadIdx.x] = s;  // keeps the chains alive
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        clk[0] = clock64() - c0;
+        clk[1] = wall_clock64() - w0;
+    }
+}
+
+typedef __bf16 pbf16x8 __attribute__((ext_vector_type(8)));
+typedef float pf32x16 __attribute__((ext_vector_type(16)));
+
+// Independent chains of v_mfma_f32_32x32x16_bf16 per wave.
+__global__ __launch_bounds__(kProbeThreads) void k_probe_mfma(int iters, float* __restrict__ sink) {
+    pbf16x8 a, b;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        a[i] = (__bf16)(1e-3f * (float)(threadIdx.x + i));
+        b[i] = (__bf16)(1e-3f * (float)(i + 1));
+    }
+    pf32x16 acc[4] = {};
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int c = 0; c < 4; c++) acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[c], 0, 0, 0);
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 4; c++) s += acc[c][0];
+    if (s == 12345.0f) sink[threadIdx.x] = s;
+}
+
+}  // namespace
+}  // namespace mdgmi
+
+using namespace mdgmi;
+
+extern "C" int mdgmi_probe_rates(double* out_host) {
+    if (!out_host) return MDGMI_E_NULL;
+    int dev = 0, wall_khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wall_khz <= 0)
+        return MDGMI_E_HIP;
+    const int blocks = device_cu_count() * 8;  // 8 waves per SIMD
+    float* sink = nullptr;
+    unsigned long long* clk = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipMalloc(&sink, sizeof(float) * kProbeThreads) != hipSuccess ||
+        hipMalloc(&clk, 2 * sizeof(unsigned long long)) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess)
+        return MDGMI_E_HIP;
+    int rc = MDGMI_OK;
+    auto run = [&](int op, int iters, double ops_per_lane_iter, double* rate, double* hz) {
+        for (int rep = 0; rep < 2; rep++) {  // the first launch warms up
+            (void)hipEventRecord(e0, nullptr);
+            if (op == 0)
+                hipLaunchKernelGGL(k_probe<0>, dim3(blocks), dim3(kProbeThreads), 0, nullptr, iters, 0.5f, sink, clk);
+            else if (op == 1)
+                hipLaunchKernelGGL(k_probe<1>, dim3(blocks), dim3(kProbeThreads), 0, nullptr, iters, 0.5f, sink, clk);
+            else
+                hipLaunchKernelGGL(k_probe_mfma, dim3(blocks), dim3(kProbeThreads), 0, nullptr, iters, sink);
+            (void)hipEventRecord(e1, nullptr);
+        }
+        float ms = 0.0f;
+        unsigned long long c[2] = {0, 0};
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess ||
+            hipMemcpy(c, clk, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess) {
+            rc = MDGMI_E_HIP;
+            return;
+        }
+        *rate = (double)blocks * kProbeThreads * iters * ops_per_lane_iter / (ms * 1e-3);
+        if (hz) *hz = c[1] > 0 ? (double)c[0] / ((double)c[1] / (wall_khz * 1e3)) : 0.0;
+    };
+    // exponentials and FMAs per lane and iteration; MFMA: 4 per wave and
+    // iteration of 2 * 32 * 32 * 16 flops each, counted per lane (/ 64)
+    run(0, 4096, kProbeChains, &out_host[0], &out_host[1]);
+    run(1, 16384, kProbeChains, &out_host[2], &out_host[3]);
+    run(2, 2048, 4.0 * 2 * 32 * 32 * 16 / 64.0, &out_host[4], nullptr);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(sink);
+    (void)hipFree(clk);
+    return rc;
+}

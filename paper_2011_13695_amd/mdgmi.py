@@ -87,6 +87,7 @@ def lib():
         L.mdgmi_q_factor_db.restype = ctypes.c_double
         L.mdgmi_q_factor_db.argtypes = [ctypes.c_double]
         L.mdgmi_set_tuning.argtypes = [ctypes.c_int]
+        L.mdgmi_probe_rates.argtypes = [_P]
         _lib = L
     return _lib
 
@@ -825,3 +826,11 @@ def mdgmi_learned_calibrate(fmt: Format, net: "MLP", y, tx_idx, sigma2, exact_pa
 def mdgmi_mlp_set_fused(waves: int) -> None:
     """Inference kernel of mdgmi_mlp_gmi: 8 (default) or 4 waves fused, 0 layer by layer."""
     _check("mdgmi_mlp_set_fused", lib().mdgmi_mlp_set_fused(int(waves)))
+
+
+def mdgmi_probe_rates() -> dict:
+    """Measured peaks of the current device (mdgmi_probe_rates)."""
+    out = np.zeros(5, dtype=np.float64)
+    _check("mdgmi_probe_rates", lib().mdgmi_probe_rates(out.ctypes.data_as(_P)))
+    return {"exp_per_s": float(out[0]), "clock_hz_exp": float(out[1]), "fma_lane_ops_per_s": float(out[2]),
+            "clock_hz_fma": float(out[3]), "mfma_bf16_flops_per_s": float(out[4])}
