@@ -59,6 +59,13 @@ static int log2_exact(int M) {
     return m;
 }
 
+/* Sent rows must index X: returns 0 if every tx_idx[s] < M. */
+static int rows_in_range(const uint32_t* tx_idx, int64_t n, int M) {
+    for (int64_t s = 0; s < n; s++)
+        if (tx_idx[s] >= (uint32_t)M) return 0;
+    return 1;
+}
+
 /* t_j = ||y - x_j||^2 / (2 sigma2) for all j (nats). */
 static void metrics(const double* y, const double* X, int M, int dim, double sigma2, double* t) {
     for (int j = 0; j < M; j++) {
@@ -123,10 +130,12 @@ int oracle_llr(const double* y, int64_t n, int dim, const double* X, const uint3
     return err ? -1 : 0;
 }
 
-/* Per-sample GMI and MI costs (bits). tx_idx[s] is the row of X sent.
- * Either output pointer may be NULL. */
+/* Per-sample GMI and MI costs (bits). tx_idx[s] is the row of X sent
+ * (returns -3, computing nothing, if some row is not below M). Either output
+ * pointer may be NULL. */
 int oracle_costs(const double* y, const uint32_t* tx_idx, int64_t n, int dim, const double* X,
                  const uint32_t* labels, int M, double sigma2, double* c_gmi, double* c_mi) {
+    if (!rows_in_range(tx_idx, n, M)) return -3;
     int m = log2_exact(M);
     int err = 0;
 #pragma omp parallel
@@ -302,6 +311,7 @@ static void hd_one(const double* y, int dim, const double* X, const uint32_t* la
 int oracle_hd(const double* y, const uint32_t* tx_idx, int64_t n, int dim, const double* X,
               const uint32_t* labels, int M, double sigma2, double* out) {
     if (n < 1) return -2;
+    if (!rows_in_range(tx_idx, n, M)) return -3;
     int m = log2_exact(M);
     int64_t bit_err = 0, sym_err = 0, bad = 0;
     int err = 0;

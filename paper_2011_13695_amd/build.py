@@ -1,6 +1,6 @@
 """Build libmdgmi.so (HIP, gfx950) in-tree with hipcc.
 
-Every .hip file under csrc/ is compiled separately (in parallel) and linked
+Every .hip and .cpp file under csrc/ is compiled separately (in parallel) and linked
 into paper_2011_13695_amd/libmdgmi.so. Packed FP32 instructions are disabled
 for all device code.
 """
@@ -35,7 +35,8 @@ EXTRA_FLAGS = {name: ["-mllvm", "-amdgpu-mfma-vgpr-form"] for name in ("exact_mf
 
 
 def sources():
-    return sorted(CSRC.glob("*.hip"))
+    """HIP sources, plus the host-only C++ ones (no device code)."""
+    return sorted([*CSRC.glob("*.hip"), *CSRC.glob("*.cpp")])
 
 
 def _compile(src: Path, incremental: bool = False) -> Path:

@@ -236,71 +236,28 @@ const char* mdgmi_status_string(int status) {
     }
 }
 
-int mdgmi_validate_labels(const uint32_t* labels_host, int32_t M) {
-    if (!labels_host) return MDGMI_E_NULL;
-    if (M < 1 || M > (1 << MDGMI_MAX_BITS)) return MDGMI_E_SHAPE;
-    std::vector<uint8_t> seen((size_t)M, 0);
-    for (int32_t j = 0; j < M; j++) {
-        uint32_t l = labels_host[j];
-        if (l >= (uint32_t)M || seen[l]) return MDGMI_E_LABELS;
-        seen[l] = 1;
-    }
-    return MDGMI_OK;
-}
-
 int mdgmi_format_create(const double* X_host, const uint32_t* labels_host, int32_t M, int32_t dim,
                         mdgmi_format** out) {
     if (!X_host || !labels_host || !out) return MDGMI_E_NULL;
     *out = nullptr;
-    if (dim != 1 && dim != 2 && dim != 4 && dim != 8) return MDGMI_E_SHAPE;
-    if (M < 2 || M > (1 << MDGMI_MAX_BITS) || (M & (M - 1)) != 0) return MDGMI_E_SHAPE;
-    int rc = mdgmi_validate_labels(labels_host, M);
+    FormatHost fh;
+    const int rc = prepare_format(X_host, labels_host, M, dim, fh);
     if (rc != MDGMI_OK) return rc;
-    for (size_t i = 0; i < (size_t)M * dim; i++)
-        if (!std::isfinite(X_host[i])) return MDGMI_E_ARG;
     mdgmi_format* f = new mdgmi_format();
     f->M = M;
     f->dim = dim;
-    f->m = 0;
-    while ((1 << f->m) < M) f->m++;
+    f->m = fh.m;
+    f->energy = fh.energy;
+    f->max_abs = fh.max_abs;
+    f->max_norm2 = fh.max_norm2;
     if (hipGetDevice(&f->device) != hipSuccess) {
         delete f;
         return MDGMI_E_HIP;
     }
-    std::vector<double> X64((size_t)M * dim);
-    std::vector<float> X32((size_t)M * dim), n32((size_t)M);
-    for (int32_t r = 0; r < M; r++) {
-        const uint32_t slot = labels_host[r];
-        double n2 = 0.0;
-        for (int d = 0; d < dim; d++) {
-            const double x = X_host[(size_t)r * dim + d];
-            X64[(size_t)slot * dim + d] = x;
-            X32[(size_t)slot * dim + d] = (float)x;
-            n2 += x * x;
-            f->max_abs = std::max(f->max_abs, std::fabs(x));
-        }
-        n32[slot] = (float)n2;
-        f->max_norm2 = std::max(f->max_norm2, n2);
-        f->energy += n2 / M;
-    }
-    // Rows sharing their coordinates with a lower label: sort rows by
-    // (coordinates, label); within a run of equal points all but the first
-    // carry kTwinBit.
-    std::vector<uint32_t> lab_hd(labels_host, labels_host + M), order((size_t)M);
-    for (int32_t r = 0; r < M; r++) order[r] = (uint32_t)r;
-    auto pt = [&](uint32_t r, int d) { return X_host[(size_t)r * dim + d]; };
-    auto same = [&](uint32_t a, uint32_t b) {
-        for (int d = 0; d < dim; d++)
-            if (!(pt(a, d) == pt(b, d))) return false;
-        return true;
-    };
-    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-        for (int d = 0; d < dim; d++)
-            if (pt(a, d) != pt(b, d)) return pt(a, d) < pt(b, d);
-        return labels_host[a] < labels_host[b];
-    });
-    for (int32_t k = 1; k < M; k++)
-        if (same(order[k - 1], order[k])) lab_hd[order[k]] |= kTwinBit;
+    const std::vector<double>& X64 = fh.X64;
+    const std::vector<float>& X32 = fh.X32;
+    const std::vector<float>& n32 = fh.n32;
+    const std::vector<uint32_t>& lab_hd = fh.labels_hd;
     f->h_X64 = new double[(size_t)M * dim];
     std::memcpy(f->h_X64, X64.data(), sizeof(double) * X64.size());
     bool ok = hipMalloc(&f->d_X64, sizeof(double) * X64.size()) == hipSuccess &&

@@ -7,6 +7,7 @@
 #include <cstddef>
 
 #include "../../include/mdgmi.h"
+#include "format_host.h"
 
 struct mdgmi_format {
     int32_t M = 0, dim = 0, m = 0;
@@ -45,8 +46,6 @@ __host__ __device__ constexpr bool mode_is_ml(int mode) { return mode == kModeMl
 // what the final reduction writes: GMI/MI, + hard decisions, or GMI only
 constexpr int kReduceGmi = 0, kReduceHd = 1, kReduceMl = 2;
 constexpr int kMaxSnrPerLaunch = 32;
-constexpr uint32_t kTwinBit = 1u << 16;   // in d_labels_hd; labels are < 2^12
-constexpr uint32_t kLabelMask = kTwinBit - 1u;
 // Exponents are taken relative to a fixed offset: e_j = 2^(kBias - t_j) with
 // t_j = ||y - x_j||^2 / (2 sigma2) * log2(e) >= 0, so no term can overflow
 // (M * 2^kBias < 2^128) and any class whose nearest point lies within
