@@ -50,6 +50,30 @@ class TrainResult:
     steps: int
     samples: int
     losses: list = field(default_factory=list)   # (step, loss in nats per sample)
+    curve: list = field(default_factory=list)    # (samples seen, paired GMI loss per held-out SNR point)
+
+
+class HeldOut:
+    """Fixed held-out samples at a few SNR points with their exact GMI: the
+    paired GMI loss GMI_exact - GMI_learned of a network on them, per SNR
+    point (a training curve that does not mix SNR points)."""
+
+    def __init__(self, gf: mdgmi.Format, snr_db=(2.0, 5.0, 8.0, 11.0, 14.0, 17.0), n: int = 65536,
+                 seed: int = 999, snr_slot0: int = 7_000_000, path: str = "mfma"):
+        import torch
+        self.gf = gf
+        self.snr = np.asarray(snr_db, dtype=np.float64)
+        s2 = sigma2_of(self.snr, gf.dim)
+        self.y, self.tx = mdgmi.mdgmi_generate(gf, seed, s2, n, snr_slot0=snr_slot0)
+        self.exact = mdgmi.mdgmi_gmi(gf, self.y, self.tx, s2, path=path).cpu().numpy()[:, 0]
+        self.out = torch.empty((self.snr.size, mdgmi.MDGMI_NFIELDS), dtype=torch.float64, device="cuda")
+        self.ws = None
+
+    def loss(self, net: mdgmi.MLP):
+        if self.ws is None:
+            self.ws = mdgmi.workspace(mdgmi.mdgmi_mlp_gmi_workspace_size(net, self.y.shape[1]))
+        mdgmi.mdgmi_mlp_gmi(net, self.gf, self.y, self.tx, self.snr, out=self.out, ws=self.ws)
+        return self.exact - self.out.cpu().numpy()[:, 0]
 
 
 class Trainer:
@@ -105,16 +129,25 @@ class Trainer:
         self.net.train_step(self.yb, self.snr, self.lb, self.lr_at(self.step_no), loss=self.loss, ws=self.train_ws)
         self.step_no += 1
 
-    def train(self, steps=None, log=None):
+    def train(self, steps=None, log=None, held_out: HeldOut | None = None, curve_points: int = 8):
+        """Runs `steps` Adam steps; with held_out, the paired GMI loss per
+        held-out SNR point is recorded curve_points times along the way."""
         steps = steps or self.cfg.steps
         res = TrainResult(0, 0)
-        for _ in range(steps):
+        marks = {max(1, round(steps * (q + 1) / curve_points)) for q in range(curve_points)} if held_out else set()
+        for k in range(1, steps + 1):
             self.step()
             if self.step_no % self.cfg.log_every == 0 or self.step_no == 1:
                 v = float(self.loss.item())
                 res.losses.append((self.step_no, v))
                 if log:
                     log(f"step {self.step_no} loss {v:.5f} nats ({v * LOG2E:.5f} bits)")
+            if k in marks:
+                lv = held_out.loss(self.net)
+                res.curve.append((self.step_no * self.cfg.batch, [float(v) for v in lv]))
+                if log:
+                    log(f"{self.step_no * self.cfg.batch:.3g} samples: held-out GMI loss " +
+                        " ".join(f"{a:g}dB:{b:.4f}" for a, b in zip(held_out.snr, lv)))
         res.steps = self.step_no
         res.samples = self.step_no * self.cfg.batch
         return res
