@@ -42,7 +42,7 @@ HBM_PEAK = 8.0e12
 # the same counter reads for a plain copy kernel of known size (a 1 GiB copy
 # reads FETCH_SIZE = 0.5 GiB and WRITE_SIZE = 1 GiB: factors 2.0 and 1.0).
 # Reported only while the kernel sources hash to the value they were taken on.
-TRAFFIC = {"sources_sha1": "1987f56503605d679da3dad70964d7d08eca7872", "fetch_kib": 2821980.8125, "write_kib": 1040.0,
+TRAFFIC = {"sources_sha1": "12ce0a7589d39c496fef99c67191afea3b711240", "fetch_kib": 2821954.5625, "write_kib": 1040.0,
            "fetch_scale": 2.0, "write_scale": 1.0}
 KERNEL_SOURCES = ("mfma_core.h", "mfma_kernels.h", "device_common.h", "internal.h", "exact_mfma_d8_f16.hip")
 
@@ -284,21 +284,30 @@ def learned_route_leg(gf, fmt_name, snr, n_eval, net, log, train=None):
 
 
 def train_net(gf, samples, log, **kw):
+    """Trains the network on gf; records the paired GMI loss on fixed
+    held-out samples at six SNR points eight times along the way."""
     import torch
     from paper_2011_13695_amd import learned
     cfg = learned.TrainConfig(log_every=2000, **kw)
     cfg.steps = max(1, int(samples) // cfg.batch)
     tr = learned.Trainer(gf, cfg)
+    held = learned.HeldOut(gf)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = tr.train(log=log)
+    res = tr.train(log=log, held_out=held)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     log(f"trained {res.samples} samples in {train_s:.1f} s")
     return tr.net, {"train_samples": res.samples, "train_seconds": train_s, "train_steps": res.steps,
                     "batch": cfg.batch, "lr": cfg.lr,
                     "train_flops_per_s": 3 * MLP_FLOPS_PER_SAMPLE * res.samples / train_s,
-                    "final_train_loss_nats": res.losses[-1][1] if res.losses else None}
+                    "final_train_loss_nats": res.losses[-1][1] if res.losses else None,
+                    "heldout_curve": {"snr_db": [float(v) for v in held.snr], "samples_per_snr": held.y.shape[1],
+                                      "gmi_exact": [float(v) for v in held.exact],
+                                      "samples_seen": [c[0] for c in res.curve],
+                                      "gmi_loss": [c[1] for c in res.curve],
+                                      "note": "paired GMI loss (bit) of the network on fixed held-out samples "
+                                              "during training; train_seconds includes these evaluations"}}
 
 
 def learned_leg(gf, wl, args, log):
