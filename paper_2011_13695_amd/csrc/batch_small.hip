@@ -76,8 +76,20 @@ __global__ __launch_bounds__(kSmallWaves * 64) void k_batch_small(const BatchIns
 
 hipError_t launch_batch_small(const BatchInst* insts, const BatchItem* items, int i0, int i1, unsigned* counter,
                               double* part, hipStream_t st) {
-    // one resident round: about 137 VGPRs leave room for three waves per SIMD
-    const int grid = std::max(1, std::min(i1 - i0, device_cu_count() * 3));
+    // one resident round: the blocks per CU that the compiled kernel's
+    // registers allow (one kernel serves every (dim, M) of the kind, so the
+    // largest formats' operand registers set it), times the CUs. Separate
+    // kernels per register class ran the 1/100-scale ragged set slower (three
+    // launches, each with a partial last round) and the full set no faster.
+    static const int per_cu = [] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, (const void*)k_batch_small, kSmallWaves * 64, 0) !=
+                hipSuccess ||
+            b < 1)
+            b = 1;
+        return b;
+    }();
+    const int grid = std::max(1, std::min(i1 - i0, device_cu_count() * per_cu));
     hipLaunchKernelGGL(k_batch_small, dim3(grid), dim3(kSmallWaves * 64), 0, st, insts, items, i0, i1, counter,
                        part);
     return hipGetLastError();
