@@ -371,16 +371,33 @@ int mdgmi_batch_destroy(mdgmi_batch* b);
 
 /* ---- autotuner --------------------------------------------------------------
  * Times the FP32 direct kernel and every MFMA launch variant on synthetic
- * samples of (dim, M) on the current device and records the fastest; the
- * table steers MDGMI_PATH_AUTO and batch plans. Rates in sample*points/s. */
+ * samples of (dim, M) at 10 dB on the current device and records the
+ * fastest, separately for two sample-count regimes of a launch (samples over
+ * all its SNR points): bulk (at least MDGMI_TUNE_SHORT_SAMPLES), timed on
+ * max(2^20, 2^28 / M) samples, at most 2^22 (at least two resident rounds of
+ * every launch shape), and short (fewer), timed on 2^15 samples. The table
+ * steers MDGMI_PATH_AUTO, the launch shape of MDGMI_PATH_F32_MFMA_F16SPLIT
+ * calls (each call by its own regime, falling back to the other regime's
+ * entry) and the per-instance kind of ragged batches (bulk). mdgmi_autotune
+ * allocates and frees device memory and synchronises its own stream; it
+ * re-times only with force or when an entry is missing. Rates in
+ * sample*points/s. */
+#define MDGMI_TUNE_SHORT_SAMPLES (1 << 18)
+#define MDGMI_TUNE_BULK 0
+#define MDGMI_TUNE_SHORT 1
 typedef struct {
     int32_t dim, M;
+    int32_t regime;        /* MDGMI_TUNE_BULK or MDGMI_TUNE_SHORT                */
     int32_t path;          /* MDGMI_PATH_F32_DIRECT or MDGMI_PATH_F32_MFMA_F16SPLIT */
     int32_t mfma_variant;  /* fastest MFMA launch variant, -1 if none ran     */
+    int32_t pad;
+    int64_t samples;       /* samples per timed call                          */
     double direct_rate, mfma_rate;
 } mdgmi_tune_entry;
+/* out: NULL or host [2], receives the bulk then the short entry */
 int mdgmi_autotune(int32_t dim, int32_t M, int32_t force, mdgmi_tune_entry* out);
-int mdgmi_tune_lookup(int32_t dim, int32_t M, mdgmi_tune_entry* out);  /* MDGMI_E_ARG if untuned */
+/* MDGMI_E_ARG if (dim, M) is untuned in that regime or regime is invalid */
+int mdgmi_tune_lookup(int32_t dim, int32_t M, int32_t regime, mdgmi_tune_entry* out);
 int mdgmi_tune_save(const char* path);   /* JSON */
 int mdgmi_tune_load(const char* path);
 int mdgmi_tune_clear(void);

@@ -39,7 +39,7 @@ int check_device(const mdgmi_format* f) {
 
 // Resolve MDGMI_PATH_AUTO and check that the path can serve the format at
 // the largest s = log2(e) / (2 sigma2) of the call.
-int resolve_path(const mdgmi_format* f, int path, double max_s, int* out) {
+int resolve_path(const mdgmi_format* f, int path, double max_s, int* out, int64_t total) {
     switch (path) {
         case MDGMI_PATH_F64:
         case MDGMI_PATH_F32_DIRECT:
@@ -56,7 +56,7 @@ int resolve_path(const mdgmi_format* f, int path, double max_s, int* out) {
         case MDGMI_PATH_AUTO: {
             const bool small = small_shape_fits(f);
             const bool mfma_ok = (f->M >= 32 || small) && mfma_supported(f, max_s);
-            const int t = tuned_path(f->dim, f->M);
+            const int t = tuned_path(f->dim, f->M, total);
             // untuned: the per-sample 4x4 shape for small formats, the 32 x 32
             // shape from 128 points; between them the vector-ALU kernel
             const bool want_mfma = t == MDGMI_PATH_F32_MFMA_F16SPLIT || (t < 0 && (f->M >= 128 || small));
@@ -94,7 +94,13 @@ GmiPlan plan_gmi(const mdgmi_format* f, int64_t n, int n_snr, int path, int mode
         p.cfg = mfma_cfg(f, n, n_snr, mode, split);
         p.image_bytes = mfma_image_bytes(f, per_launch, split);
     }
-    p.part_bytes = (size_t)n_snr * p.cfg.blocks_per_snr * part_stride(mode) * sizeof(double);
+    int64_t blocks = (int64_t)n_snr * p.cfg.blocks_per_snr;
+    // MFMA launch shapes follow the tuning table, per sample-count regime:
+    // room for whichever shape a call over these samples (or a subset of
+    // the SNR points) may take
+    if (path == MDGMI_PATH_F32_MFMA_F16SPLIT || path == MDGMI_PATH_F32_MFMA_BF16SPLIT)
+        blocks = std::max(blocks, mfma_blocks_bound(f, n, n_snr, mode, path == MDGMI_PATH_F32_MFMA_BF16SPLIT ? 1 : 0));
+    p.part_bytes = (size_t)blocks * part_stride(mode) * sizeof(double);
     p.total = align_up(p.part_bytes) + align_up(p.image_bytes);
     return p;
 }
@@ -162,7 +168,7 @@ int run_gmi(const mdgmi_format* fmt, const void* y, const uint32_t* tx_idx, int6
         max_s = std::max(max_s, s_of(sigma2_host[q]));
     }
     int p = 0;
-    int rc = resolve_path(fmt, path, max_s, &p);
+    int rc = resolve_path(fmt, path, max_s, &p, n * (int64_t)n_snr);
     if (rc != MDGMI_OK) return rc;
     GmiPlan pl = plan_gmi(fmt, n, n_snr, p, mode);
     if (!ws || ws_bytes < pl.total) return MDGMI_E_WORKSPACE;
@@ -191,7 +197,7 @@ int run_llr(const mdgmi_format* fmt, const void* y, int64_t n, double sigma2, vo
     if (n < 1) return MDGMI_E_SHAPE;
     if (!finite_pos(sigma2)) return MDGMI_E_SIGMA2;
     int p = 0;
-    int rc = resolve_path(fmt, path, s_of(sigma2), &p);
+    int rc = resolve_path(fmt, path, s_of(sigma2), &p, n);
     if (rc != MDGMI_OK) return rc;
     size_t need = 0;
     rc = mdgmi_llr_workspace_size(fmt, n, p, &need);

@@ -1,15 +1,21 @@
-// Autotuner: per (dim, M) it times the FP32 direct kernel and every MFMA
-// launch variant on synthetic samples of that shape on the current device,
-// and records the fastest. The table steers MDGMI_PATH_AUTO calls and the
-// per-instance path of ragged batches; it can be saved to and loaded from a
-// small JSON file ({"arch": ..., "entries": [{"dim", "M", "path",
-// "variant", "direct_rate", "mfma_rate"}, ...]}).
+// Autotuner: per (dim, M) and per sample-count regime it times the FP32
+// direct kernel and every MFMA launch variant on synthetic samples of that
+// shape on the current device, and records the fastest. The bulk regime
+// (launches of at least kTuneShortSamples samples over their SNR points) is
+// timed on at least 2^20 samples, two resident rounds of the widest launch
+// shape and more; the short regime on 2^15 samples, a fraction of one round.
+// The table steers MDGMI_PATH_AUTO calls, the MFMA launch shape of
+// fp16-split calls and the per-instance kind of ragged batches (bulk); it
+// can be saved to and loaded from a small JSON file ({"arch": ...,
+// "entries": [{"dim", "M", "regime", "samples", "path", "variant",
+// "direct_rate", "mfma_rate"}, ...]}).
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -21,7 +27,16 @@ namespace mdgmi {
 namespace {
 
 std::mutex g_mu;
-std::map<std::pair<int, int>, mdgmi_tune_entry> g_table;
+std::map<std::tuple<int, int, int>, mdgmi_tune_entry> g_table;  // (dim, M, regime)
+
+// Entry of (dim, M) for a launch of `total` samples: its regime's, else
+// the other regime's; nullptr when (dim, M) is untuned. Caller holds g_mu.
+const mdgmi_tune_entry* find_entry(int dim, int M, int64_t total) {
+    const int r = tune_regime(total);
+    auto it = g_table.find({dim, M, r});
+    if (it == g_table.end()) it = g_table.find({dim, M, 1 - r});
+    return it == g_table.end() ? nullptr : &it->second;
+}
 
 // Synthetic format for timing only: two shells (radius 1 and 1.6) in `dim`
 // dimensions with Box-Muller directions from a fixed xorshift stream, unit
@@ -58,21 +73,21 @@ void synth_format(int dim, int M, std::vector<double>& X, std::vector<uint32_t>&
 
 int tuned_batch_kind(int dim, int M) {
     std::lock_guard<std::mutex> g(g_mu);
-    auto it = g_table.find({dim, M});
-    if (it == g_table.end()) return -1;
-    return it->second.path == MDGMI_PATH_F32_MFMA_F16SPLIT ? kKindMfma : kKindDirect;
+    const mdgmi_tune_entry* e = find_entry(dim, M, INT64_MAX);  // a batch is one bulk launch per kind
+    if (!e) return -1;
+    return e->path == MDGMI_PATH_F32_MFMA_F16SPLIT ? kKindMfma : kKindDirect;
 }
 
-int tuned_path(int dim, int M) {
+int tuned_path(int dim, int M, int64_t total) {
     std::lock_guard<std::mutex> g(g_mu);
-    auto it = g_table.find({dim, M});
-    return it == g_table.end() ? -1 : it->second.path;
+    const mdgmi_tune_entry* e = find_entry(dim, M, total);
+    return e ? e->path : -1;
 }
 
-int tuned_mfma_variant(int dim, int M) {
+int tuned_mfma_variant(int dim, int M, int64_t total) {
     std::lock_guard<std::mutex> g(g_mu);
-    auto it = g_table.find({dim, M});
-    return it == g_table.end() ? -1 : it->second.mfma_variant;
+    const mdgmi_tune_entry* e = find_entry(dim, M, total);
+    return e ? e->mfma_variant : -1;
 }
 
 int64_t tuned_item_pairs() { return kItemPairsDefault; }
@@ -83,10 +98,11 @@ using namespace mdgmi;
 
 extern "C" {
 
-int mdgmi_tune_lookup(int32_t dim, int32_t M, mdgmi_tune_entry* out) {
+int mdgmi_tune_lookup(int32_t dim, int32_t M, int32_t regime, mdgmi_tune_entry* out) {
     if (!out) return MDGMI_E_NULL;
+    if (regime != MDGMI_TUNE_BULK && regime != MDGMI_TUNE_SHORT) return MDGMI_E_ARG;
     std::lock_guard<std::mutex> g(g_mu);
-    auto it = g_table.find({dim, M});
+    auto it = g_table.find({dim, M, regime});
     if (it == g_table.end()) return MDGMI_E_ARG;
     *out = it->second;
     return MDGMI_OK;
@@ -103,9 +119,12 @@ int mdgmi_autotune(int32_t dim, int32_t M, int32_t force, mdgmi_tune_entry* out)
     if (M < 2 || M > (1 << MDGMI_MAX_BITS) || (M & (M - 1))) return MDGMI_E_SHAPE;
     if (!force) {
         std::lock_guard<std::mutex> g(g_mu);
-        auto it = g_table.find({dim, M});
-        if (it != g_table.end()) {
-            if (out) *out = it->second;
+        auto bulk = g_table.find({dim, M, MDGMI_TUNE_BULK}), shrt = g_table.find({dim, M, MDGMI_TUNE_SHORT});
+        if (bulk != g_table.end() && shrt != g_table.end()) {
+            if (out) {
+                out[0] = bulk->second;
+                out[1] = shrt->second;
+            }
             return MDGMI_OK;
         }
     }
@@ -115,9 +134,15 @@ int mdgmi_autotune(int32_t dim, int32_t M, int32_t force, mdgmi_tune_entry* out)
     mdgmi_format* f = nullptr;
     int rc = mdgmi_format_create(X.data(), lab.data(), M, dim, &f);
     if (rc != MDGMI_OK) return rc;
-    // about 2^28 sample*points per timed call, at least 2^14 samples
-    int64_t n = std::max<int64_t>(int64_t(1) << 14, (int64_t(1) << 28) / M);
-    n = std::min<int64_t>(n, int64_t(1) << 22);
+    // bulk: about 2^28 sample*points per timed call and at least 2^20
+    // samples (two resident rounds of every launch shape: the widest, the
+    // per-sample 4x4 shape, holds about 3.3e5 samples per round on 256 CUs),
+    // at most 2^22; short: 2^15 samples
+    int64_t n_regime[2];
+    n_regime[MDGMI_TUNE_BULK] = std::min<int64_t>(
+        int64_t(1) << 22, std::max<int64_t>(int64_t(1) << 20, (int64_t(1) << 28) / M));
+    n_regime[MDGMI_TUNE_SHORT] = int64_t(1) << 15;
+    const int64_t n = n_regime[MDGMI_TUNE_BULK];
     const double sigma2 = 1.0 / (dim * 10.0);  // 10 dB
     float* y = nullptr;
     uint32_t* tx = nullptr;
@@ -125,11 +150,7 @@ int mdgmi_autotune(int32_t dim, int32_t M, int32_t force, mdgmi_tune_entry* out)
     void* ws = nullptr;
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    mdgmi_tune_entry best{};
-    best.dim = dim;
-    best.M = M;
-    best.path = MDGMI_PATH_F32_DIRECT;
-    best.mfma_variant = -1;
+    mdgmi_tune_entry best[2]{};
     size_t wsb = 0, t;
     rc = MDGMI_E_HIP;
     const int saved_override = mdgmi_get_tuning();
@@ -140,7 +161,7 @@ int mdgmi_autotune(int32_t dim, int32_t M, int32_t force, mdgmi_tune_entry* out)
         if (hipMalloc(&tx, sizeof(uint32_t) * n) != hipSuccess) break;
         if (hipMalloc(&o, sizeof(double) * MDGMI_NFIELDS) != hipSuccess) break;
         if (mdgmi_generate(f, 12345, &sigma2, 1, n, 0, y, tx, 0, st) != MDGMI_OK) break;
-        // workspace for the largest candidate
+        // workspace for the largest candidate (the short calls need less)
         if (mdgmi_gmi_workspace_size(f, n, 1, MDGMI_PATH_F32_DIRECT, &wsb) != MDGMI_OK) break;
         for (int v = 0; v < kMfmaVariants; v++) {
             mdgmi_set_tuning(v);
@@ -148,37 +169,48 @@ int mdgmi_autotune(int32_t dim, int32_t M, int32_t force, mdgmi_tune_entry* out)
         }
         mdgmi_set_tuning(saved_override);
         if (hipMalloc(&ws, wsb) != hipSuccess) break;
-        auto time_call = [&](int path) -> double {
-            if (mdgmi_gmi(f, y, tx, n, &sigma2, 1, path, o, ws, wsb, st) != MDGMI_OK) return -1.0;
-            float best_ms = 1e30f;
-            for (int r = 0; r < 3; r++) {
-                (void)hipEventRecord(e0, st);
-                if (mdgmi_gmi(f, y, tx, n, &sigma2, 1, path, o, ws, wsb, st) != MDGMI_OK) return -1.0;
-                (void)hipEventRecord(e1, st);
-                if (hipEventSynchronize(e1) != hipSuccess) return -1.0;
-                float ms = 0.0f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                best_ms = std::min(best_ms, ms);
-            }
-            return (double)n * M / (best_ms * 1e-3);
-        };
-        best.direct_rate = time_call(MDGMI_PATH_F32_DIRECT);
-        double best_rate = best.direct_rate;
-        best.mfma_rate = 0.0;
-        if ((M >= 32 || small_shape_fits(f)) && mfma_supported(f, kLog2e / (2.0 * sigma2))) {
-            for (int v = 0; v < kMfmaVariants; v++) {
-                mdgmi_set_tuning(v);
-                const double r = time_call(MDGMI_PATH_F32_MFMA_F16SPLIT);
-                if (r > best.mfma_rate) {
-                    best.mfma_rate = r;
-                    best.mfma_variant = v;
+        bool ok = true;
+        for (int r = 0; r < 2 && ok; r++) {
+            const int64_t nr = n_regime[r];
+            // best of 3 timed calls after one untimed call; rate in sample*points/s
+            auto time_call = [&](int path) -> double {
+                if (mdgmi_gmi(f, y, tx, nr, &sigma2, 1, path, o, ws, wsb, st) != MDGMI_OK) return -1.0;
+                float best_ms = 1e30f;
+                for (int k = 0; k < 3; k++) {
+                    (void)hipEventRecord(e0, st);
+                    if (mdgmi_gmi(f, y, tx, nr, &sigma2, 1, path, o, ws, wsb, st) != MDGMI_OK) return -1.0;
+                    (void)hipEventRecord(e1, st);
+                    if (hipEventSynchronize(e1) != hipSuccess) return -1.0;
+                    float ms = 0.0f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    best_ms = std::min(best_ms, ms);
                 }
+                return (double)nr * M / (best_ms * 1e-3);
+            };
+            mdgmi_tune_entry& b = best[r];
+            b.dim = dim;
+            b.M = M;
+            b.regime = r;
+            b.samples = nr;
+            b.path = MDGMI_PATH_F32_DIRECT;
+            b.mfma_variant = -1;
+            b.direct_rate = time_call(MDGMI_PATH_F32_DIRECT);
+            ok = b.direct_rate > 0.0;
+            b.mfma_rate = 0.0;
+            if (ok && (M >= 32 || small_shape_fits(f)) && mfma_supported(f, kLog2e / (2.0 * sigma2))) {
+                for (int v = 0; v < kMfmaVariants; v++) {
+                    mdgmi_set_tuning(v);
+                    const double rate = time_call(MDGMI_PATH_F32_MFMA_F16SPLIT);
+                    if (rate > b.mfma_rate) {
+                        b.mfma_rate = rate;
+                        b.mfma_variant = v;
+                    }
+                }
+                mdgmi_set_tuning(saved_override);
+                if (b.mfma_rate > b.direct_rate) b.path = MDGMI_PATH_F32_MFMA_F16SPLIT;
             }
-            mdgmi_set_tuning(saved_override);
-            // (the batch kernel still runs MFMA only where M >= 128)
-            if (best.mfma_rate > best_rate) best.path = MDGMI_PATH_F32_MFMA_F16SPLIT;
         }
-        rc = MDGMI_OK;
+        if (ok) rc = MDGMI_OK;
     } while (0);
     mdgmi_set_tuning(saved_override);
     if (st) (void)hipStreamSynchronize(st);
@@ -193,9 +225,12 @@ int mdgmi_autotune(int32_t dim, int32_t M, int32_t force, mdgmi_tune_entry* out)
     if (rc != MDGMI_OK) return rc;
     {
         std::lock_guard<std::mutex> g(g_mu);
-        g_table[{dim, M}] = best;
+        for (int r = 0; r < 2; r++) g_table[{dim, M, r}] = best[r];
     }
-    if (out) *out = best;
+    if (out) {
+        out[0] = best[0];
+        out[1] = best[1];
+    }
     return MDGMI_OK;
 }
 
@@ -209,9 +244,9 @@ int mdgmi_tune_save(const char* path) {
     for (const auto& kv : g_table) {
         const mdgmi_tune_entry& e = kv.second;
         std::fprintf(fp,
-                     "  {\"dim\": %d, \"M\": %d, \"path\": %d, \"variant\": %d, \"direct_rate\": %.6e, "
-                     "\"mfma_rate\": %.6e}%s\n",
-                     e.dim, e.M, e.path, e.mfma_variant, e.direct_rate, e.mfma_rate,
+                     "  {\"dim\": %d, \"M\": %d, \"regime\": %d, \"samples\": %lld, \"path\": %d, "
+                     "\"variant\": %d, \"direct_rate\": %.6e, \"mfma_rate\": %.6e}%s\n",
+                     e.dim, e.M, e.regime, (long long)e.samples, e.path, e.mfma_variant, e.direct_rate, e.mfma_rate,
                      ++k < g_table.size() ? "," : "");
     }
     std::fprintf(fp, "]}\n");
@@ -233,16 +268,21 @@ int mdgmi_tune_load(const char* path) {
     size_t pos = 0;
     while ((pos = text.find("{\"dim\"", pos)) != std::string::npos) {
         mdgmi_tune_entry e{};
+        long long samples = 0;
         if (std::sscanf(text.c_str() + pos,
-                        "{\"dim\": %d, \"M\": %d, \"path\": %d, \"variant\": %d, \"direct_rate\": %lf, "
-                        "\"mfma_rate\": %lf}",
-                        &e.dim, &e.M, &e.path, &e.mfma_variant, &e.direct_rate, &e.mfma_rate) == 6) {
-            const bool ok = (e.dim == 1 || e.dim == 2 || e.dim == 4 || e.dim == 8) && e.M >= 2 && e.M <= (1 << MDGMI_MAX_BITS) &&
+                        "{\"dim\": %d, \"M\": %d, \"regime\": %d, \"samples\": %lld, \"path\": %d, "
+                        "\"variant\": %d, \"direct_rate\": %lf, \"mfma_rate\": %lf}",
+                        &e.dim, &e.M, &e.regime, &samples, &e.path, &e.mfma_variant, &e.direct_rate,
+                        &e.mfma_rate) == 8) {
+            e.samples = samples;
+            const bool ok = (e.dim == 1 || e.dim == 2 || e.dim == 4 || e.dim == 8) && e.M >= 2 &&
+                            e.M <= (1 << MDGMI_MAX_BITS) && (e.M & (e.M - 1)) == 0 &&
+                            (e.regime == MDGMI_TUNE_BULK || e.regime == MDGMI_TUNE_SHORT) &&
                             (e.path == MDGMI_PATH_F32_DIRECT || e.path == MDGMI_PATH_F32_MFMA_F16SPLIT) &&
-                            e.mfma_variant < kMfmaVariants;
+                            e.mfma_variant >= -1 && e.mfma_variant < kMfmaVariants;
             if (ok) {
                 std::lock_guard<std::mutex> g(g_mu);
-                g_table[{e.dim, e.M}] = e;
+                g_table[{e.dim, e.M, e.regime}] = e;
                 loaded++;
             }
         }

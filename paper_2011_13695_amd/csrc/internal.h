@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdint>
 #include <cstddef>
 
@@ -79,6 +80,7 @@ struct SnrArgs {
 struct LaunchCfg {
     int blocks_per_snr;
     int threads;
+    int variant = -1;          // MFMA paths: the launch shape chosen by mfma_cfg
 };
 
 // ---- launchers (each in the .hip file holding the kernel) ----
@@ -99,7 +101,8 @@ hipError_t launch_direct(const mdgmi_format* f, const float* y, const uint32_t* 
 // Per-sample 4x4-block shape of the fp16-split path for 4 <= M <= 512
 // (8-D: M <= 256), exact_mfma4.hip; used by launch_mfma where it applies.
 bool small_shape_fits(const mdgmi_format* f);
-// whether the fp16-split path runs f on that shape (tuning table, override)
+// whether the fp16-split path runs f on that shape in launches of many
+// samples (tuning table, override): the ragged batch's choice
 bool prefers_small(const mdgmi_format* f);
 size_t small_image_bytes(const mdgmi_format* f, int n_snr);
 LaunchCfg small_cfg(const mdgmi_format* f, int64_t n, int n_snr);
@@ -109,6 +112,10 @@ hipError_t launch_small(const mdgmi_format* f, const float* y, const uint32_t* t
 // split: 0 = fp16 hi + lo operands, 1 = bf16 in three parts (see mfma_core.h)
 bool mfma_supported(const mdgmi_format* f, double max_s, int split = 0);
 LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr, int mode = kModeGmi, int split = 0);
+// the most blocks, over all SNR points, that any MFMA launch shape takes for
+// n samples at n_snr points or at any subset of them: a partial-sum
+// workspace that holds whichever shape the tuning table picks
+int64_t mfma_blocks_bound(const mdgmi_format* f, int64_t n, int n_snr, int mode = kModeGmi, int split = 0);
 size_t mfma_image_bytes(const mdgmi_format* f, int n_snr, int split = 0);
 hipError_t launch_mfma(const mdgmi_format* f, const float* y, const uint32_t* tx, int64_t n,
                        const SnrArgs& sa, int mode, float* llr, double* part, void* image,
@@ -119,8 +126,9 @@ size_t align_up(size_t v);
 bool finite_pos(double v);
 int check_device(const mdgmi_format* f);
 // Resolve MDGMI_PATH_AUTO and check that the path can serve the format at
-// the largest s = log2(e) / (2 sigma2) of the call.
-int resolve_path(const mdgmi_format* f, int path, double max_s, int* out);
+// the largest s = log2(e) / (2 sigma2) of the call; total = samples of the
+// call over all its SNR points (selects the tuning regime).
+int resolve_path(const mdgmi_format* f, int path, double max_s, int* out, int64_t total = INT64_MAX);
 double s_of(double sigma2);
 int part_stride(int mode);
 struct GmiPlan {
@@ -163,8 +171,12 @@ int gmi_with_workspace(const mdgmi_format* fmt, const void* y, const uint32_t* t
                        const double* sigma2_host, int32_t n_snr, int32_t path, double* out, void* ws, size_t ws_bytes,
                        void* stream);
 
-// autotuner table (autotune.hip); -1 where (dim, M) is untuned
-int tuned_path(int dim, int M);
-int tuned_mfma_variant(int dim, int M);
+// autotuner table (autotune.hip), per (dim, M) and sample-count regime of
+// the launch (total samples over its SNR points below kTuneShortSamples:
+// the short regime); -1 where (dim, M) is untuned
+constexpr int64_t kTuneShortSamples = MDGMI_TUNE_SHORT_SAMPLES;
+inline int tune_regime(int64_t total) { return total < kTuneShortSamples ? 1 : 0; }
+int tuned_path(int dim, int M, int64_t total);
+int tuned_mfma_variant(int dim, int M, int64_t total);
 
 }  // namespace mdgmi

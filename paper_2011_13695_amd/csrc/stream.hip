@@ -117,7 +117,7 @@ int mdgmi_stream_create(const mdgmi_format* fmt, double sigma2, int64_t buffer_n
         return MDGMI_E_SHAPE;
     if (!finite_pos(sigma2)) return MDGMI_E_SIGMA2;
     int p = 0;
-    int rc = resolve_path(fmt, path, s_of(sigma2), &p);
+    int rc = resolve_path(fmt, path, s_of(sigma2), &p, buffer_n);
     if (rc != MDGMI_OK) return rc;
     rc = check_device(fmt);
     if (rc != MDGMI_OK) return rc;

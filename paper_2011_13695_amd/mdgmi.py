@@ -475,12 +475,17 @@ class mdgmi_instance(ctypes.Structure):
     _fields_ = [("fmt", _P), ("y", _P), ("tx_idx", _P), ("n", ctypes.c_int64), ("sigma2", ctypes.c_double)]
 
 
+MDGMI_TUNE_BULK, MDGMI_TUNE_SHORT = 0, 1
+MDGMI_TUNE_SHORT_SAMPLES = 1 << 18
+
+
 class mdgmi_tune_entry(ctypes.Structure):
-    _fields_ = [("dim", ctypes.c_int32), ("M", ctypes.c_int32), ("path", ctypes.c_int32),
-                ("mfma_variant", ctypes.c_int32), ("direct_rate", ctypes.c_double), ("mfma_rate", ctypes.c_double)]
+    _fields_ = [("dim", ctypes.c_int32), ("M", ctypes.c_int32), ("regime", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("mfma_variant", ctypes.c_int32), ("pad", ctypes.c_int32), ("samples", ctypes.c_int64),
+                ("direct_rate", ctypes.c_double), ("mfma_rate", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
 def _batch_sigs():
@@ -495,7 +500,7 @@ def _batch_sigs():
     L.mdgmi_batch_info.argtypes = [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     L.mdgmi_batch_destroy.argtypes = [_P]
     L.mdgmi_autotune.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(mdgmi_tune_entry)]
-    L.mdgmi_tune_lookup.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(mdgmi_tune_entry)]
+    L.mdgmi_tune_lookup.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(mdgmi_tune_entry)]
     L.mdgmi_tune_save.argtypes = [ctypes.c_char_p]
     L.mdgmi_tune_load.argtypes = [ctypes.c_char_p]
     L._batch_sigs = True
@@ -572,16 +577,19 @@ class Batch:
 
 
 def mdgmi_autotune(dim: int, M: int, force: bool = False) -> dict:
+    """Bulk-regime entry as a dict, the short-regime entry under "short"."""
     L = _batch_sigs()
-    e = mdgmi_tune_entry()
-    _check("mdgmi_autotune", L.mdgmi_autotune(dim, M, int(force), ctypes.byref(e)))
-    return e.as_dict()
+    e = (mdgmi_tune_entry * 2)()
+    _check("mdgmi_autotune", L.mdgmi_autotune(dim, M, int(force), e))
+    d = e[0].as_dict()
+    d["short"] = e[1].as_dict()
+    return d
 
 
-def mdgmi_tune_lookup(dim: int, M: int):
+def mdgmi_tune_lookup(dim: int, M: int, regime: int = MDGMI_TUNE_BULK):
     L = _batch_sigs()
     e = mdgmi_tune_entry()
-    rc = L.mdgmi_tune_lookup(dim, M, ctypes.byref(e))
+    rc = L.mdgmi_tune_lookup(dim, M, int(regime), ctypes.byref(e))
     return e.as_dict() if rc == MDGMI_OK else None
 
 

@@ -125,3 +125,48 @@ def test_binding_checks_element_types():
         mdgmi._check_y(y32, mdgmi.MDGMI_PATH_F64)
     with pytest.raises(TypeError):
         mdgmi._check_y(y32, mdgmi.MDGMI_PATH_AUTO, tx.to(torch.int64))
+
+
+def _tune_json(entries):
+    rows = ",\n".join(
+        f'  {{"dim": {d}, "M": {M}, "regime": {r}, "samples": {n}, "path": {p}, "variant": {v}, '
+        f'"direct_rate": {dr:.6e}, "mfma_rate": {mr:.6e}}}' for d, M, r, n, p, v, dr, mr in entries)
+    return '{"arch": "gfx950", "entries": [\n' + rows + "\n]}\n"
+
+
+def test_tune_table_regimes_json_host_only(tmp_path):
+    """The tuning table holds one entry per (dim, M, sample-count regime);
+    it survives a save/load round trip, and the loader skips malformed
+    entries (no device involved)."""
+    p = tmp_path / "t.json"
+    p.write_text(_tune_json([(8, 256, 0, 1 << 20, 1, -1, 2.0e12, 1.0e12),
+                             (8, 256, 1, 1 << 15, 2, 4, 1.0e12, 3.0e12),
+                             (4, 64, 1, 1 << 15, 2, 8, 1.0e12, 2.5e12),
+                             (4, 48, 0, 1 << 20, 1, -1, 1.0e12, 0.0),      # M not a power of two
+                             (2, 16, 2, 1 << 20, 1, -1, 1.0e12, 0.0)]))    # no such regime
+    mdgmi.mdgmi_tune_clear()
+    try:
+        mdgmi.mdgmi_tune_load(p)
+        bulk = mdgmi.mdgmi_tune_lookup(8, 256, mdgmi.MDGMI_TUNE_BULK)
+        short = mdgmi.mdgmi_tune_lookup(8, 256, mdgmi.MDGMI_TUNE_SHORT)
+        assert bulk["path"] == mdgmi.MDGMI_PATH_F32_DIRECT and bulk["samples"] == 1 << 20
+        assert short["path"] == mdgmi.MDGMI_PATH_F32_MFMA_F16SPLIT and short["mfma_variant"] == 4
+        assert short["regime"] == mdgmi.MDGMI_TUNE_SHORT and short["samples"] == 1 << 15
+        assert mdgmi.mdgmi_tune_lookup(4, 64, mdgmi.MDGMI_TUNE_BULK) is None
+        assert mdgmi.mdgmi_tune_lookup(4, 64, mdgmi.MDGMI_TUNE_SHORT)["mfma_variant"] == 8
+        assert mdgmi.mdgmi_tune_lookup(4, 48, mdgmi.MDGMI_TUNE_BULK) is None
+        assert mdgmi.mdgmi_tune_lookup(2, 16, mdgmi.MDGMI_TUNE_BULK) is None
+        assert mdgmi.mdgmi_tune_lookup(8, 256, 2) is None
+        q = tmp_path / "u.json"
+        mdgmi.mdgmi_tune_save(q)
+        mdgmi.mdgmi_tune_clear()
+        assert mdgmi.mdgmi_tune_lookup(8, 256, mdgmi.MDGMI_TUNE_SHORT) is None
+        mdgmi.mdgmi_tune_load(q)
+        assert mdgmi.mdgmi_tune_lookup(8, 256, mdgmi.MDGMI_TUNE_SHORT) == short
+        assert mdgmi.mdgmi_tune_lookup(8, 256, mdgmi.MDGMI_TUNE_BULK) == bulk
+        bad = tmp_path / "bad.json"
+        bad.write_text(_tune_json([(3, 256, 0, 1 << 20, 1, -1, 1.0, 0.0)]))
+        with pytest.raises(mdgmi.MdgmiError):
+            mdgmi.mdgmi_tune_load(bad)
+    finally:
+        mdgmi.mdgmi_tune_clear()

@@ -109,6 +109,11 @@ def test_autotuner_table_roundtrip(tmp_path):
     e = mdgmi.mdgmi_autotune(8, 256, force=True)
     assert e["dim"] == 8 and e["M"] == 256 and e["direct_rate"] > 0 and e["mfma_rate"] > 0
     assert e["path"] in (mdgmi.MDGMI_PATH_F32_DIRECT, mdgmi.MDGMI_PATH_F32_MFMA_F16SPLIT)
+    # bulk timing on at least 2^20 samples, the short regime on 2^15
+    assert e["regime"] == mdgmi.MDGMI_TUNE_BULK and e["samples"] >= 1 << 20
+    s = e["short"]
+    assert s["regime"] == mdgmi.MDGMI_TUNE_SHORT and s["samples"] == 1 << 15 and s["direct_rate"] > 0
+    assert mdgmi.mdgmi_tune_lookup(8, 256, mdgmi.MDGMI_TUNE_SHORT) == s
     e2 = mdgmi.mdgmi_autotune(2, 16, force=True)
     # small formats time the MFMA shapes too (the per-sample 4x4 shape among them)
     assert e2["path"] in (mdgmi.MDGMI_PATH_F32_DIRECT, mdgmi.MDGMI_PATH_F32_MFMA_F16SPLIT)
@@ -133,3 +138,29 @@ def test_batch_rejects_bad_instances(mixed):
     with pytest.raises(mdgmi.MdgmiError) as e:     # M = 2 cannot take the MFMA batch path
         mdgmi.mdgmi_gmi_batched(mdgmi.instances([(gf, yd, td, s2)]), path="mfma")
     assert e.value.code == mdgmi.MDGMI_E_UNSUPPORTED
+
+
+def test_auto_path_follows_the_regime_of_the_call(tmp_path):
+    """A table whose bulk entry says "direct" and whose short entry says "the
+    fp16 split, variant 4": AUTO calls of fewer than 2^18 samples give
+    exactly the fp16-split result, larger ones exactly the direct result."""
+    f = w.random_shells(8, 256, seed=3)
+    gf = mdgmi.Format.of(f)
+    p = tmp_path / "regimes.json"
+    rows = [f'  {{"dim": 8, "M": {f.M}, "regime": 0, "samples": 1048576, "path": 1, "variant": -1, '
+            f'"direct_rate": 2.000000e+12, "mfma_rate": 1.000000e+12}}',
+            f'  {{"dim": 8, "M": {f.M}, "regime": 1, "samples": 32768, "path": 2, "variant": 4, '
+            f'"direct_rate": 1.000000e+12, "mfma_rate": 3.000000e+12}}']
+    p.write_text('{"arch": "gfx950", "entries": [\n' + ",\n".join(rows) + "\n]}\n")
+    mdgmi.mdgmi_tune_clear()
+    try:
+        mdgmi.mdgmi_tune_load(p)
+        s2 = float(w.sigma2_from_snr_db(10.0, 8))
+        for n, ref_path in ((5000, "mfma"), (300_000, "direct")):
+            say(f"[tune] AUTO at n={n}: expect the {ref_path} path")
+            y, tx = mdgmi.mdgmi_generate(gf, 21, [s2], n, dtype=torch.float32)
+            a = mdgmi.mdgmi_gmi(gf, y, tx, [s2], path="auto").cpu().numpy()
+            b = mdgmi.mdgmi_gmi(gf, y, tx, [s2], path=ref_path).cpu().numpy()
+            np.testing.assert_array_equal(a, b)
+    finally:
+        mdgmi.mdgmi_tune_clear()
