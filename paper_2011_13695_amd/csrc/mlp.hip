@@ -53,13 +53,19 @@ namespace {
 
 using namespace mlp;
 
-constexpr int64_t kKSplit = 1024;  // samples per split-K slice of the weight gradients
-constexpr int64_t kColChunk = 128; // samples per partial column sum of the bias gradients
+constexpr int64_t kKSplit = 256;  // samples per split-K slice of the weight gradients (at least)
+constexpr int64_t kMaxSplits = 64;
 
 int64_t al(int64_t v) { return (v + 255) / 256 * 256; }
 
 // chunk length of the bias-gradient column sums (at most 65535 chunks: grid.y)
-int64_t colsum_chunk(int64_t n) { return std::max<int64_t>(kColChunk, (n + 65534) / 65535); }
+// Samples per split-K slice of the weight gradients: kKSplit, or more so
+// that there are at most kMaxSplits slices (a multiple of the GEMM's K step).
+int64_t split_len(int64_t n) {
+    const int64_t s = std::max<int64_t>(kKSplit, (n + kMaxSplits - 1) / kMaxSplits);
+    return (s + mlp::kKStep - 1) / mlp::kKStep * mlp::kKStep;
+}
+
 
 // ---- elementwise kernels ----
 __global__ void k_to_bf16(const float* __restrict__ x, int64_t cnt, __bf16* __restrict__ out) {
@@ -116,26 +122,21 @@ __global__ void k_reduce_splits(const float* __restrict__ partial, int splits, i
     grad[i] = s;
 }
 
-// db[o] = sum_s D[s][o] in a fixed order: chunk c of colsum_chunk(n) samples is
-// summed by thread (c, o) into part[c][o], then the chunk sums are added in
-// chunk order.
-__global__ void k_colsum_part(const __bf16* __restrict__ D, int64_t n, int out, int64_t chunk,
-                              float* __restrict__ part) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= out) return;
-    const int64_t r0 = (int64_t)blockIdx.y * chunk;
-    const int64_t r1 = r0 + chunk < n ? r0 + chunk : n;
+// db[o] = sum_s D^T[o][s] in a fixed order: thread t of block o adds
+// samples t, t + 256, ... in turn, then a fixed tree over the 256 threads.
+__global__ __launch_bounds__(256) void k_rowsum(const __bf16* __restrict__ Dt, int64_t n, float* __restrict__ db) {
+    __shared__ float red[256];
+    const int64_t o = blockIdx.x;
+    const __bf16* row = Dt + o * n;
     float s = 0.0f;
-    for (int64_t i = r0; i < r1; i++) s += (float)D[i * out + o];
-    part[(int64_t)blockIdx.y * out + o] = s;
-}
-
-__global__ void k_colsum_final(const float* __restrict__ part, int64_t nchunks, int out, float* __restrict__ db) {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= out) return;
-    float s = 0.0f;
-    for (int64_t c = 0; c < nchunks; c++) s += part[c * out + o];
-    db[o] = s;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += (float)row[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[o] = red[0];
 }
 
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
@@ -148,6 +149,47 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
     m[i] = mi;
     v[i] = vi;
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// dst [cols][rows] = src [rows][cols] (bf16), through 64 x 64 LDS tiles:
+// coalesced reads along cols, coalesced writes along rows. blockIdx.z
+// selects one of two matrices with the same row count (one launch for both
+// operands of a weight gradient).
+struct TransposeArgs {
+    const __bf16* src[2];
+    __bf16* dst[2];
+    int cols[2];
+};
+
+__global__ __launch_bounds__(256) void k_transpose_bf16(TransposeArgs a, int64_t rows) {
+    __shared__ __bf16 tile[64][66];
+    const __bf16* __restrict__ src = a.src[blockIdx.z];
+    __bf16* __restrict__ dst = a.dst[blockIdx.z];
+    const int cols = a.cols[blockIdx.z];
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int c0 = blockIdx.y * 64;
+    if (c0 >= cols) return;  // the narrower matrix has fewer column tiles
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4 threads
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t r = r0 + i;
+        const int c = c0 + tx;
+        tile[i][tx] = (r < rows && c < cols) ? src[r * cols + c] : (__bf16)0.0f;
+    }
+    __syncthreads();
+    for (int i = ty; i < 64; i += 4) {
+        const int c = c0 + i;
+        const int64_t r = r0 + tx;
+        if (c < cols && r < rows) dst[(int64_t)c * rows + r] = tile[tx][i];
+    }
+}
+
+// src0 [rows][cols0] -> dst0 [cols0][rows] and src1 [rows][cols1] -> dst1 [cols1][rows]
+hipError_t transpose2_bf16(const __bf16* src0, int cols0, __bf16* dst0, const __bf16* src1, int cols1, __bf16* dst1,
+                           int64_t rows, hipStream_t st) {
+    TransposeArgs a{{src0, src1}, {dst0, dst1}, {cols0, cols1}};
+    const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((std::max(cols0, cols1) + 63) / 64), 2);
+    hipLaunchKernelGGL(k_transpose_bf16, grid, dim3(256), 0, st, a, rows);
+    return hipGetLastError();
 }
 
 // bf16 copies W [out][in] and W^T [in][out] of one layer
@@ -184,7 +226,7 @@ GemmArgs gargs() {
 
 // Workspace layout for n samples.
 struct MlpWs {
-    int64_t x0, z[MDGMI_MLP_MAX_LAYERS], h[MDGMI_MLP_MAX_LAYERS], logits, d0, d1, part, cpart, lpart, total;
+    int64_t x0, z[MDGMI_MLP_MAX_LAYERS], h[MDGMI_MLP_MAX_LAYERS], logits, d0, d1, dt, ht, part, lpart, total;
 };
 
 MlpWs mlp_ws(const mdgmi_mlp* net, int64_t n) {
@@ -203,11 +245,16 @@ MlpWs mlp_ws(const mdgmi_mlp* net, int64_t n) {
     o += al(n * net->width * 2);
     w.d1 = o;
     o += al(n * net->width * 2);
-    const int64_t splits = (n + kKSplit - 1) / kKSplit;
+    // transposed copies [features][n] of D and of the layer input for the
+    // weight gradients (the sample axis is their K axis)
+    const int64_t widest = std::max<int64_t>(net->width, net->sizes[0]);
+    w.dt = o;
+    o += al(n * widest * 2);
+    w.ht = o;
+    o += al(n * widest * 2);
+    const int64_t splits = (n + split_len(n) - 1) / split_len(n);
     w.part = o;
     o += al(splits * (int64_t)net->width * net->width * 4);
-    w.cpart = o;
-    o += al((n + colsum_chunk(n) - 1) / colsum_chunk(n) * (int64_t)net->width * 4);
     w.lpart = o;
     o += al(1024 * 8);
     w.total = o;
@@ -413,32 +460,35 @@ int mdgmi_mlp_loss_grad(mdgmi_mlp* net, const float* x, const float* target_llr,
     hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(64), 0, st, (const double*)(base + w.lpart), nb, n, loss);
     __bf16* D = (__bf16*)(base + w.d0);
     __bf16* Dn = (__bf16*)(base + w.d1);
-    const int splits = (int)((n + kKSplit - 1) / kKSplit);
+    const int64_t slen = split_len(n);
+    const int splits = (int)((n + slen - 1) / slen);
     for (int l = L - 1; l >= 0; l--) {
         const int in = net->sizes[l], out = net->sizes[l + 1];
         const __bf16* Hprev = l > 0 ? (const __bf16*)(base + w.h[l - 1]) : (const __bf16*)(base + w.x0);
-        // dW_l [out][in] = sum_s D[s][o] Hprev[s][i]  (split over samples)
+        // dW_l [out][in] = sum_s D[s][o] Hprev[s][i]  (split over samples),
+        // on copies with the sample axis contiguous: D^T [out][n], Hprev^T [in][n]
+        __bf16* Dt = (__bf16*)(base + w.dt);
+        __bf16* Ht = (__bf16*)(base + w.ht);
+        if (transpose2_bf16(D, out, Dt, Hprev, in, Ht, n, st) != hipSuccess) return MDGMI_E_HIP;
         GemmArgs g = gargs();
-        g.A = D;
-        g.a_sm = 1;
-        g.a_sk = out;
-        g.B = Hprev;
-        g.b_sk = in;
-        g.b_sn = 1;
+        g.A = Dt;
+        g.a_sm = n;
+        g.a_sk = 1;
+        g.B = Ht;
+        g.b_sk = 1;
+        g.b_sn = n;
         g.M = out;
         g.N = in;
         g.K = n;
-        g.k_per_split = kKSplit;
+        g.k_per_split = slen;
         g.C = (float*)(base + w.part);
-        if (gemm<kEpiPartial>(g, false, false, splits, st) != hipSuccess) return MDGMI_E_HIP;
+        if (gemm<kEpiPartial>(g, true, true, splits, st) != hipSuccess) return MDGMI_E_HIP;
         const int64_t cnt = (int64_t)out * in;
         hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
                            (const float*)(base + w.part), splits, cnt, net->d_grad + net->woff[l]);
-        const int64_t cc = colsum_chunk(n), nchunks = (n + cc - 1) / cc;
-        hipLaunchKernelGGL(k_colsum_part, dim3((out + 63) / 64, (unsigned)nchunks), dim3(64), 0, st, D, n, out, cc,
-                           (float*)(base + w.cpart));
-        hipLaunchKernelGGL(k_colsum_final, dim3((out + 63) / 64), dim3(64), 0, st, (const float*)(base + w.cpart),
-                           nchunks, out, net->d_grad + net->boff[l]);
+        // db_l [out] = sum_s D[s][o], from the same transposed copy
+        hipLaunchKernelGGL(k_rowsum, dim3((unsigned)out), dim3(256), 0, st, (const __bf16*)Dt, n,
+                           net->d_grad + net->boff[l]);
         if (l > 0) {
             // D_prev [n][in] = (D [n][out] W_l [out][in]) * gelu'(Z_{l-1})
             GemmArgs h = gargs();
