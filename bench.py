@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--path", default="mfma", choices=["mfma", "mfma_bf16", "direct", "f64", "auto"])
     ap.add_argument("--n", type=int, default=10_000_000, help="samples per SNR point")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=18.0, help="target length of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-direct", action="store_true", help="skip timing the FP32 direct path beside")
     ap.add_argument("--learned-samples", type=float, default=2e8,
