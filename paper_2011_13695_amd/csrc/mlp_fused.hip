@@ -80,51 +80,73 @@ __global__ void k_fused_weights(const float* __restrict__ W, int out, int in, in
     ((uint4*)dst)[g] = p.u;
 }
 
+// Output tiles [OT0, OT0 + G) of one hidden layer: K-major MFMA chains (G
+// independent accumulators, weights from LDS in the fused layout), then
+// gelu(W h + b) of those tiles into act_out, one tile's GELUs at a time.
+template <int OT0, int G>
+__device__ __forceinline__ void tile_run(const uint4* __restrict__ Wl, const float* __restrict__ bias,
+                                         const bf16x8 (&act_in)[kTiles][2], bf16x8 (&act_out)[kTiles][2], int lane) {
+    const int h = lane >> 5;
+    f32x16 acc[G];
+#pragma unroll
+    for (int j = 0; j < G; j++) acc[j] = bias_acc(bias, OT0 + j, h);
+#pragma unroll
+    for (int kb = 0; kb < kKB; kb++) {
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            P8 a;
+            a.u = Wl[((OT0 + j) * kKB + kb) * 64 + lane];
+            acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, act_in[kb >> 1][kb & 1], acc[j], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int j = 0; j < G; j++) {
+        P8 o0, o1;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const __bf16 v = (__bf16)mlp::gelu_f(acc[j][r]);
+            if (r < 8)
+                o0.h[r] = v;
+            else
+                o1.h[r - 8] = v;
+        }
+        act_out[OT0 + j][0] = o0.v;
+        act_out[OT0 + j][1] = o1.v;
+        // one tile's GELUs at a time keeps their temporaries few
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // One hidden layer: in activations act_in [kTiles][2] (bf16x8 per lane),
 // weights in LDS (fused layout), out activations gelu(W h + b) into act_out.
-// Output tiles go in groups of kGroup: per group, K-major order with kGroup
-// independent accumulation chains, so the live set is kGroup x 16
-// accumulators, the resident input activations, one K-block of weight
-// operands and the output tiles done so far.
+// Output tiles go in runs of kGroup: per run, kGroup MFMA chains, then their
+// GELUs. With two waves per SIMD, odd waves shift their runs by one tile
+// (runs {0}, {1,2}, ..., {7}): the two waves of a SIMD then tend to be in
+// opposite phases, one wave's GELUs on the vector ALU while the other's
+// MFMAs run on the matrix core, rather than both in the same phase after
+// the block's barrier.
 template <int kGroup>
 __device__ __forceinline__ void hidden_layer(const uint4* __restrict__ Wl, const float* __restrict__ bias,
                                              const bf16x8 (&act_in)[kTiles][2], bf16x8 (&act_out)[kTiles][2],
-                                             int lane) {
-    const int h = lane >> 5;
-    constexpr int kHalf = kGroup;
-#pragma unroll
-    for (int half = 0; half < kTiles / kGroup; half++) {
-        f32x16 acc[kHalf];
-#pragma unroll
-        for (int j = 0; j < kHalf; j++) acc[j] = bias_acc(bias, half * kHalf + j, h);
-#pragma unroll
-        for (int kb = 0; kb < kKB; kb++) {
-#pragma unroll
-            for (int j = 0; j < kHalf; j++) {
-                const int ot = half * kHalf + j;
-                P8 a;
-                a.u = Wl[(ot * kKB + kb) * 64 + lane];
-                acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, act_in[kb >> 1][kb & 1], acc[j], 0, 0, 0);
-            }
-            __builtin_amdgcn_sched_barrier(0);
+                                             int lane, bool shifted) {
+    if constexpr (kGroup == 2) {
+        if (shifted) {
+            tile_run<0, 1>(Wl, bias, act_in, act_out, lane);
+            tile_run<1, 2>(Wl, bias, act_in, act_out, lane);
+            tile_run<3, 2>(Wl, bias, act_in, act_out, lane);
+            tile_run<5, 2>(Wl, bias, act_in, act_out, lane);
+            tile_run<7, 1>(Wl, bias, act_in, act_out, lane);
+        } else {
+            tile_run<0, 2>(Wl, bias, act_in, act_out, lane);
+            tile_run<2, 2>(Wl, bias, act_in, act_out, lane);
+            tile_run<4, 2>(Wl, bias, act_in, act_out, lane);
+            tile_run<6, 2>(Wl, bias, act_in, act_out, lane);
         }
-#pragma unroll
-        for (int j = 0; j < kHalf; j++) {
-            const int ot = half * kHalf + j;
-            P8 o0, o1;
-#pragma unroll
-            for (int r = 0; r < 16; r++) {
-                const __bf16 v = (__bf16)mlp::gelu_f(acc[j][r]);
-                if (r < 8)
-                    o0.h[r] = v;
-                else
-                    o1.h[r - 8] = v;
-            }
-            act_out[ot][0] = o0.v;
-            act_out[ot][1] = o1.v;
-            // one tile's GELUs at a time keeps their temporaries few
-            __builtin_amdgcn_sched_barrier(0);
-        }
+    } else {
+        static_assert(kGroup == 4, "runs of 2 or 4 tiles");
+        tile_run<0, 4>(Wl, bias, act_in, act_out, lane);
+        tile_run<4, 4>(Wl, bias, act_in, act_out, lane);
     }
 }
 
@@ -207,13 +229,13 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp_fused(
 #pragma unroll 4
         for (int k = threadIdx.x; k < kWHU; k += kThreads) sWH[k] = w2f[k];
         __syncthreads();
-        hidden_layer<kWaves == 4 ? 4 : 2>(sWH, sB + kH, actA, actB, lane);
+        hidden_layer<kWaves == 4 ? 4 : 2>(sWH, sB + kH, actA, actB, lane, (wave & 1) != 0);
         __syncthreads();
         // ---- layer 3
 #pragma unroll 4
         for (int k = threadIdx.x; k < kWHU; k += kThreads) sWH[k] = w3f[k];
         __syncthreads();
-        hidden_layer<kWaves == 4 ? 4 : 2>(sWH, sB + 2 * kH, actB, actA, lane);
+        hidden_layer<kWaves == 4 ? 4 : 2>(sWH, sB + 2 * kH, actB, actA, lane, (wave & 1) != 0);
         // ---- layer 4: logits, one output tile of 32 rows
         f32x16 zo = bias_acc(sB + 3 * kH, 0, h);
 #pragma unroll
