@@ -170,3 +170,7 @@ def test_tune_table_regimes_json_host_only(tmp_path):
             mdgmi.mdgmi_tune_load(bad)
     finally:
         mdgmi.mdgmi_tune_clear()
+
+
+def test_probe_rejects_null_output():
+    assert mdgmi.lib().mdgmi_probe_rates(None) == mdgmi.MDGMI_E_NULL

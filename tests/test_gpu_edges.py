@@ -201,3 +201,15 @@ def test_auto_takes_the_bf16_split_beyond_the_fp16_range(orc):
         ref = orc.gmi(y.astype(np.float32).astype(np.float64), tx, f.X, f.labels, s2)
         assert np.max(np.abs(auto[0, :2] - ref[:2])) <= 1e-4
         say(f"[edge] AUTO at {snr} dB -> {expect}: GMI {auto[0, 0]:.6f}")
+
+
+def test_peak_probe_rates_are_plausible():
+    """mdgmi_probe_rates: the exponential, FMA and bf16 MFMA rates it measures
+    on this device are positive and ordered as the hardware is built (a plain
+    FMA issues at least as fast as v_exp_f32) and no larger than the chip's
+    nominal figures allow (256 CUs at 2.4 GHz with some clock margin)."""
+    r = mdgmi.mdgmi_probe_rates()
+    say(f"[probe] {r}")
+    assert 1e12 < r["exp_per_s"] <= 1.1 * 256 * 32 * 2.4e9
+    assert r["exp_per_s"] <= r["fma_lane_ops_per_s"] <= 1.1 * 256 * 64 * 2.4e9
+    assert 1e14 < r["mfma_bf16_flops_per_s"] <= 1.1 * 2.5e15
