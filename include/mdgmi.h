@@ -312,11 +312,14 @@ double mdgmi_q_factor_db(double ber);
  * per-block FP64 partials and the per-SNR operand images) taken from a
  * static device array of MDGMI_STATIC_SCRATCH_BYTES that the library holds
  * on every device it runs on until the process ends. It calls no allocator.
- *  - MDGMI_E_WORKSPACE if the call needs more scratch than the array holds,
- *    i.e. mdgmi_gmi_workspace_size(fmt, n, n_snr, path) exceeds
- *    MDGMI_STATIC_SCRATCH_BYTES (16 MiB covers 32 SNR points per launch of
- *    any format on every path; very many SNR points in one call may not
- *    fit); nothing is launched then.
+ *  - MDGMI_E_WORKSPACE if the call's plan (the resolved path's partial sums
+ *    and operand images, at most mdgmi_gmi_workspace_size(fmt, n, n_snr,
+ *    path)) needs more than MDGMI_STATIC_SCRATCH_BYTES; nothing is launched
+ *    then. 16 MiB holds the images of up to 32 SNR points (the most one
+ *    launch takes) of every format on every path, except 32 points of an
+ *    8-D M = 4096 format on the bf16 split (512 KiB each), which holds 31;
+ *    the partial sums add 5 doubles per block and SNR point of the call,
+ *    so calls with very many SNR points may not fit.
  *  - Every call on one device uses the same array, which keeps the last
  *    call's contents: calls that overlap on a device (other streams or host
  *    threads) race and must be ordered by the caller. No part of the array

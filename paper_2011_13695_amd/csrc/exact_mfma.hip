@@ -114,9 +114,11 @@ LaunchCfg mfma_cfg(const mdgmi_format* f, int64_t n, int n_snr, int mode, int sp
 }
 
 int64_t mfma_blocks_bound(const mdgmi_format* f, int64_t n, int n_snr, int mode, int split) {
-    // per shape, the blocks of a call over k of the n_snr points, k = 1..n_snr
+    // per shape, the blocks of a call over k of the n_snr points: the blocks
+    // per point depend on k only up to kMaxSnrPerLaunch points per launch,
+    // beyond which k times them grows with k, so k = 1..32 and k = n_snr
     int64_t b = (int64_t)n_snr * mfma_cfg(f, n, n_snr, mode, split).blocks_per_snr;
-    for (int k = 1; k <= n_snr; k++) {
+    for (int k = 1; k <= n_snr; k = (k < kMaxSnrPerLaunch || k == n_snr) ? k + 1 : n_snr) {
         if (split == kSplitF16 && small_shape_fits(f))
             b = std::max<int64_t>(b, (int64_t)k * small_cfg(f, n, k).blocks_per_snr);
         for (int v = -1; v < kNumVariants; v++)
