@@ -11,10 +11,16 @@
 // k_fused_weights): for a K-block of 16 inputs, lane half h holds inputs
 // {4h..4h+3, 8+4h..8+4h+3}. Activations never leave registers.
 //
+// GELU: the hidden layers' accumulators hold s = x / 4 (the weights of the
+// first layer and the hidden biases are scaled by 1/4, the output layer's
+// weights by 4, all exact powers of two), and they become GELU(4 s) / 4 in
+// packed fp16 arithmetic without transcendentals (gelu_quarter8 below). In
+// the hidden layers each output tile's GELUs run interleaved with the next
+// tile's MFMA chain.
+//
 // LDS: W_1 (8 KiB), W_4 (16 KiB) and all biases stay resident; W_2 and W_3
 // (128 KiB each) are staged in turn into one buffer, once per block of
-// 32 samples per wave (8 waves by default: two per SIMD, so one wave's
-// GELUs overlap the other's MFMAs). In GMI mode the logits are turned into
+// 32 samples per wave (8 waves by default, two per SIMD). In GMI mode the logits are turned into
 // the per-sample GMI cost in the kernel and only FP64 block partials are
 // written; in LLR mode the logits are stored, [n][out] FP32.
 #include <algorithm>
@@ -62,11 +68,78 @@ __device__ __forceinline__ f32x16 bias_acc(const float* __restrict__ bias, int o
     return a;
 }
 
-// Fused-layout weights of one layer: [out tile][K-block][lane][8] bf16.
-// Layer 0 takes its inputs in natural order; later layers in the order the
-// previous MFMA output lands in registers.
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef _Float16 half8v __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ half8v splat8(float c) {
+    const _Float16 h = (_Float16)c;
+    return (half8v){h, h, h, h, h, h, h, h};
+}
+
+__device__ __forceinline__ half8v clamp01(half8v v) {
+    return __builtin_elementwise_min(__builtin_elementwise_max(v, splat8(0.0f)), splat8(1.0f));
+}
+
+// The gate of the tanh-form GELU, Phi(x) = sigmoid(2 sqrt(2/pi) (x + 0.044715 x^3)),
+// at x = 4 s is taken as clamp(1/2 + s P(v), 0, 1) with v = max(1 - s^2, 0)
+// and P(v) = sum_k kGateP[k] v^k. P(0) = 1/2 makes the gate exactly 1 for
+// x >= 4 and 0 for x <= -4 (the tanh form is within 2e-5 of those there).
+// The coefficients are a minimax fit of the gate on [0, 4] (odd symmetry
+// gives the rest), rounded to fp16 and then adjusted by a few fp16 ulps to
+// minimise the error of the fp16 evaluation below; that error is at most
+// 8e-4 on the gate and 2.1e-3 on GELU(x) - GELU_tanh(x) over all inputs.
+constexpr float kGateP[7] = {0.5f, 0.241455078125f, 0.3515625f, -0.87451171875f,
+                             2.96875f, -3.5546875f, 1.9609375f};
+
+// GELU(4 s) / 4 = s Phi(4 s) of eight accumulators, rounded to bf16: s to
+// fp16 (toward zero, v_cvt_pkrtz, two values per instruction), v, P and the
+// gate in packed fp16 FMAs (with the [0, 1] clamp of the instruction), the
+// product with the FP32 s in one v_fma_mix_f32 per value. 12 issue slots per
+// pair against 19 for the exp2 + reciprocal form. Eight values at a time
+// give four independent Horner chains: a chain of dependent packed FMAs
+// would need a wait state between its steps.
+__device__ __forceinline__ void gelu_quarter8(const float* z, bf16x8& out) {
+    half8v s;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const half2v t = __builtin_bit_cast(half2v, __builtin_amdgcn_cvt_pkrtz(z[2 * i], z[2 * i + 1]));
+        s[2 * i] = t.x;
+        s[2 * i + 1] = t.y;
+    }
+    const half8v v = clamp01(__builtin_elementwise_fma(-s, s, splat8(1.0f)));
+    half8v p = splat8(kGateP[6]);
+#pragma unroll
+    for (int k = 5; k >= 0; k--) p = __builtin_elementwise_fma(p, v, splat8(kGateP[k]));
+    const half8v phi = clamp01(__builtin_elementwise_fma(s, p, splat8(0.5f)));
+#pragma unroll
+    for (int i = 0; i < 8; i++)  // fma with +0, not a product, keeps the fp16 conversion inside v_fma_mix_f32
+        out[i] = (__bf16)__builtin_fmaf(z[i], (float)phi[i], 0.0f);
+}
+
+// Keeps a value's computation where it is written: without it the compiler
+// may sink a tile's GELUs towards their use in the next layer, out of the
+// MFMA chain they are meant to overlap.
+__device__ __forceinline__ void pin(bf16x8& v) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 u = __builtin_bit_cast(u32x4, v);
+    asm volatile("" : "+v"(u));
+    v = __builtin_bit_cast(bf16x8, u);
+}
+
+// Sixteen accumulators of one output tile -> two bf16x8 activations.
+__device__ __forceinline__ void gelu_tile(const f32x16& z, bf16x8& lo, bf16x8& hi) {
+    float a[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) a[r] = z[r];
+    gelu_quarter8(a, lo);
+    gelu_quarter8(a + 8, hi);
+}
+
+// Fused-layout weights of one layer: [out tile][K-block][lane][8] bf16,
+// times scale. Layer 0 takes its inputs in natural order; later layers in
+// the order the previous MFMA output lands in registers.
 __global__ void k_fused_weights(const float* __restrict__ W, int out, int in, int permute, int n_tiles, int n_kb,
-                                __bf16* __restrict__ dst) {
+                                float scale, __bf16* __restrict__ dst) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one per (tile, kb, lane)
     if (g >= (int64_t)n_tiles * n_kb * 64) return;
     const int lane = (int)(g % 64), kb = (int)((g / 64) % n_kb), t = (int)(g / (64 * n_kb));
@@ -75,79 +148,46 @@ __global__ void k_fused_weights(const float* __restrict__ W, int out, int in, in
 #pragma unroll
     for (int i = 0; i < 8; i++) {
         const int k = 16 * kb + (permute ? perm_in(h, i) : 8 * h + i);
-        p.h[i] = (row < out && k < in) ? (__bf16)W[(int64_t)row * in + k] : (__bf16)0.0f;
+        p.h[i] = (row < out && k < in) ? (__bf16)(W[(int64_t)row * in + k] * scale) : (__bf16)0.0f;
     }
     ((uint4*)dst)[g] = p.u;
 }
 
-// Output tiles [OT0, OT0 + G) of one hidden layer: K-major MFMA chains (G
-// independent accumulators, weights from LDS in the fused layout), then
-// gelu(W h + b) of those tiles into act_out, one tile's GELUs at a time.
-template <int OT0, int G>
-__device__ __forceinline__ void tile_run(const uint4* __restrict__ Wl, const float* __restrict__ bias,
-                                         const bf16x8 (&act_in)[kTiles][2], bf16x8 (&act_out)[kTiles][2], int lane) {
-    const int h = lane >> 5;
-    f32x16 acc[G];
-#pragma unroll
-    for (int j = 0; j < G; j++) acc[j] = bias_acc(bias, OT0 + j, h);
-#pragma unroll
-    for (int kb = 0; kb < kKB; kb++) {
-#pragma unroll
-        for (int j = 0; j < G; j++) {
-            P8 a;
-            a.u = Wl[((OT0 + j) * kKB + kb) * 64 + lane];
-            acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, act_in[kb >> 1][kb & 1], acc[j], 0, 0, 0);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int j = 0; j < G; j++) {
-        P8 o0, o1;
-#pragma unroll
-        for (int r = 0; r < 16; r++) {
-            const __bf16 v = (__bf16)mlp::gelu_f(acc[j][r]);
-            if (r < 8)
-                o0.h[r] = v;
-            else
-                o1.h[r - 8] = v;
-        }
-        act_out[OT0 + j][0] = o0.v;
-        act_out[OT0 + j][1] = o1.v;
-        // one tile's GELUs at a time keeps their temporaries few
-        __builtin_amdgcn_sched_barrier(0);
-    }
-}
-
 // One hidden layer: in activations act_in [kTiles][2] (bf16x8 per lane),
 // weights in LDS (fused layout), out activations gelu(W h + b) into act_out.
-// Output tiles go in runs of kGroup: per run, kGroup MFMA chains, then their
-// GELUs. With two waves per SIMD, odd waves shift their runs by one tile
-// (runs {0}, {1,2}, ..., {7}): the two waves of a SIMD then tend to be in
-// opposite phases, one wave's GELUs on the vector ALU while the other's
-// MFMAs run on the matrix core, rather than both in the same phase after
-// the block's barrier.
-template <int kGroup>
+// Software-pipelined over the output tiles: the MFMA chain of tile t (16
+// K-blocks, weights read from LDS) is interleaved with the GELUs of tile
+// t - 1, so that within each wave the vector ALU works while the matrix
+// core runs (each MFMA of the chain is followed by about six of the GELUs'
+// vector instructions: 96 per tile against 16 MFMAs).
 __device__ __forceinline__ void hidden_layer(const uint4* __restrict__ Wl, const float* __restrict__ bias,
                                              const bf16x8 (&act_in)[kTiles][2], bf16x8 (&act_out)[kTiles][2],
-                                             int lane, bool shifted) {
-    if constexpr (kGroup == 2) {
-        if (shifted) {
-            tile_run<0, 1>(Wl, bias, act_in, act_out, lane);
-            tile_run<1, 2>(Wl, bias, act_in, act_out, lane);
-            tile_run<3, 2>(Wl, bias, act_in, act_out, lane);
-            tile_run<5, 2>(Wl, bias, act_in, act_out, lane);
-            tile_run<7, 1>(Wl, bias, act_in, act_out, lane);
-        } else {
-            tile_run<0, 2>(Wl, bias, act_in, act_out, lane);
-            tile_run<2, 2>(Wl, bias, act_in, act_out, lane);
-            tile_run<4, 2>(Wl, bias, act_in, act_out, lane);
-            tile_run<6, 2>(Wl, bias, act_in, act_out, lane);
+                                             int lane) {
+    const int h = lane >> 5;
+    f32x16 prev;
+#pragma unroll
+    for (int t = 0; t < kTiles; t++) {
+        f32x16 acc = bias_acc(bias, t, h);
+#pragma unroll
+        for (int kb = 0; kb < kKB; kb++) {
+            P8 a;
+            a.u = Wl[(t * kKB + kb) * 64 + lane];
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, act_in[kb >> 1][kb & 1], acc, 0, 0, 0);
         }
-    } else {
-        static_assert(kGroup == 4, "runs of 2 or 4 tiles");
-        tile_run<0, 4>(Wl, bias, act_in, act_out, lane);
-        tile_run<4, 4>(Wl, bias, act_in, act_out, lane);
+        if (t > 0) {
+            gelu_tile(prev, act_out[t - 1][0], act_out[t - 1][1]);
+#pragma unroll
+            for (int kb = 0; kb < kKB; kb++) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+                __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // six vector ALU instructions
+            }
+            pin(act_out[t - 1][0]);
+            pin(act_out[t - 1][1]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        prev = acc;
     }
+    gelu_tile(prev, act_out[kTiles - 1][0], act_out[kTiles - 1][1]);
 }
 
 // LLR: store the logits (llr [n][out_dim]); else the GMI cost into part.
@@ -169,13 +209,13 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp_fused(
     for (int k = threadIdx.x; k < kW1U; k += kThreads) sW1[k] = w1f[k];
     for (int k = threadIdx.x; k < kW4U; k += kThreads) sW4[k] = w4f[k];
     for (int k = threadIdx.x; k < kBiasF; k += kThreads) {
-        float v;
+        float v;  // hidden biases / 4: their accumulators hold x / 4
         if (k < kH)
-            v = b1[k];
+            v = 0.25f * b1[k];
         else if (k < 2 * kH)
-            v = b2[k - kH];
+            v = 0.25f * b2[k - kH];
         else if (k < 3 * kH)
-            v = b3[k - 2 * kH];
+            v = 0.25f * b3[k - 2 * kH];
         else
             v = (k - 3 * kH) < out_dim ? b4[k - 3 * kH] : 0.0f;
         sB[k] = v;
@@ -211,31 +251,21 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp_fused(
         for (int ot = 0; ot < kTiles; ot++) {
             P8 a;
             a.u = sW1[ot * 64 + lane];
-            f32x16 z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, xin, bias_acc(sB, ot, h), 0, 0, 0);
-            P8 o0, o1;
-#pragma unroll
-            for (int r = 0; r < 16; r++) {
-                const __bf16 v = (__bf16)mlp::gelu_f(z[r]);
-                if (r < 8)
-                    o0.h[r] = v;
-                else
-                    o1.h[r - 8] = v;
-            }
-            actA[ot][0] = o0.v;
-            actA[ot][1] = o1.v;
+            const f32x16 z = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, xin, bias_acc(sB, ot, h), 0, 0, 0);
+            gelu_tile(z, actA[ot][0], actA[ot][1]);
             __builtin_amdgcn_sched_barrier(0);
         }
         // ---- layer 2
 #pragma unroll 4
         for (int k = threadIdx.x; k < kWHU; k += kThreads) sWH[k] = w2f[k];
         __syncthreads();
-        hidden_layer<kWaves == 4 ? 4 : 2>(sWH, sB + kH, actA, actB, lane, (wave & 1) != 0);
+        hidden_layer(sWH, sB + kH, actA, actB, lane);
         __syncthreads();
         // ---- layer 3
 #pragma unroll 4
         for (int k = threadIdx.x; k < kWHU; k += kThreads) sWH[k] = w3f[k];
         __syncthreads();
-        hidden_layer<kWaves == 4 ? 4 : 2>(sWH, sB + 2 * kH, actB, actA, lane, (wave & 1) != 0);
+        hidden_layer(sWH, sB + 2 * kH, actB, actA, lane);
         // ---- layer 4: logits, one output tile of 32 rows
         f32x16 zo = bias_acc(sB + 3 * kH, 0, h);
 #pragma unroll
@@ -296,14 +326,16 @@ hipError_t build_fused_weights(const float* W, int out, int in, int layer, __bf1
     using namespace fused;
     const int n_tiles = (out + 31) / 32, n_kb = (in + 15) / 16;
     const int64_t cnt = (int64_t)n_tiles * n_kb * 64;
+    // layer 0 -> x / 4 in the first accumulators; the output layer reads GELU / 4
+    const float scale = layer == 0 ? 0.25f : layer == 3 ? 4.0f : 1.0f;
     hipLaunchKernelGGL(k_fused_weights, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, W, out, in,
-                       layer == 0 ? 0 : 1, n_tiles, n_kb, dst);
+                       layer == 0 ? 0 : 1, n_tiles, n_kb, scale, dst);
     return hipGetLastError();
 }
 
 int fused_grid() { return device_cu_count(); }
 
-int g_fused_waves = 8;  // 8: two waves per SIMD (256 VGPRs, output tiles in pairs); 4: one, whole register file
+int g_fused_waves = 8;  // 8: two waves per SIMD (256 VGPRs each); 4: one, whole register file
 
 template <int W, bool LLR>
 hipError_t launch_fused_w(__bf16* const* wf, const float* const* bias, int in_dim, int out_dim, const float* y, int dim,
