@@ -508,15 +508,19 @@ int mdgmi_mlp_load(mdgmi_mlp* net, const char* path);
 
 /* Measured peaks of the current device, behind the roofline figures (the
  * demapper is bound by the exponential issue rate of the vector ALU, the
- * learned demapper by the matrix cores): out_host [5] receives
+ * learned demapper by the vector ALU beside the matrix cores): out_host [8]
+ * receives
  *   [0] v_exp_f32 results per second over the whole device,
  *   [1] the core clock during that probe (Hz, s_memtime cycles against the
  *       constant reference clock),
  *   [2] FP32 FMA lane-operations per second, [3] the clock during it,
- *   [4] v_mfma_f32_32x32x16_bf16 flops per second.
- * Each probe runs 8 waves per SIMD of independent dependency chains; it
- * allocates and frees a few bytes of device memory and synchronises the
- * device (a measurement call, not for hot loops). */
+ *   [4] v_mfma_f32_32x32x16_bf16 flops per second,
+ *   [5], [6], [7] the same MFMA flops per second at two waves per SIMD when
+ *       each MFMA is followed by 0, 4 and 8 independent FP32 FMAs of its
+ *       wave (how much vector work issues while the matrix core runs).
+ * Probes [0]-[4] run 8 waves per SIMD of independent dependency chains; the
+ * call allocates and frees a few bytes of device memory and synchronises
+ * the device (a measurement call, not for hot loops). */
 int mdgmi_probe_rates(double* out_host);
 
 /* Launch-shape override of the MFMA path for tuning sweeps: variant v in

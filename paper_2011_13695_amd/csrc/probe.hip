@@ -69,6 +69,37 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_mfma(int iters, float* 
     if (s == 12345.0f) sink[threadIdx.x] = s;
 }
 
+// Co-issue: two independent chains of v_mfma_f32_32x32x16_bf16 per wave,
+// each MFMA followed by K independent FP32 FMAs (8 chains) of the same
+// wave, two waves per SIMD (the fused MLP kernel's shape). The MFMA rate
+// with K > 0 against K = 0 shows how many vector instructions issue while
+// the matrix core runs.
+template <int K>
+__global__ __launch_bounds__(kProbeThreads) void k_probe_mix(int iters, float* __restrict__ sink) {
+    pbf16x8 a, b;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        a[i] = (__bf16)(1e-3f * (float)(threadIdx.x + i));
+        b[i] = (__bf16)(1e-3f * (float)(i + 1));
+    }
+    pf32x16 acc[2] = {};
+    float v[kProbeChains];
+#pragma unroll
+    for (int c = 0; c < kProbeChains; c++) v[c] = 1e-6f * (float)(threadIdx.x + c + 1);
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int m = 0; m < 2; m++) {
+            acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[m], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < K; j++) v[j % kProbeChains] = fmaf(v[j % kProbeChains], 0.999999f, 1.0e-7f);
+        }
+    }
+    float s = acc[0][0] + acc[1][0];
+#pragma unroll
+    for (int c = 0; c < kProbeChains; c++) s += v[c];
+    if (s == 12345.0f) sink[threadIdx.x] = s;
+}
+
 }  // namespace
 }  // namespace mdgmi
 
@@ -89,15 +120,23 @@ extern "C" int mdgmi_probe_rates(double* out_host) {
         hipEventCreate(&e1) != hipSuccess)
         return MDGMI_E_HIP;
     int rc = MDGMI_OK;
+    const int mix_blocks = device_cu_count() * 2;  // 2 waves per SIMD
     auto run = [&](int op, int iters, double ops_per_lane_iter, double* rate, double* hz) {
+        const int nb = op >= 3 ? mix_blocks : blocks;
         for (int rep = 0; rep < 2; rep++) {  // the first launch warms up
             (void)hipEventRecord(e0, nullptr);
             if (op == 0)
-                hipLaunchKernelGGL(k_probe<0>, dim3(blocks), dim3(kProbeThreads), 0, nullptr, iters, 0.5f, sink, clk);
+                hipLaunchKernelGGL(k_probe<0>, dim3(nb), dim3(kProbeThreads), 0, nullptr, iters, 0.5f, sink, clk);
             else if (op == 1)
-                hipLaunchKernelGGL(k_probe<1>, dim3(blocks), dim3(kProbeThreads), 0, nullptr, iters, 0.5f, sink, clk);
+                hipLaunchKernelGGL(k_probe<1>, dim3(nb), dim3(kProbeThreads), 0, nullptr, iters, 0.5f, sink, clk);
+            else if (op == 2)
+                hipLaunchKernelGGL(k_probe_mfma, dim3(nb), dim3(kProbeThreads), 0, nullptr, iters, sink);
+            else if (op == 3)
+                hipLaunchKernelGGL(k_probe_mix<0>, dim3(nb), dim3(kProbeThreads), 0, nullptr, iters, sink);
+            else if (op == 4)
+                hipLaunchKernelGGL(k_probe_mix<4>, dim3(nb), dim3(kProbeThreads), 0, nullptr, iters, sink);
             else
-                hipLaunchKernelGGL(k_probe_mfma, dim3(blocks), dim3(kProbeThreads), 0, nullptr, iters, sink);
+                hipLaunchKernelGGL(k_probe_mix<8>, dim3(nb), dim3(kProbeThreads), 0, nullptr, iters, sink);
             (void)hipEventRecord(e1, nullptr);
         }
         float ms = 0.0f;
@@ -107,7 +146,7 @@ extern "C" int mdgmi_probe_rates(double* out_host) {
             rc = MDGMI_E_HIP;
             return;
         }
-        *rate = (double)blocks * kProbeThreads * iters * ops_per_lane_iter / (ms * 1e-3);
+        *rate = (double)nb * kProbeThreads * iters * ops_per_lane_iter / (ms * 1e-3);
         if (hz) *hz = c[1] > 0 ? (double)c[0] / ((double)c[1] / (wall_khz * 1e3)) : 0.0;
     };
     // exponentials and FMAs per lane and iteration; MFMA: 4 per wave and
@@ -115,6 +154,8 @@ extern "C" int mdgmi_probe_rates(double* out_host) {
     run(0, 4096, kProbeChains, &out_host[0], &out_host[1]);
     run(1, 16384, kProbeChains, &out_host[2], &out_host[3]);
     run(2, 2048, 4.0 * 2 * 32 * 32 * 16 / 64.0, &out_host[4], nullptr);
+    // MFMA flops per second at two waves per SIMD with 0, 4 and 8 FMAs per MFMA
+    for (int k = 0; k < 3; k++) run(3 + k, 8192, 2.0 * 2 * 32 * 32 * 16 / 64.0, &out_host[5 + k], nullptr);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(sink);

@@ -213,3 +213,6 @@ def test_peak_probe_rates_are_plausible():
     assert 1e12 < r["exp_per_s"] <= 1.1 * 256 * 32 * 2.4e9
     assert r["exp_per_s"] <= r["fma_lane_ops_per_s"] <= 1.1 * 256 * 64 * 2.4e9
     assert 1e14 < r["mfma_bf16_flops_per_s"] <= 1.1 * 2.5e15
+    # vector instructions beside the MFMAs can only slow the matrix core down
+    assert 1e14 < r["mfma_with_8_fma_flops_per_s"] <= 1.05 * r["mfma_with_4_fma_flops_per_s"]
+    assert r["mfma_with_4_fma_flops_per_s"] <= 1.05 * r["mfma_2waves_flops_per_s"] <= 1.1 * 2.5e15
