@@ -78,6 +78,32 @@ def test_mlp_llr_elementwise_against_oracle(orc, fmt8, n):
     assert mb.check(lam2, ref, mb.logits_sd(p, SIZES, x)) <= 1.0
 
 
+def test_mlp_llr_saturated_gelus_and_nan_rows(orc, fmt8):
+    """Inputs far outside the trained range drive most pre-activations past
+    |x| = 4, where the fused kernel's GELU gate is exactly 0 or 1: the LLRs
+    still follow the oracle within the error model; a NaN input row gives NaN
+    logits on that row only."""
+    f, gf = fmt8
+    net = mdgmi.MLP(SIZES, seed=33)
+    rng = np.random.default_rng(5)
+    n = 515
+    snr = rng.choice(np.arange(2.0, 17.25, 0.25), size=n)
+    y = (300.0 * rng.standard_normal((n, 8))).astype(np.float32)
+    y[7, 3] = np.nan
+    say("[learned] mdgmi_mlp_llr saturated inputs")
+    lam = net.llr(torch.from_numpy(y).cuda(), torch.from_numpy(snr.astype(np.float32)).cuda()).cpu().numpy()
+    assert np.all(np.isnan(lam[7])) and np.all(np.isfinite(np.delete(lam, 7, axis=0)))
+    p = net.params().astype(np.float64)
+    keep = np.arange(n) != 7
+    x = feats(y[keep], snr[keep])
+    ref = orc.mlp_forward(p, SIZES, x)
+    zs, _, _ = mb.forward_sd(p, SIZES, x)
+    assert np.mean(np.abs(zs[0]) >= 4.0) > 0.5           # most first-layer GELUs saturated
+    r = mb.check(lam[keep], ref, mb.logits_sd(p, SIZES, x))
+    say(f"[learned] saturated: max |d| / bar = {r:.3f}")
+    assert r <= 1.0
+
+
 def test_fused_gmi_is_the_gmi_of_its_llrs(orc, fmt8):
     """The fused GMI mode costs the same logits its LLR mode stores."""
     f, gf = fmt8
