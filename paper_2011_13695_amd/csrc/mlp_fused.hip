@@ -25,6 +25,7 @@
 // written; in LLR mode the logits are stored, [n][out] FP32.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "device_common.h"
 #include "mlp_gemm.h"
@@ -285,24 +286,33 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp_fused(
             }
             continue;
         }
-        // ---- per-sample GMI cost of the logits (bits), both lane halves.
-        // Rows >= out_dim have zero weights and bias, so their logit is
-        // exactly 0 and their cost exactly softplus2(0); every row is costed
-        // and those are taken off in FP64 (no per-row masks to keep live).
+        // ---- per-sample GMI cost of the logits (bits), both lane halves:
+        // the sum over rows of max(x, 0) + log2(1 + 2^-|x|), the second part
+        // as one logarithm of the product of its factors (each in (1, 2]).
+        // Rows >= out_dim have zero weights and bias: their logit is exactly
+        // 0, their factor exactly 2 and their cost exactly one bit, taken off
+        // at the end. With out_dim <= 16 only the first 16 rows are costed.
         const uint32_t row = valid ? tx[i] : 0u;
         const bool row_ok = row < (uint32_t)M;
         const uint32_t labh = labels[row_ok ? row : 0u] >> (4 * h);
-        double c = 0.0;
+        float mx = 0.0f, prod = 1.0f;
+        auto cost_rows = [&](auto nregs) {
 #pragma unroll
-        for (int r = 0; r < 16; r++) {
-            const float z = zo[r] * 1.4426950408889634f;
-            const float xx = ((labh >> (8 * (r >> 2) + (r & 3))) & 1) ? -z : z;
-            c += (double)(fmaxf(xx, 0.0f) + lg2(1.0f + ex2(-fabsf(xx))));
-        }
-        const float zero = 0.0f * snr_feat;  // a runtime 0 so the constant is computed like the rows
-        const double pad_cost = (double)(fmaxf(zero, 0.0f) + lg2(1.0f + ex2(-fabsf(zero))));
+            for (int r = 0; r < decltype(nregs)::value; r++) {
+                const float z = zo[r] * 1.4426950408889634f;
+                const float xx = ((labh >> (8 * (r >> 2) + (r & 3))) & 1) ? -z : z;
+                mx += fmaxf(xx, 0.0f);
+                prod *= 1.0f + ex2(-fabsf(xx));
+            }
+        };
+        const bool narrow = out_dim <= 16;  // registers 0..7 hold rows 0..15
+        if (narrow)
+            cost_rows(std::integral_constant<int, 8>{});
+        else
+            cost_rows(std::integral_constant<int, 16>{});
+        double c = (double)mx + (double)lg2(prod);
         c += __shfl_xor(c, 32, 64);
-        c -= (double)(32 - out_dim) * pad_cost;
+        c -= (double)((narrow ? 16 : 32) - out_dim);
         if (h == 0 && valid) acc.add(row_ok ? c : NAN, 0.0);
     }
     if constexpr (!LLR) block_reduce_store(acc, part + (size_t)blockIdx.x * kNPart);
