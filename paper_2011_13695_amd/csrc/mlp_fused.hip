@@ -276,12 +276,23 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp_fused(
             zo = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a.v, actA[kb >> 1][kb & 1], zo, 0, 0, 0);
         }
         if constexpr (LLR) {
-            // register r of lane half h is logit row 8 (r >> 2) + 4 h + (r & 3)
+            // registers 4g..4g+3 of lane half h are the consecutive logit
+            // rows 8g + 4h .. 8g + 4h + 3: one 16-byte store per group that
+            // lies wholly below out_dim (4-byte aligned, as global stores
+            // allow), single stores for a partial group
             if (valid) {
+                float* dst = llr + i * out_dim;
 #pragma unroll
-                for (int r = 0; r < 16; r++) {
-                    const int row = 8 * (r >> 2) + 4 * h + (r & 3);
-                    if (row < out_dim) llr[i * out_dim + row] = zo[r];
+                for (int g = 0; g < 4; g++) {
+                    const int r0 = 8 * g + 4 * h;
+                    if (r0 + 4 <= out_dim) {
+                        typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
+                        *(f32x4u*)(dst + r0) = (f32x4u){zo[4 * g], zo[4 * g + 1], zo[4 * g + 2], zo[4 * g + 3]};
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; q++)
+                            if (r0 + q < out_dim) dst[r0 + q] = zo[4 * g + q];
+                    }
                 }
             }
             continue;

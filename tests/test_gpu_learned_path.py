@@ -78,6 +78,26 @@ def test_mlp_llr_elementwise_against_oracle(orc, fmt8, n):
     assert mb.check(lam2, ref, mb.logits_sd(p, SIZES, x)) <= 1.0
 
 
+@pytest.mark.parametrize("out", [1, 5, 16, 21, 32])
+def test_mlp_llr_output_widths(orc, out):
+    """The fused kernel's LLR stores for output widths that fill whole
+    groups of four rows (16, 32) and that end inside one (1, 5, 21), each
+    row against the oracle's logits."""
+    sizes = [9, 256, 256, 256, out]
+    net = mdgmi.MLP(sizes, seed=40 + out)
+    rng = np.random.default_rng(out)
+    n = 301
+    snr = rng.choice(np.arange(2.0, 17.25, 0.25), size=n)
+    y = rng.normal(0.0, 0.7, (n, 8)).astype(np.float32)
+    say(f"[learned] mdgmi_mlp_llr out={out}")
+    lam = net.llr(torch.from_numpy(y).cuda(), torch.from_numpy(snr.astype(np.float32)).cuda()).cpu().numpy()
+    assert lam.shape == (n, out)
+    p = net.params().astype(np.float64)
+    x = feats(y, snr)
+    ref = orc.mlp_forward(p, sizes, x)
+    assert mb.check(lam, ref, mb.logits_sd(p, sizes, x)) <= 1.0
+
+
 def test_mlp_llr_saturated_gelus_and_nan_rows(orc, fmt8):
     """Inputs far outside the trained range drive most pre-activations past
     |x| = 4, where the fused kernel's GELU gate is exactly 0 or 1: the LLRs
