@@ -279,20 +279,37 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp_fused(
             // registers 4g..4g+3 of lane half h are the consecutive logit
             // rows 8g + 4h .. 8g + 4h + 3: one 16-byte store per group that
             // lies wholly below out_dim (4-byte aligned, as global stores
-            // allow), single stores for a partial group
+            // allow), and one store of the 1-3 rows of the group that out_dim
+            // cuts, by the lane half that holds it. (Row-by-row conditional
+            // stores here led the compiler to a schedule of the hidden layers
+            // without the GELU/MFMA interleaving.)
             if (valid) {
                 float* dst = llr + i * out_dim;
+                typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
+                typedef float f32x3u __attribute__((ext_vector_type(3), aligned(4)));
+                typedef float f32x2u __attribute__((ext_vector_type(2), aligned(4)));
 #pragma unroll
                 for (int g = 0; g < 4; g++) {
                     const int r0 = 8 * g + 4 * h;
-                    if (r0 + 4 <= out_dim) {
-                        typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
+                    if (r0 + 4 <= out_dim)
                         *(f32x4u*)(dst + r0) = (f32x4u){zo[4 * g], zo[4 * g + 1], zo[4 * g + 2], zo[4 * g + 3]};
-                    } else {
+                }
+                const int tail = out_dim & 3, rt = out_dim & ~3, gt = rt >> 3;
+                if (tail != 0 && ((rt >> 2) & 1) == h) {
+                    float t0 = zo[0], t1 = zo[1], t2 = zo[2];
 #pragma unroll
-                        for (int q = 0; q < 4; q++)
-                            if (r0 + q < out_dim) dst[r0 + q] = zo[4 * g + q];
-                    }
+                    for (int g = 1; g < 4; g++)
+                        if (g == gt) {
+                            t0 = zo[4 * g];
+                            t1 = zo[4 * g + 1];
+                            t2 = zo[4 * g + 2];
+                        }
+                    if (tail == 3)
+                        *(f32x3u*)(dst + rt) = (f32x3u){t0, t1, t2};
+                    else if (tail == 2)
+                        *(f32x2u*)(dst + rt) = (f32x2u){t0, t1};
+                    else
+                        dst[rt] = t0;
                 }
             }
             continue;
