@@ -469,7 +469,11 @@ int mdgmi_mlp_train_step(mdgmi_mlp* net, const float* y, const float* snr_db, co
  * y [n][dim] at per-sample SNRs snr_db [n] (device float, dB). Networks of
  * the fused shape [<= 16, 256, 256, 256, <= 32] run the fused kernel and
  * need no workspace (size 0; ws may be NULL), others the layer-by-layer
- * GEMMs in a workspace of mdgmi_mlp_llr_workspace_size bytes. */
+ * GEMMs in a workspace of mdgmi_mlp_llr_workspace_size bytes. The fused
+ * kernel evaluates the GELU gate sigmoid(2 sqrt(2/pi) (x + 0.044715 x^3))
+ * as a clamped polynomial in packed fp16 (within 8e-4 of it; exactly 0 / 1
+ * for |x| >= 4), the layer-by-layer path in the tanh form itself; both
+ * results carry the bf16 rounding of weights and activations. */
 int mdgmi_mlp_llr_workspace_size(const mdgmi_mlp* net, int64_t n, size_t* bytes);
 int mdgmi_mlp_llr(const mdgmi_mlp* net, const float* y, const float* snr_db, int64_t n, float* llr, void* ws,
                   size_t ws_bytes, void* stream);
