@@ -512,7 +512,7 @@ int mdgmi_mlp_load(mdgmi_mlp* net, const char* path);
 
 /* Measured peaks of the current device, behind the roofline figures (the
  * demapper is bound by the exponential issue rate of the vector ALU, the
- * learned demapper by the vector ALU beside the matrix cores): out_host [8]
+ * learned demapper by the vector ALU beside the matrix cores): out_host [9]
  * receives
  *   [0] v_exp_f32 results per second over the whole device,
  *   [1] the core clock during that probe (Hz, s_memtime cycles against the
@@ -521,7 +521,10 @@ int mdgmi_mlp_load(mdgmi_mlp* net, const char* path);
  *   [4] v_mfma_f32_32x32x16_bf16 flops per second,
  *   [5], [6], [7] the same MFMA flops per second at two waves per SIMD when
  *       each MFMA is followed by 0, 4 and 8 independent FP32 FMAs of its
- *       wave (how much vector work issues while the matrix core runs).
+ *       wave (how much vector work issues while the matrix core runs),
+ *   [8] iterations per second of each SIMD when one of its two waves runs
+ *       two MFMAs and the other sixteen FP32 FMAs per iteration (whether an
+ *       MFMA holds up the vector issue of the other wave too).
  * Probes [0]-[4] run 8 waves per SIMD of independent dependency chains; the
  * call allocates and frees a few bytes of device memory and synchronises
  * the device (a measurement call, not for hot loops). */

@@ -100,6 +100,40 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_mix(int iters, float* _
     if (s == 12345.0f) sink[threadIdx.x] = s;
 }
 
+// The same across waves: blocks of 8 waves (two per SIMD, waves w and w + 4
+// sharing one), waves 0-3 running two MFMA chains and waves 4-7 sixteen FP32
+// FMAs per iteration on 8 chains. With MFMA and vector work in different
+// waves of one SIMD the time shows whether an MFMA holds up only its own
+// wave's vector issue or the whole SIMD's.
+__global__ __launch_bounds__(512) void k_probe_split(int iters, float* __restrict__ sink) {
+    float s = 0.0f;
+    if ((threadIdx.x >> 6) < 4) {
+        pbf16x8 a, b;
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            a[i] = (__bf16)(1e-3f * (float)(threadIdx.x + i));
+            b[i] = (__bf16)(1e-3f * (float)(i + 1));
+        }
+        pf32x16 acc[2] = {};
+        for (int it = 0; it < iters; it++) {
+#pragma unroll
+            for (int m = 0; m < 2; m++) acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[m], 0, 0, 0);
+        }
+        s = acc[0][0] + acc[1][0];
+    } else {
+        float v[kProbeChains];
+#pragma unroll
+        for (int c = 0; c < kProbeChains; c++) v[c] = 1e-6f * (float)(threadIdx.x + c + 1);
+        for (int it = 0; it < iters; it++) {
+#pragma unroll
+            for (int j = 0; j < 16; j++) v[j % kProbeChains] = fmaf(v[j % kProbeChains], 0.999999f, 1.0e-7f);
+        }
+#pragma unroll
+        for (int c = 0; c < kProbeChains; c++) s += v[c];
+    }
+    if (s == 12345.0f) sink[threadIdx.x & (kProbeThreads - 1)] = s;
+}
+
 }  // namespace
 }  // namespace mdgmi
 
@@ -122,7 +156,7 @@ extern "C" int mdgmi_probe_rates(double* out_host) {
     int rc = MDGMI_OK;
     const int mix_blocks = device_cu_count() * 2;  // 2 waves per SIMD
     auto run = [&](int op, int iters, double ops_per_lane_iter, double* rate, double* hz) {
-        const int nb = op >= 3 ? mix_blocks : blocks;
+        const int nb = op == 6 ? device_cu_count() : op >= 3 ? mix_blocks : blocks;
         for (int rep = 0; rep < 2; rep++) {  // the first launch warms up
             (void)hipEventRecord(e0, nullptr);
             if (op == 0)
@@ -135,8 +169,10 @@ extern "C" int mdgmi_probe_rates(double* out_host) {
                 hipLaunchKernelGGL(k_probe_mix<0>, dim3(nb), dim3(kProbeThreads), 0, nullptr, iters, sink);
             else if (op == 4)
                 hipLaunchKernelGGL(k_probe_mix<4>, dim3(nb), dim3(kProbeThreads), 0, nullptr, iters, sink);
-            else
+            else if (op == 5)
                 hipLaunchKernelGGL(k_probe_mix<8>, dim3(nb), dim3(kProbeThreads), 0, nullptr, iters, sink);
+            else
+                hipLaunchKernelGGL(k_probe_split, dim3(device_cu_count()), dim3(512), 0, nullptr, iters, sink);
             (void)hipEventRecord(e1, nullptr);
         }
         float ms = 0.0f;
@@ -146,7 +182,7 @@ extern "C" int mdgmi_probe_rates(double* out_host) {
             rc = MDGMI_E_HIP;
             return;
         }
-        *rate = (double)nb * kProbeThreads * iters * ops_per_lane_iter / (ms * 1e-3);
+        *rate = (double)nb * (op == 6 ? 512 : kProbeThreads) * iters * ops_per_lane_iter / (ms * 1e-3);
         if (hz) *hz = c[1] > 0 ? (double)c[0] / ((double)c[1] / (wall_khz * 1e3)) : 0.0;
     };
     // exponentials and FMAs per lane and iteration; MFMA: 4 per wave and
@@ -156,6 +192,10 @@ extern "C" int mdgmi_probe_rates(double* out_host) {
     run(2, 2048, 4.0 * 2 * 32 * 32 * 16 / 64.0, &out_host[4], nullptr);
     // MFMA flops per second at two waves per SIMD with 0, 4 and 8 FMAs per MFMA
     for (int k = 0; k < 3; k++) run(3 + k, 8192, 2.0 * 2 * 32 * 32 * 16 / 64.0, &out_host[5 + k], nullptr);
+    // MFMA and FMA waves side by side (k_probe_split): iterations per second
+    // of each SIMD, an iteration being two MFMAs in one of its waves and
+    // sixteen FMAs in the other
+    run(6, 8192, 1.0 / (512.0 * device_cu_count()), &out_host[8], nullptr);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipFree(sink);

@@ -838,9 +838,9 @@ def mdgmi_mlp_set_fused(waves: int) -> None:
 
 def mdgmi_probe_rates() -> dict:
     """Measured peaks of the current device (mdgmi_probe_rates)."""
-    out = np.zeros(8, dtype=np.float64)
+    out = np.zeros(9, dtype=np.float64)
     _check("mdgmi_probe_rates", lib().mdgmi_probe_rates(out.ctypes.data_as(_P)))
     return {"exp_per_s": float(out[0]), "clock_hz_exp": float(out[1]), "fma_lane_ops_per_s": float(out[2]),
             "clock_hz_fma": float(out[3]), "mfma_bf16_flops_per_s": float(out[4]),
             "mfma_2waves_flops_per_s": float(out[5]), "mfma_with_4_fma_flops_per_s": float(out[6]),
-            "mfma_with_8_fma_flops_per_s": float(out[7])}
+            "mfma_with_8_fma_flops_per_s": float(out[7]), "split_waves_iters_per_s": float(out[8])}

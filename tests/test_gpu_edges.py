@@ -216,3 +216,11 @@ def test_peak_probe_rates_are_plausible():
     # vector instructions beside the MFMAs can only slow the matrix core down
     assert 1e14 < r["mfma_with_8_fma_flops_per_s"] <= 1.05 * r["mfma_with_4_fma_flops_per_s"]
     assert r["mfma_with_4_fma_flops_per_s"] <= 1.05 * r["mfma_2waves_flops_per_s"] <= 1.1 * 2.5e15
+    # MFMA and FMA waves side by side: an iteration (2 MFMAs of one wave, 16 FMAs of
+    # the other) takes at least as long as the longer of its two parts alone
+    simd = torch.cuda.get_device_properties(0).multi_processor_count * 4
+    t_mfma = 2 * 32768 / (r["mfma_2waves_flops_per_s"] / simd)
+    t_fma = 16 * 64 / (r["fma_lane_ops_per_s"] / simd)
+    t_split = 1.0 / r["split_waves_iters_per_s"]
+    say(f"[probe] split waves: {t_split * 1e9:.1f} ns per iteration; MFMA part {t_mfma * 1e9:.1f}, FMA part {t_fma * 1e9:.1f}")
+    assert 0.95 * max(t_mfma, t_fma) <= t_split <= 1.5 * (t_mfma + t_fma)
