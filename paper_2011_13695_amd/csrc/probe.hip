@@ -149,10 +149,18 @@ extern "C" int mdgmi_probe_rates(double* out_host) {
     float* sink = nullptr;
     unsigned long long* clk = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto release = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (sink) (void)hipFree(sink);
+        if (clk) (void)hipFree(clk);
+    };
     if (hipMalloc(&sink, sizeof(float) * kProbeThreads) != hipSuccess ||
         hipMalloc(&clk, 2 * sizeof(unsigned long long)) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
-        hipEventCreate(&e1) != hipSuccess)
+        hipEventCreate(&e1) != hipSuccess) {
+        release();
         return MDGMI_E_HIP;
+    }
     int rc = MDGMI_OK;
     const int mix_blocks = device_cu_count() * 2;  // 2 waves per SIMD
     auto run = [&](int op, int iters, double ops_per_lane_iter, double* rate, double* hz) {
@@ -196,9 +204,6 @@ extern "C" int mdgmi_probe_rates(double* out_host) {
     // of each SIMD, an iteration being two MFMAs in one of its waves and
     // sixteen FMAs in the other
     run(6, 8192, 1.0 / (512.0 * device_cu_count()), &out_host[8], nullptr);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(sink);
-    (void)hipFree(clk);
+    release();
     return rc;
 }
