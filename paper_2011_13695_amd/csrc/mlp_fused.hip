@@ -25,7 +25,6 @@
 // written; in LLR mode the logits are stored, [n][out] FP32.
 #include <algorithm>
 #include <cmath>
-#include <type_traits>
 
 #include "device_common.h"
 #include "mlp_gemm.h"
@@ -317,30 +316,24 @@ __global__ __launch_bounds__(kWaves * 64) void k_mlp_fused(
         // ---- per-sample GMI cost of the logits (bits), both lane halves:
         // the sum over rows of max(x, 0) + log2(1 + 2^-|x|), the second part
         // as one logarithm of the product of its factors (each in (1, 2]).
-        // Rows >= out_dim have zero weights and bias: their logit is exactly
-        // 0, their factor exactly 2 and their cost exactly one bit, taken off
-        // at the end. With out_dim <= 16 only the first 16 rows are costed.
+        // In GMI mode out_dim is the format's bit count (<= 12), so rows
+        // 0..15, registers 0..7, hold every logit; rows out_dim..15 have zero
+        // weights and bias: their logit is exactly 0, their factor exactly 2
+        // and their cost exactly one bit, taken off at the end.
         const uint32_t row = valid ? tx[i] : 0u;
         const bool row_ok = row < (uint32_t)M;
         const uint32_t labh = labels[row_ok ? row : 0u] >> (4 * h);
         float mx = 0.0f, prod = 1.0f;
-        auto cost_rows = [&](auto nregs) {
 #pragma unroll
-            for (int r = 0; r < decltype(nregs)::value; r++) {
-                const float z = zo[r] * 1.4426950408889634f;
-                const float xx = ((labh >> (8 * (r >> 2) + (r & 3))) & 1) ? -z : z;
-                mx += fmaxf(xx, 0.0f);
-                prod *= 1.0f + ex2(-fabsf(xx));
-            }
-        };
-        const bool narrow = out_dim <= 16;  // registers 0..7 hold rows 0..15
-        if (narrow)
-            cost_rows(std::integral_constant<int, 8>{});
-        else
-            cost_rows(std::integral_constant<int, 16>{});
+        for (int r = 0; r < 8; r++) {
+            const float z = zo[r] * 1.4426950408889634f;
+            const float xx = ((labh >> (8 * (r >> 2) + (r & 3))) & 1) ? -z : z;
+            mx += fmaxf(xx, 0.0f);
+            prod *= 1.0f + ex2(-fabsf(xx));
+        }
         double c = (double)mx + (double)lg2(prod);
         c += __shfl_xor(c, 32, 64);
-        c -= (double)((narrow ? 16 : 32) - out_dim);
+        c -= (double)(16 - out_dim);
         if (h == 0 && valid) acc.add(row_ok ? c : NAN, 0.0);
     }
     if constexpr (!LLR) block_reduce_store(acc, part + (size_t)blockIdx.x * kNPart);
@@ -396,6 +389,7 @@ hipError_t launch_fused_w(__bf16* const* wf, const float* const* bias, int in_di
 hipError_t launch_mlp_gmi_fused(__bf16* const* wf, const float* const* bias, int in_dim, int out_dim, const float* y,
                                 int dim, const uint32_t* tx, const uint32_t* labels, int M, int64_t n, float snr_feat,
                                 double* part, int grid, hipStream_t st) {
+    if (out_dim < 1 || out_dim > 16) return hipErrorInvalidValue;  // the GMI cost reads rows 0..15
     if (g_fused_waves == 8)
         return launch_fused_w<8, false>(wf, bias, in_dim, out_dim, y, dim, tx, labels, M, n, nullptr, snr_feat,
                                         nullptr, part, grid, st);
