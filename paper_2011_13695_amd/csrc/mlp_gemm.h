@@ -122,18 +122,64 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     const int64_t kb = (int64_t)blockIdx.z * g.k_per_split;
     const int64_t ke = kb + g.k_per_split < g.K ? kb + g.k_per_split : g.K;
     f32x16 acc = {};
-    for (int64_t k0 = kb; k0 < ke; k0 += kKStep) {
-        load_tile_a<A_K_CONTIG>(g, m0, k0, ke, As);
-        load_tile_b<B_K_CONTIG>(g, n0, k0, ke, Bs);
-        __syncthreads();
+    if constexpr (A_K_CONTIG && B_K_CONTIG) {
+        // Both operands k-contiguous (every call of the training step): each
+        // thread moves 8 consecutive k of one A row and one B column per
+        // K-step, as one 16-byte load where the row pitch, the pointer and
+        // the K range allow, and the next K-step's loads are issued before
+        // the MFMAs of the current one.
+        const int t = threadIdx.x, rr = t >> 2, kk = (t & 3) * 8;
+        const bool avec = g.a_sk == 1 && g.a_sm % 8 == 0 && ((uintptr_t)g.A & 15) == 0;
+        const bool bvec = g.b_sk == 1 && g.b_sn % 8 == 0 && ((uintptr_t)g.B & 15) == 0;
+        auto fetch = [&](const __bf16* base, int64_t row, int64_t rows, int64_t pitch, int64_t sk, bool vec,
+                         int64_t k0) {
+            const int64_t k = k0 + kk;
+            union {
+                uint4 u;
+                __bf16 h[8];
+            } p;
+            if (vec && row < rows && k + 8 <= ke) {
+                p.u = *(const uint4*)(base + row * pitch + k);
+            } else {
 #pragma unroll
-        for (int ks = 0; ks < kKStep; ks += 16) {
-            const int kofs = ks + 8 * (lane >> 5);
-            const bf16x8 a = *(const bf16x8*)(As + (wm + (lane & 31)) * kLdsPitch + kofs);
-            const bf16x8 b = *(const bf16x8*)(Bs + (wn + (lane & 31)) * kLdsPitch + kofs);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+                for (int i = 0; i < 8; i++)
+                    p.h[i] = (row < rows && k + i < ke) ? base[row * pitch + (k + i) * sk] : (__bf16)0.0f;
+            }
+            return p.u;
+        };
+        uint4 ra = fetch(g.A, m0 + rr, g.M, g.a_sm, g.a_sk, avec, kb);
+        uint4 rb = fetch(g.B, n0 + rr, g.N, g.b_sn, g.b_sk, bvec, kb);
+        for (int64_t k0 = kb; k0 < ke; k0 += kKStep) {
+            *(uint4*)(As + rr * kLdsPitch + kk) = ra;
+            *(uint4*)(Bs + rr * kLdsPitch + kk) = rb;
+            __syncthreads();
+            if (k0 + kKStep < ke) {
+                ra = fetch(g.A, m0 + rr, g.M, g.a_sm, g.a_sk, avec, k0 + kKStep);
+                rb = fetch(g.B, n0 + rr, g.N, g.b_sn, g.b_sk, bvec, k0 + kKStep);
+            }
+#pragma unroll
+            for (int ks = 0; ks < kKStep; ks += 16) {
+                const int kofs = ks + 8 * (lane >> 5);
+                const bf16x8 a = *(const bf16x8*)(As + (wm + (lane & 31)) * kLdsPitch + kofs);
+                const bf16x8 b = *(const bf16x8*)(Bs + (wn + (lane & 31)) * kLdsPitch + kofs);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+            }
+            __syncthreads();
         }
-        __syncthreads();
+    } else {
+        for (int64_t k0 = kb; k0 < ke; k0 += kKStep) {
+            load_tile_a<A_K_CONTIG>(g, m0, k0, ke, As);
+            load_tile_b<B_K_CONTIG>(g, n0, k0, ke, Bs);
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < kKStep; ks += 16) {
+                const int kofs = ks + 8 * (lane >> 5);
+                const bf16x8 a = *(const bf16x8*)(As + (wm + (lane & 31)) * kLdsPitch + kofs);
+                const bf16x8 b = *(const bf16x8*)(Bs + (wn + (lane & 31)) * kLdsPitch + kofs);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+            }
+            __syncthreads();
+        }
     }
     // lane holds rows 8 (r >> 2) + 4 (lane >> 5) + (r & 3) of column lane & 31
     const int64_t n = n0 + wn + (lane & 31);
