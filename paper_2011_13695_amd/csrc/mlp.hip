@@ -42,7 +42,8 @@ namespace mdgmi {
 // mlp_fused.hip
 bool fused_shape_ok(const int* sizes, int L);
 size_t fused_weight_bytes(int layer);
-hipError_t build_fused_weights(const float* W, int out, int in, int layer, __bf16* dst, hipStream_t st);
+hipError_t build_fused_weights(const float* const* W, const int* out, const int* in, __bf16* const* dst,
+                               hipStream_t st);
 int fused_grid();
 extern int g_fused_waves;
 hipError_t launch_mlp_gmi_fused(__bf16* const* wf, const float* const* bias, int in_dim, int out_dim, const float* y,
@@ -68,9 +69,14 @@ int64_t split_len(int64_t n) {
 
 
 // ---- elementwise kernels ----
-__global__ void k_to_bf16(const float* __restrict__ x, int64_t cnt, __bf16* __restrict__ out) {
+// out [n][cols] = bf16(x), and xt [cols][n] (if not null) the transposed copy
+__global__ void k_to_bf16(const float* __restrict__ x, int64_t n, int cols, __bf16* __restrict__ out,
+                          __bf16* __restrict__ xt) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cnt) out[i] = (__bf16)x[i];
+    if (i >= n * cols) return;
+    const __bf16 b = (__bf16)x[i];
+    out[i] = b;
+    if (xt) xt[(i % cols) * n + i / cols] = b;
 }
 
 __global__ void k_features(const float* __restrict__ y, int64_t n, int dim, float snr_feature,
@@ -81,17 +87,20 @@ __global__ void k_features(const float* __restrict__ y, int64_t n, int dim, floa
     x[i * (dim + 1) + dim] = snr_feature;
 }
 
-// D = (sigmoid(z) - sigmoid(lambda)) / n in bf16, and per-block FP64 loss
-// partials sum_k softplus(z) - p z.
+// D = (sigmoid(z) - sigmoid(lambda)) / n in bf16 (and its transpose Dt
+// [out][n]), and per-block FP64 loss partials sum_k softplus(z) - p z.
 __global__ __launch_bounds__(256) void k_bce(const float* __restrict__ logits, const float* __restrict__ target_llr,
-                                             int64_t n, int out, __bf16* __restrict__ D, double* __restrict__ part) {
+                                             int64_t n, int out, __bf16* __restrict__ D, __bf16* __restrict__ Dt,
+                                             double* __restrict__ part) {
     const int64_t cnt = n * out;
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
         const float z = logits[i];
         const float p = 1.0f / (1.0f + expf(-target_llr[i]));
         const float sz = 1.0f / (1.0f + expf(-z));
-        D[i] = (__bf16)((sz - p) / (float)n);
+        const __bf16 d = (__bf16)((sz - p) / (float)n);
+        D[i] = d;
+        Dt[(i % out) * n + i / out] = d;
         const double sp = (z > 0.0f ? (double)z : 0.0) + log1p(exp(-(double)fabsf(z)));
         acc += sp - (double)p * (double)z;
     }
@@ -105,31 +114,72 @@ __global__ __launch_bounds__(256) void k_bce(const float* __restrict__ logits, c
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_sum_loss(const double* __restrict__ part, int nb, int64_t n, double* __restrict__ loss) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int b = 0; b < nb; b++) s += part[b];
-        *loss = s / (double)n;
+// loss = sum of the block partials / n: thread t adds partials t, t + 64,
+// ... in turn, then a fixed tree over the 64 threads.
+__global__ __launch_bounds__(64) void k_sum_loss(const double* __restrict__ part, int nb, int64_t n,
+                                                 double* __restrict__ loss) {
+    __shared__ double red[64];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 64) s += part[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *loss = red[0] / (double)n;
 }
 
-// grad[o * in + i] = sum over splits of partial[s][o][i] (fixed order)
-__global__ void k_reduce_splits(const float* __restrict__ partial, int splits, int64_t cnt, float* __restrict__ grad) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cnt) return;
-    float s = 0.0f;
-    for (int k = 0; k < splits; k++) s += partial[(int64_t)k * cnt + i];
-    grad[i] = s;
-}
-
-// db[o] = sum_s D^T[o][s] in a fixed order: thread t of block o adds
-// samples t, t + 256, ... in turn, then a fixed tree over the 256 threads.
-__global__ __launch_bounds__(256) void k_rowsum(const __bf16* __restrict__ Dt, int64_t n, float* __restrict__ db) {
+// The weight and bias gradients of one layer, one launch. Blocks below nr:
+// grad[o * in + i] = sum over the split-K slices of partial[s][o][i], in
+// slice order, four consecutive i per thread (16-byte loads where the count
+// and the pointer allow). The next `out` blocks: db[o] = sum_s D^T[o][s],
+// thread t of the block adding samples 8t .. 8t + 7, then 8t + 2048 .. in
+// turn (16-byte loads where n and the row allow), then a fixed tree over the
+// 256 threads.
+__global__ __launch_bounds__(256) void k_grad_finish(const float* __restrict__ partial, int splits, int64_t cnt,
+                                                     float* __restrict__ grad, int nr, const __bf16* __restrict__ Dt,
+                                                     int64_t n, float* __restrict__ db) {
+    if ((int)blockIdx.x < nr) {
+        const int64_t i = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+        if (i >= cnt) return;
+        if (i + 4 <= cnt && cnt % 4 == 0 && ((uintptr_t)grad & 15) == 0) {
+            float4 s = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            for (int k = 0; k < splits; k++) {
+                const float4 v = *(const float4*)(partial + (int64_t)k * cnt + i);
+                s.x += v.x;
+                s.y += v.y;
+                s.z += v.z;
+                s.w += v.w;
+            }
+            *(float4*)(grad + i) = s;
+        } else {
+            for (int64_t j = i; j < i + 4 && j < cnt; j++) {
+                float s = 0.0f;
+                for (int k = 0; k < splits; k++) s += partial[(int64_t)k * cnt + j];
+                grad[j] = s;
+            }
+        }
+        return;
+    }
     __shared__ float red[256];
-    const int64_t o = blockIdx.x;
+    const int64_t o = blockIdx.x - nr;
     const __bf16* row = Dt + o * n;
+    const bool vec = n % 8 == 0 && ((uintptr_t)row & 15) == 0;
     float s = 0.0f;
-    for (int64_t i = threadIdx.x; i < n; i += 256) s += (float)row[i];
+    for (int64_t i = 8 * (int64_t)threadIdx.x; i < n; i += 8 * 256) {
+        if (vec) {
+            union {
+                uint4 u;
+                __bf16 h[8];
+            } p;
+            p.u = *(const uint4*)(row + i);
+#pragma unroll
+            for (int j = 0; j < 8; j++) s += (float)p.h[j];
+        } else {
+            for (int64_t j = i; j < i + 8 && j < n; j++) s += (float)row[j];
+        }
+    }
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -151,56 +201,23 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// dst [cols][rows] = src [rows][cols] (bf16), through 64 x 64 LDS tiles:
-// coalesced reads along cols, coalesced writes along rows. blockIdx.z
-// selects one of two matrices with the same row count (one launch for both
-// operands of a weight gradient).
-struct TransposeArgs {
-    const __bf16* src[2];
-    __bf16* dst[2];
-    int cols[2];
+// bf16 copies W [out][in] and W^T [in][out] of every layer, one launch
+// (blockIdx.y = layer)
+struct RefreshArgs {
+    const float* W[MDGMI_MLP_MAX_LAYERS];
+    __bf16* w[MDGMI_MLP_MAX_LAYERS];
+    __bf16* wt[MDGMI_MLP_MAX_LAYERS];
+    int out[MDGMI_MLP_MAX_LAYERS], in[MDGMI_MLP_MAX_LAYERS];
 };
 
-__global__ __launch_bounds__(256) void k_transpose_bf16(TransposeArgs a, int64_t rows) {
-    __shared__ __bf16 tile[64][66];
-    const __bf16* __restrict__ src = a.src[blockIdx.z];
-    __bf16* __restrict__ dst = a.dst[blockIdx.z];
-    const int cols = a.cols[blockIdx.z];
-    const int64_t r0 = (int64_t)blockIdx.x * 64;
-    const int c0 = blockIdx.y * 64;
-    if (c0 >= cols) return;  // the narrower matrix has fewer column tiles
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4 threads
-    for (int i = ty; i < 64; i += 4) {
-        const int64_t r = r0 + i;
-        const int c = c0 + tx;
-        tile[i][tx] = (r < rows && c < cols) ? src[r * cols + c] : (__bf16)0.0f;
-    }
-    __syncthreads();
-    for (int i = ty; i < 64; i += 4) {
-        const int c = c0 + i;
-        const int64_t r = r0 + tx;
-        if (c < cols && r < rows) dst[(int64_t)c * rows + r] = tile[tx][i];
-    }
-}
-
-// src0 [rows][cols0] -> dst0 [cols0][rows] and src1 [rows][cols1] -> dst1 [cols1][rows]
-hipError_t transpose2_bf16(const __bf16* src0, int cols0, __bf16* dst0, const __bf16* src1, int cols1, __bf16* dst1,
-                           int64_t rows, hipStream_t st) {
-    TransposeArgs a{{src0, src1}, {dst0, dst1}, {cols0, cols1}};
-    const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((std::max(cols0, cols1) + 63) / 64), 2);
-    hipLaunchKernelGGL(k_transpose_bf16, grid, dim3(256), 0, st, a, rows);
-    return hipGetLastError();
-}
-
-// bf16 copies W [out][in] and W^T [in][out] of one layer
-__global__ void k_refresh(const float* __restrict__ W, int out, int in, __bf16* __restrict__ w,
-                          __bf16* __restrict__ wt) {
+__global__ void k_refresh(RefreshArgs a) {
+    const int l = blockIdx.y, out = a.out[l], in = a.in[l];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)out * in) return;
     const int o = (int)(i / in), j = (int)(i % in);
-    const __bf16 b = (__bf16)W[i];
-    w[i] = b;
-    wt[(int64_t)j * out + o] = b;
+    const __bf16 b = (__bf16)a.W[l][i];
+    a.w[l][i] = b;
+    a.wt[l][(int64_t)j * out + o] = b;
 }
 
 // ---- GEMM launch ----
@@ -226,7 +243,8 @@ GemmArgs gargs() {
 
 // Workspace layout for n samples.
 struct MlpWs {
-    int64_t x0, z[MDGMI_MLP_MAX_LAYERS], h[MDGMI_MLP_MAX_LAYERS], logits, d0, d1, dt, ht, part, lpart, total;
+    int64_t x0, z[MDGMI_MLP_MAX_LAYERS], h[MDGMI_MLP_MAX_LAYERS], logits, d0, d1, dt, ht[MDGMI_MLP_MAX_LAYERS], part,
+        lpart, total;
 };
 
 MlpWs mlp_ws(const mdgmi_mlp* net, int64_t n) {
@@ -245,13 +263,15 @@ MlpWs mlp_ws(const mdgmi_mlp* net, int64_t n) {
     o += al(n * net->width * 2);
     w.d1 = o;
     o += al(n * net->width * 2);
-    // transposed copies [features][n] of D and of the layer input for the
-    // weight gradients (the sample axis is their K axis)
-    const int64_t widest = std::max<int64_t>(net->width, net->sizes[0]);
+    // transposed copies [features][n] of D and of every layer's input for
+    // the weight gradients (the sample axis is their K axis), written by the
+    // kernels that produce D and the inputs
     w.dt = o;
-    o += al(n * widest * 2);
-    w.ht = o;
-    o += al(n * widest * 2);
+    o += al(n * net->width * 2);
+    for (int l = 0; l < net->L; l++) {
+        w.ht[l] = o;
+        o += al(n * net->sizes[l] * 2);
+    }
     const int64_t splits = (n + split_len(n) - 1) / split_len(n);
     w.part = o;
     o += al(splits * (int64_t)net->width * net->width * 4);
@@ -262,11 +282,13 @@ MlpWs mlp_ws(const mdgmi_mlp* net, int64_t n) {
 }
 
 // Forward pass of n samples: Z_l (FP32) and H_l (bf16) of every layer into
-// the workspace; the last layer's Z is the logits.
-hipError_t forward(const mdgmi_mlp* net, const float* x, int64_t n, char* ws, const MlpWs& w, hipStream_t st) {
+// the workspace; the last layer's Z is the logits. With `transposed`, each
+// layer's input is also stored as [features][n] for the weight gradients.
+hipError_t forward(const mdgmi_mlp* net, const float* x, int64_t n, char* ws, const MlpWs& w, hipStream_t st,
+                   bool transposed = false) {
     const int in0 = net->sizes[0];
-    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n * in0 + 255) / 256)), dim3(256), 0, st, x, n * in0,
-                       (__bf16*)(ws + w.x0));
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n * in0 + 255) / 256)), dim3(256), 0, st, x, n, in0,
+                       (__bf16*)(ws + w.x0), transposed ? (__bf16*)(ws + w.ht[0]) : nullptr);
     const __bf16* prev = (const __bf16*)(ws + w.x0);
     for (int l = 0; l < net->L; l++) {
         const int in = net->sizes[l], out = net->sizes[l + 1];
@@ -288,6 +310,10 @@ hipError_t forward(const mdgmi_mlp* net, const float* x, int64_t n, char* ws, co
         if (l < net->L - 1) {
             g.H = (__bf16*)(ws + w.h[l]);
             g.ldh = out;
+            if (transposed) {
+                g.Ht = (__bf16*)(ws + w.ht[l + 1]);
+                g.ldht = n;
+            }
             e = gemm<kEpiGeluBf16>(g, true, true, 1, st);
         } else {
             e = gemm<kEpiF32>(g, true, true, 1, st);
@@ -299,12 +325,19 @@ hipError_t forward(const mdgmi_mlp* net, const float* x, int64_t n, char* ws, co
 }
 
 void refresh_all(mdgmi_mlp* net, hipStream_t st) {
+    RefreshArgs a{};
+    int64_t most = 0;
+    const float* W[MDGMI_MLP_MAX_LAYERS];
     for (int l = 0; l < net->L; l++) {
-        const int in = net->sizes[l], out = net->sizes[l + 1];
-        hipLaunchKernelGGL(k_refresh, dim3((unsigned)(((int64_t)out * in + 255) / 256)), dim3(256), 0, st,
-                           net->d_params + net->woff[l], out, in, net->d_w[l], net->d_wt[l]);
-        if (net->fused) (void)build_fused_weights(net->d_params + net->woff[l], out, in, l, net->d_wf[l], st);
+        W[l] = a.W[l] = net->d_params + net->woff[l];
+        a.w[l] = net->d_w[l];
+        a.wt[l] = net->d_wt[l];
+        a.out[l] = net->sizes[l + 1];
+        a.in[l] = net->sizes[l];
+        most = std::max<int64_t>(most, (int64_t)a.out[l] * a.in[l]);
     }
+    hipLaunchKernelGGL(k_refresh, dim3((unsigned)((most + 255) / 256), (unsigned)net->L), dim3(256), 0, st, a);
+    if (net->fused) (void)build_fused_weights(W, a.out, a.in, net->d_wf, st);
 }
 
 bool ok_sizes(const int32_t* sizes, int L) {
@@ -452,11 +485,11 @@ int mdgmi_mlp_loss_grad(mdgmi_mlp* net, const float* x, const float* target_llr,
     if (ws_bytes < (size_t)w.total) return MDGMI_E_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     char* base = (char*)ws;
-    if (forward(net, x, n, base, w, st) != hipSuccess) return MDGMI_E_HIP;
+    if (forward(net, x, n, base, w, st, true) != hipSuccess) return MDGMI_E_HIP;
     const int L = net->L, outL = net->sizes[L];
     const int nb = (int)std::min<int64_t>(1024, (n * outL + 255) / 256);
     hipLaunchKernelGGL(k_bce, dim3(nb), dim3(256), 0, st, (const float*)(base + w.logits), target_llr, n, outL,
-                       (__bf16*)(base + w.d0), (double*)(base + w.lpart));
+                       (__bf16*)(base + w.d0), (__bf16*)(base + w.dt), (double*)(base + w.lpart));
     hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(64), 0, st, (const double*)(base + w.lpart), nb, n, loss);
     __bf16* D = (__bf16*)(base + w.d0);
     __bf16* Dn = (__bf16*)(base + w.d1);
@@ -464,12 +497,10 @@ int mdgmi_mlp_loss_grad(mdgmi_mlp* net, const float* x, const float* target_llr,
     const int splits = (int)((n + slen - 1) / slen);
     for (int l = L - 1; l >= 0; l--) {
         const int in = net->sizes[l], out = net->sizes[l + 1];
-        const __bf16* Hprev = l > 0 ? (const __bf16*)(base + w.h[l - 1]) : (const __bf16*)(base + w.x0);
         // dW_l [out][in] = sum_s D[s][o] Hprev[s][i]  (split over samples),
-        // on copies with the sample axis contiguous: D^T [out][n], Hprev^T [in][n]
-        __bf16* Dt = (__bf16*)(base + w.dt);
-        __bf16* Ht = (__bf16*)(base + w.ht);
-        if (transpose2_bf16(D, out, Dt, Hprev, in, Ht, n, st) != hipSuccess) return MDGMI_E_HIP;
+        // on the copies with the sample axis contiguous: D^T [out][n], Hprev^T [in][n]
+        const __bf16* Dt = (const __bf16*)(base + w.dt);
+        const __bf16* Ht = (const __bf16*)(base + w.ht[l]);
         GemmArgs g = gargs();
         g.A = Dt;
         g.a_sm = n;
@@ -483,12 +514,12 @@ int mdgmi_mlp_loss_grad(mdgmi_mlp* net, const float* x, const float* target_llr,
         g.k_per_split = slen;
         g.C = (float*)(base + w.part);
         if (gemm<kEpiPartial>(g, true, true, splits, st) != hipSuccess) return MDGMI_E_HIP;
+        // dW_l from the slices and db_l [out] = sum_s D[s][o] from the same transposed copy
         const int64_t cnt = (int64_t)out * in;
-        hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
-                           (const float*)(base + w.part), splits, cnt, net->d_grad + net->woff[l]);
-        // db_l [out] = sum_s D[s][o], from the same transposed copy
-        hipLaunchKernelGGL(k_rowsum, dim3((unsigned)out), dim3(256), 0, st, (const __bf16*)Dt, n,
-                           net->d_grad + net->boff[l]);
+        const int nr = (int)((cnt + 1023) / 1024);
+        hipLaunchKernelGGL(k_grad_finish, dim3((unsigned)(nr + out)), dim3(256), 0, st,
+                           (const float*)(base + w.part), splits, cnt, net->d_grad + net->woff[l], nr,
+                           (const __bf16*)Dt, n, net->d_grad + net->boff[l]);
         if (l > 0) {
             // D_prev [n][in] = (D [n][out] W_l [out][in]) * gelu'(Z_{l-1})
             GemmArgs h = gargs();
@@ -506,6 +537,8 @@ int mdgmi_mlp_loss_grad(mdgmi_mlp* net, const float* x, const float* target_llr,
             h.ldh = in;
             h.Z = (const float*)(base + w.z[l - 1]);
             h.ldz = in;
+            h.Ht = (__bf16*)(base + w.dt);  // D_{l-1}^T for the next weight gradient (this layer's uses are done)
+            h.ldht = n;
             if (gemm<kEpiGeluGrad>(h, true, true, 1, st) != hipSuccess) return MDGMI_E_HIP;
             std::swap(D, Dn);
         }
@@ -610,14 +643,34 @@ __global__ __launch_bounds__(256) void k_learned_cost(const float* __restrict__ 
     block_reduce_store(a, part + (size_t)blockIdx.x * kNPart);
 }
 
-__global__ void k_learned_finish(const double* __restrict__ part, int nb, int64_t n, int m, double* __restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Sums of the nb block partials in a fixed order (thread t adds blocks t,
+// t + 64, ... in turn, then a fixed tree over the 64 threads), then the GMI
+// estimate and its standard error.
+__global__ __launch_bounds__(64) void k_learned_finish(const double* __restrict__ part, int nb, int64_t n, int m,
+                                                       double* __restrict__ out) {
+    __shared__ double red[3][64];
+    const int t = threadIdx.x;
     double s = 0.0, s2 = 0.0, bad = 0.0;
-    for (int b = 0; b < nb; b++) {
+    for (int b = t; b < nb; b += 64) {
         s += part[(size_t)b * kNPart + 0];
         s2 += part[(size_t)b * kNPart + 1];
         bad += part[(size_t)b * kNPart + 4];
     }
+    red[0][t] = s;
+    red[1][t] = s2;
+    red[2][t] = bad;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (t < w) {
+            red[0][t] += red[0][t + w];
+            red[1][t] += red[1][t + w];
+            red[2][t] += red[2][t + w];
+        }
+        __syncthreads();
+    }
+    if (t != 0) return;
+    s = red[0][0];
+    s2 = red[1][0];
     const double N = (double)n;
     out[MDGMI_F_GMI] = m - s / N;
     out[MDGMI_F_MI] = NAN;  // the learned demapper gives bit metrics only
@@ -625,7 +678,7 @@ __global__ void k_learned_finish(const double* __restrict__ part, int nb, int64_
     out[MDGMI_F_SE_GMI] = sqrt(fmax(v, 0.0) / N);
     out[MDGMI_F_SE_MI] = NAN;
     out[MDGMI_F_N] = N;
-    out[MDGMI_F_NONFINITE] = bad;
+    out[MDGMI_F_NONFINITE] = red[2][0];
 }
 
 constexpr int kLearnedBlocks = 1024;

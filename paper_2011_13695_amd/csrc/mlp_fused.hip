@@ -135,22 +135,33 @@ __device__ __forceinline__ void gelu_tile(const f32x16& z, bf16x8& lo, bf16x8& h
     gelu_quarter8(a + 8, hi);
 }
 
-// Fused-layout weights of one layer: [out tile][K-block][lane][8] bf16,
-// times scale. Layer 0 takes its inputs in natural order; later layers in
-// the order the previous MFMA output lands in registers.
-__global__ void k_fused_weights(const float* __restrict__ W, int out, int in, int permute, int n_tiles, int n_kb,
-                                float scale, __bf16* __restrict__ dst) {
+// Fused-layout weights of the four layers: [out tile][K-block][lane][8]
+// bf16, times a power-of-two scale (layer 0: 1/4, so that the first
+// accumulators hold x / 4; the output layer: 4, as it reads GELU / 4).
+// Layer 0 takes its inputs in natural order; later layers in the order the
+// previous MFMA output lands in registers. One launch, blockIdx.y = layer.
+struct FusedWArgs {
+    const float* W[4];
+    __bf16* dst[4];
+    int out[4], in[4];
+};
+
+__global__ void k_fused_weights(FusedWArgs a) {
+    const int l = blockIdx.y;
+    const int out = a.out[l], in = a.in[l], n_tiles = (out + 31) / 32, n_kb = (in + 15) / 16;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one per (tile, kb, lane)
     if (g >= (int64_t)n_tiles * n_kb * 64) return;
+    const float scale = l == 0 ? 0.25f : l == 3 ? 4.0f : 1.0f;
+    const float* __restrict__ W = a.W[l];
     const int lane = (int)(g % 64), kb = (int)((g / 64) % n_kb), t = (int)(g / (64 * n_kb));
     const int row = 32 * t + (lane & 31), h = lane >> 5;
     P8 p;
 #pragma unroll
     for (int i = 0; i < 8; i++) {
-        const int k = 16 * kb + (permute ? perm_in(h, i) : 8 * h + i);
+        const int k = 16 * kb + (l > 0 ? perm_in(h, i) : 8 * h + i);
         p.h[i] = (row < out && k < in) ? (__bf16)(W[(int64_t)row * in + k] * scale) : (__bf16)0.0f;
     }
-    ((uint4*)dst)[g] = p.u;
+    ((uint4*)a.dst[l])[g] = p.u;
 }
 
 // One hidden layer: in activations act_in [kTiles][2] (bf16x8 per lane),
@@ -353,14 +364,19 @@ size_t fused_weight_bytes(int layer) {
     return 16 * (size_t)(layer == 0 ? kW1U : layer == 3 ? kW4U : kWHU);
 }
 
-hipError_t build_fused_weights(const float* W, int out, int in, int layer, __bf16* dst, hipStream_t st) {
+hipError_t build_fused_weights(const float* const* W, const int* out, const int* in, __bf16* const* dst,
+                               hipStream_t st) {
     using namespace fused;
-    const int n_tiles = (out + 31) / 32, n_kb = (in + 15) / 16;
-    const int64_t cnt = (int64_t)n_tiles * n_kb * 64;
-    // layer 0 -> x / 4 in the first accumulators; the output layer reads GELU / 4
-    const float scale = layer == 0 ? 0.25f : layer == 3 ? 4.0f : 1.0f;
-    hipLaunchKernelGGL(k_fused_weights, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, W, out, in,
-                       layer == 0 ? 0 : 1, n_tiles, n_kb, scale, dst);
+    FusedWArgs a;
+    int64_t most = 0;
+    for (int l = 0; l < 4; l++) {
+        a.W[l] = W[l];
+        a.dst[l] = dst[l];
+        a.out[l] = out[l];
+        a.in[l] = in[l];
+        most = std::max<int64_t>(most, (int64_t)((out[l] + 31) / 32) * ((in[l] + 15) / 16) * 64);
+    }
+    hipLaunchKernelGGL(k_fused_weights, dim3((unsigned)((most + 255) / 256), 4), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -65,6 +65,8 @@ struct GemmArgs {
     int64_t ldh;
     const float* Z;              // pre-activation for kEpiGeluGrad, row-major [M][ldz]
     int64_t ldz;
+    __bf16* Ht;                  // optional transposed copy of H, [N][ldht] (kEpiGeluBf16, kEpiGeluGrad)
+    int64_t ldht;
 };
 
 template <bool A_K_CONTIG>
@@ -183,6 +185,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     }
     // lane holds rows 8 (r >> 2) + 4 (lane >> 5) + (r & 3) of column lane & 31
     const int64_t n = n0 + wn + (lane & 31);
+    __bf16 hv[16];
 #pragma unroll
     for (int r = 0; r < 16; r++) {
         const int64_t m = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -194,11 +197,37 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         } else if (EPI == kEpiGeluBf16) {
             v += g.bias[n];
             ((float*)g.C)[m * g.ldc + n] = v;  // pre-activation kept for the backward pass
-            g.H[m * g.ldh + n] = (__bf16)gelu_f(v);
+            hv[r] = (__bf16)gelu_f(v);
+            g.H[m * g.ldh + n] = hv[r];
         } else if (EPI == kEpiGeluGrad) {
-            g.H[m * g.ldh + n] = (__bf16)(v * gelu_grad_f(g.Z[m * g.ldz + n]));
+            hv[r] = (__bf16)(v * gelu_grad_f(g.Z[m * g.ldz + n]));
+            g.H[m * g.ldh + n] = hv[r];
         } else {
             g.C[(int64_t)blockIdx.z * g.M * g.N + m * g.N + n] = v;
+        }
+    }
+    if constexpr (EPI == kEpiGeluBf16 || EPI == kEpiGeluGrad) {
+        // H^T [n][m]: each run of four rows is four consecutive m of column n,
+        // one 8-byte store where the run is whole and the pitch allows
+        if (g.Ht && n < g.N) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int64_t mb = m0 + wm + 8 * q + 4 * (lane >> 5);
+                __bf16* dst = g.Ht + n * g.ldht + mb;
+                if (mb + 4 <= g.M && g.ldht % 4 == 0 && ((uintptr_t)g.Ht & 7) == 0) {
+                    union {
+                        uint2 u;
+                        __bf16 h[4];
+                    } p;
+#pragma unroll
+                    for (int j = 0; j < 4; j++) p.h[j] = hv[4 * q + j];
+                    *(uint2*)dst = p.u;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        if (mb + j < g.M) dst[j] = hv[4 * q + j];
+                }
+            }
         }
     }
 }
