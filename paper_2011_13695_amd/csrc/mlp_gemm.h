@@ -44,8 +44,8 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
 }
 
 enum Epi : int {
-    kEpiF32 = 0,        // C (FP32) = acc (+ bias[n] if bias)
-    kEpiGeluBf16 = 1,   // Z (FP32) = acc + bias[n]; H (bf16) = gelu(Z)
+    kEpiF32 = 0,        // C (FP32) = bias[n] (if bias) + acc
+    kEpiGeluBf16 = 1,   // Z (FP32) = bias[n] + acc; H (bf16) = gelu(Z)
     kEpiGeluGrad = 2,   // D (bf16) = acc * gelu'(Z[m][n])
     kEpiPartial = 3     // C + split * M * N (FP32) = acc  (split-K partials)
 };
@@ -124,49 +124,103 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     const int64_t kb = (int64_t)blockIdx.z * g.k_per_split;
     const int64_t ke = kb + g.k_per_split < g.K ? kb + g.k_per_split : g.K;
     f32x16 acc = {};
+    // The epilogue's inputs are fetched before the K loop, so that their
+    // latency is spent under it: the bias seeds the accumulators, and the
+    // pre-activations that GELU' reads are held in registers.
+    // lane holds rows 8 (r >> 2) + 4 (lane >> 5) + (r & 3) of column lane & 31
+    const int64_t n = n0 + wn + (lane & 31);
+    if constexpr (EPI == kEpiF32 || EPI == kEpiGeluBf16) {
+        if (g.bias && n < g.N) {
+            const float b = g.bias[n];
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[r] = b;
+        }
+    }
+    float zp[16];
+    if constexpr (EPI == kEpiGeluGrad) {
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int64_t m = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            zp[r] = (m < g.M && n < g.N) ? g.Z[m * g.ldz + n] : 0.0f;
+        }
+    }
     if constexpr (A_K_CONTIG && B_K_CONTIG) {
         // Both operands k-contiguous (every call of the training step): each
         // thread moves 8 consecutive k of one A row and one B column per
-        // K-step, as one 16-byte load where the row pitch, the pointer and
-        // the K range allow, and the next K-step's loads are issued before
-        // the MFMAs of the current one.
+        // K-step.
         const int t = threadIdx.x, rr = t >> 2, kk = (t & 3) * 8;
         const bool avec = g.a_sk == 1 && g.a_sm % 8 == 0 && ((uintptr_t)g.A & 15) == 0;
         const bool bvec = g.b_sk == 1 && g.b_sn % 8 == 0 && ((uintptr_t)g.B & 15) == 0;
-        auto fetch = [&](const __bf16* base, int64_t row, int64_t rows, int64_t pitch, int64_t sk, bool vec,
-                         int64_t k0) {
-            const int64_t k = k0 + kk;
-            union {
-                uint4 u;
-                __bf16 h[8];
-            } p;
-            if (vec && row < rows && k + 8 <= ke) {
-                p.u = *(const uint4*)(base + row * pitch + k);
-            } else {
+        if (avec && bvec && (ke - kb) % 8 == 0 && ke - kb >= 8) {
+            // 16-byte loads with no branch: rows past M / N and k past ke
+            // read a clamped in-range address and are zeroed when stored to
+            // LDS, so no load waits for another and each is first waited for
+            // where its K-step stores it.
+            const bool arow = m0 + rr < g.M, brow = n0 + rr < g.N;
+            const __bf16* pa = g.A + (arow ? m0 + rr : g.M - 1) * g.a_sm;
+            const __bf16* pb = g.B + (brow ? n0 + rr : g.N - 1) * g.b_sn;
+            auto ld = [&](const __bf16* p, int64_t k) { return *(const uint4*)(p + (k < ke - 8 ? k : ke - 8)); };
+            // zeroing by masks on the values (a select of whole vectors is
+            // made through the stack)
+            auto masked = [](uint4 v, bool keep) {
+                const uint32_t m = keep ? ~0u : 0u;
+                return make_uint4(v.x & m, v.y & m, v.z & m, v.w & m);
+            };
+            // One K-step: the operands loaded two steps earlier go to LDS, and
+            // the same registers take the loads for two steps later, so two
+            // steps' loads are in flight under each step's MFMAs.
+            auto step = [&](int64_t k0, uint4& ra, uint4& rb) {
+                const bool kin = k0 + kk < ke;
+                *(uint4*)(As + rr * kLdsPitch + kk) = masked(ra, arow && kin);
+                *(uint4*)(Bs + rr * kLdsPitch + kk) = masked(rb, brow && kin);
+                __syncthreads();
+                // unconditional (loads past ke read a clamped address and go
+                // unused): a conditional load would be merged with the old
+                // value, and that copy waits for the load
+                ra = ld(pa, k0 + 2 * kKStep + kk);
+                rb = ld(pb, k0 + 2 * kKStep + kk);
+#pragma unroll
+                for (int ks = 0; ks < kKStep; ks += 16) {
+                    const int kofs = ks + 8 * (lane >> 5);
+                    const bf16x8 a = *(const bf16x8*)(As + (wm + (lane & 31)) * kLdsPitch + kofs);
+                    const bf16x8 b = *(const bf16x8*)(Bs + (wn + (lane & 31)) * kLdsPitch + kofs);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+                }
+                __syncthreads();
+            };
+            uint4 ra0 = ld(pa, kb + kk), rb0 = ld(pb, kb + kk);
+            uint4 ra1 = ld(pa, kb + kKStep + kk), rb1 = ld(pb, kb + kKStep + kk);
+            // steps in pairs; a step past ke (odd count) multiplies zeros
+            for (int64_t k0 = kb; k0 < ke; k0 += 2 * kKStep) {
+                step(k0, ra0, rb0);
+                step(k0 + kKStep, ra1, rb1);
+            }
+        } else {
+            // any pitch, pointer or K range: element loads, zero past the edges
+            auto fetch = [&](const __bf16* base, int64_t row, int64_t rows, int64_t pitch, int64_t sk, int64_t k0) {
+                const int64_t k = k0 + kk;
+                union {
+                    uint4 u;
+                    __bf16 h[8];
+                } p;
 #pragma unroll
                 for (int i = 0; i < 8; i++)
                     p.h[i] = (row < rows && k + i < ke) ? base[row * pitch + (k + i) * sk] : (__bf16)0.0f;
-            }
-            return p.u;
-        };
-        uint4 ra = fetch(g.A, m0 + rr, g.M, g.a_sm, g.a_sk, avec, kb);
-        uint4 rb = fetch(g.B, n0 + rr, g.N, g.b_sn, g.b_sk, bvec, kb);
-        for (int64_t k0 = kb; k0 < ke; k0 += kKStep) {
-            *(uint4*)(As + rr * kLdsPitch + kk) = ra;
-            *(uint4*)(Bs + rr * kLdsPitch + kk) = rb;
-            __syncthreads();
-            if (k0 + kKStep < ke) {
-                ra = fetch(g.A, m0 + rr, g.M, g.a_sm, g.a_sk, avec, k0 + kKStep);
-                rb = fetch(g.B, n0 + rr, g.N, g.b_sn, g.b_sk, bvec, k0 + kKStep);
-            }
+                return p.u;
+            };
+            for (int64_t k0 = kb; k0 < ke; k0 += kKStep) {
+                *(uint4*)(As + rr * kLdsPitch + kk) = fetch(g.A, m0 + rr, g.M, g.a_sm, g.a_sk, k0);
+                *(uint4*)(Bs + rr * kLdsPitch + kk) = fetch(g.B, n0 + rr, g.N, g.b_sn, g.b_sk, k0);
+                __syncthreads();
 #pragma unroll
-            for (int ks = 0; ks < kKStep; ks += 16) {
-                const int kofs = ks + 8 * (lane >> 5);
-                const bf16x8 a = *(const bf16x8*)(As + (wm + (lane & 31)) * kLdsPitch + kofs);
-                const bf16x8 b = *(const bf16x8*)(Bs + (wn + (lane & 31)) * kLdsPitch + kofs);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+                for (int ks = 0; ks < kKStep; ks += 16) {
+                    const int kofs = ks + 8 * (lane >> 5);
+                    const bf16x8 a = *(const bf16x8*)(As + (wm + (lane & 31)) * kLdsPitch + kofs);
+                    const bf16x8 b = *(const bf16x8*)(Bs + (wn + (lane & 31)) * kLdsPitch + kofs);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
     } else {
         for (int64_t k0 = kb; k0 < ke; k0 += kKStep) {
@@ -183,24 +237,20 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
             __syncthreads();
         }
     }
-    // lane holds rows 8 (r >> 2) + 4 (lane >> 5) + (r & 3) of column lane & 31
-    const int64_t n = n0 + wn + (lane & 31);
     __bf16 hv[16];
 #pragma unroll
     for (int r = 0; r < 16; r++) {
         const int64_t m = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         if (m >= g.M || n >= g.N) continue;
-        float v = acc[r];
+        const float v = acc[r];
         if (EPI == kEpiF32) {
-            if (g.bias) v += g.bias[n];
             g.C[m * g.ldc + n] = v;
         } else if (EPI == kEpiGeluBf16) {
-            v += g.bias[n];
             ((float*)g.C)[m * g.ldc + n] = v;  // pre-activation kept for the backward pass
             hv[r] = (__bf16)gelu_f(v);
             g.H[m * g.ldh + n] = hv[r];
         } else if (EPI == kEpiGeluGrad) {
-            hv[r] = (__bf16)(v * gelu_grad_f(g.Z[m * g.ldz + n]));
+            hv[r] = (__bf16)(v * gelu_grad_f(zp[r]));
             g.H[m * g.ldh + n] = hv[r];
         } else {
             g.C[(int64_t)blockIdx.z * g.M * g.N + m * g.N + n] = v;
