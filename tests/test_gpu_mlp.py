@@ -121,6 +121,39 @@ def test_loss_and_gradient_match_oracle(net, orc, n):
     say(f"[mlp] gradient n={n}: max |d| / bar = {worst:.3f}")
 
 
+@pytest.mark.parametrize("n", [776, 777])
+def test_gradient_of_ragged_widths_matches_oracle(orc, n):
+    """Widths that fill neither a 64-wide GEMM tile nor a 32-wide K-step
+    (40, 24: multiples of 8, so the 16-byte operand path runs with its row
+    and k masks) and sample counts on both sides of a multiple of 8 (776:
+    the weight gradients take the 16-byte path over ragged K slices; 777:
+    the element path)."""
+    sizes = [9, 40, 24, 11]
+    m_ = mdgmi.MLP(sizes, seed=11)
+    f, y, tx, x, s2 = demapper_inputs(n, seed=n)
+    lam = orc.llr(y, f.X, f.labels, s2)
+    x32 = x.astype(np.float32)
+    say(f"[mlp] ragged widths {sizes} n={n}")
+    loss = m_.loss_grad(torch.from_numpy(x32).cuda(), torch.from_numpy(lam.astype(np.float32)).cuda())
+    g = m_.grad().astype(np.float64)
+    p = m_.params().astype(np.float64)
+    target = 1.0 / (1.0 + np.exp(-lam.astype(np.float32).astype(np.float64)))
+    pq, xq = mb.round_operands(p, sizes, x32.astype(np.float64))
+    ref_loss, ref_g = orc.mlp_loss_grad(pq, sizes, xq, target)
+    sd_loss, sd_w, sd_b = mb.grad_sd(pq, sizes, xq, target)
+    assert abs(float(loss.item()) - ref_loss) <= mb.K_SIGMA * sd_loss + 1e-6 * abs(ref_loss)
+    for l, (ws, bs) in enumerate(layer_slices(sizes)):
+        for sl, sd, name in ((ws, sd_w[l].ravel(), "W"), (bs, sd_b[l], "b")):
+            r = mb.check(g[sl], ref_g[sl], sd)
+            assert r <= 1.0, (l, name, r)
+            assert rel(g[sl], ref_g[sl]) <= 0.1, (l, name, rel(g[sl], ref_g[sl]))
+    logits = m_.forward(torch.from_numpy(x32).cuda()).cpu().numpy()
+    ref = orc.mlp_forward(p, sizes, x32.astype(np.float64))
+    r = mb.check(logits, ref, mb.logits_sd(p, sizes, x32.astype(np.float64)))
+    say(f"[mlp] ragged widths n={n}: logits max |d| / bar = {r:.3f}")
+    assert r <= 1.0, r
+
+
 def test_adam_matches_oracle_on_the_gpu_gradient(orc):
     sizes = [9, 64, 11]
     m_ = mdgmi.MLP(sizes, seed=3)
