@@ -16,6 +16,7 @@
 
 #include "device_common.h"
 #include "mlp_gemm.h"
+#include "mlp_layout.h"
 
 using mdgmi::mlp::GemmArgs;
 
@@ -189,16 +190,48 @@ __global__ __launch_bounds__(256) void k_grad_finish(const float* __restrict__ p
     if (threadIdx.x == 0) db[o] = red[0];
 }
 
-__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
-                       int64_t P, float lr, float b1, float b2, float eps, float c1, float c2) {
+// Adam on every parameter, and the bf16 copies of each updated weight in
+// the same thread: W [out][in], W^T [in][out] and, for the fused shape, its
+// element of the fused inference layout (the layout's padding stays as the
+// whole-layout build wrote it).
+struct AdamArgs {
+    float* p;
+    const float* g;
+    float* m;
+    float* v;
+    int64_t P;
+    float lr, b1, b2, eps, c1, c2;
+};
+
+struct CopyArgs {
+    int L;
+    bool fused;
+    int64_t woff[MDGMI_MLP_MAX_LAYERS];
+    int out[MDGMI_MLP_MAX_LAYERS], in[MDGMI_MLP_MAX_LAYERS];
+    __bf16* w[MDGMI_MLP_MAX_LAYERS];
+    __bf16* wt[MDGMI_MLP_MAX_LAYERS];
+    __bf16* wf[4];
+};
+
+__global__ void k_adam(AdamArgs a, CopyArgs c) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P) return;
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    if (i >= a.P) return;
+    const float gi = a.g[i];
+    const float mi = a.b1 * a.m[i] + (1.0f - a.b1) * gi;
+    const float vi = a.b2 * a.v[i] + (1.0f - a.b2) * gi * gi;
+    a.m[i] = mi;
+    a.v[i] = vi;
+    const float pi = a.p[i] - a.lr * (mi / a.c1) / (sqrtf(vi / a.c2) + a.eps);
+    a.p[i] = pi;
+    for (int l = 0; l < c.L; l++) {
+        const int64_t j = i - c.woff[l];
+        if (j < 0 || j >= (int64_t)c.out[l] * c.in[l]) continue;
+        const int o = (int)(j / c.in[l]), k = (int)(j % c.in[l]);
+        const __bf16 b = (__bf16)pi;
+        c.w[l][j] = b;
+        c.wt[l][(int64_t)k * c.out[l] + o] = b;
+        if (c.fused) c.wf[l][fused::fused_offset(l, o, k, c.in[l])] = (__bf16)(pi * fused::layer_scale(l));
+    }
 }
 
 // bf16 copies W [out][in] and W^T [in][out] of every layer, one launch
@@ -554,9 +587,19 @@ int mdgmi_mlp_adam_step(mdgmi_mlp* net, float lr, float beta1, float beta2, floa
     net->step++;
     const float c1 = (float)(1.0 - std::pow((double)beta1, (double)net->step));
     const float c2 = (float)(1.0 - std::pow((double)beta2, (double)net->step));
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((net->P + 255) / 256)), dim3(256), 0, st, net->d_params, net->d_grad,
-                       net->d_m, net->d_v, net->P, lr, beta1, beta2, eps, c1, c2);
-    refresh_all(net, st);
+    const AdamArgs a{net->d_params, net->d_grad, net->d_m, net->d_v, net->P, lr, beta1, beta2, eps, c1, c2};
+    CopyArgs c{};
+    c.L = net->L;
+    c.fused = net->fused;
+    for (int l = 0; l < net->L; l++) {
+        c.woff[l] = net->woff[l];
+        c.out[l] = net->sizes[l + 1];
+        c.in[l] = net->sizes[l];
+        c.w[l] = net->d_w[l];
+        c.wt[l] = net->d_wt[l];
+        if (l < 4) c.wf[l] = net->d_wf[l];
+    }
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((net->P + 255) / 256)), dim3(256), 0, st, a, c);
     return hipGetLastError() == hipSuccess ? MDGMI_OK : MDGMI_E_HIP;
 }
 

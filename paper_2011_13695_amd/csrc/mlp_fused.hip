@@ -28,6 +28,7 @@
 
 #include "device_common.h"
 #include "mlp_gemm.h"
+#include "mlp_layout.h"
 
 namespace mdgmi {
 namespace fused {
@@ -50,7 +51,6 @@ union P8 {
     __bf16 h[8];
 };
 
-__device__ __forceinline__ int perm_in(int h, int i) { return i < 4 ? 4 * h + i : 8 + 4 * h + (i - 4); }
 
 // Accumulator seeded with the bias of output tile ot: register r of lane
 // half h is row 8 (r >> 2) + 4 h + (r & 3), four runs of four consecutive
@@ -151,7 +151,7 @@ __global__ void k_fused_weights(FusedWArgs a) {
     const int out = a.out[l], in = a.in[l], n_tiles = (out + 31) / 32, n_kb = (in + 15) / 16;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one per (tile, kb, lane)
     if (g >= (int64_t)n_tiles * n_kb * 64) return;
-    const float scale = l == 0 ? 0.25f : l == 3 ? 4.0f : 1.0f;
+    const float scale = layer_scale(l);
     const float* __restrict__ W = a.W[l];
     const int lane = (int)(g % 64), kb = (int)((g / 64) % n_kb), t = (int)(g / (64 * n_kb));
     const int row = 32 * t + (lane & 31), h = lane >> 5;
