@@ -3,7 +3,8 @@ the FP64 oracle (serial and with OpenMP threads) and the C-ABI's format
 checks and preparation (csrc/format_host.cpp, the code behind
 mdgmi_validate_labels and mdgmi_format_create's argument checks), each
 driven over every dimension, edge inputs and every rejected argument by a
-small driver under tests/sanitize/. A sanitizer report aborts the driver."""
+small driver under tests/sanitize/, and the fused inference layout's index
+map. A sanitizer report aborts the driver."""
 import os
 import shutil
 import subprocess
@@ -39,3 +40,16 @@ def test_format_checks_under_sanitizers(tmp_path):
          str(ROOT / "tests" / "sanitize" / "format_driver.cpp"), "-o", str(exe)])
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1")
     assert "format driver ok" in run([str(exe)], env=env)
+
+
+@pytest.mark.skipif(shutil.which("g++") is None or not Path("/opt/rocm/include/hip").is_dir(),
+                    reason="g++ or the HIP headers not available")
+def test_fused_layout_index_map(tmp_path):
+    """csrc/mlp_layout.h on the host: the inverse index map the Adam step
+    writes through agrees with the whole-layout builder's forward map."""
+    exe = tmp_path / "layout_san"
+    csrc = ROOT / "paper_2011_13695_amd" / "csrc"
+    run(["g++", "-std=c++17", "-Wall", *SAN, "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", f"-I{csrc}",
+         str(ROOT / "tests" / "sanitize" / "layout_driver.cpp"), "-o", str(exe)])
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1")
+    assert "layout driver ok" in run([str(exe)], env=env)
