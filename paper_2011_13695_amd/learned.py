@@ -93,8 +93,10 @@ class Trainer:
         self.y = torch.empty((S, n, gf.dim), dtype=torch.float32, device="cuda")
         self.tx = torch.empty((S, n), dtype=torch.int32, device="cuda")
         self.lam = torch.empty((S, n, gf.m), dtype=torch.float32, device="cuda")
-        self.yb = torch.empty((B, gf.dim), dtype=torch.float32, device="cuda")
-        self.lb = torch.empty((B, gf.m), dtype=torch.float32, device="cuda")
+        # the chunk regrouped by step: step k's batch (block k of every
+        # slice) is yb[k], contiguous, so a step copies nothing
+        self.yb = torch.empty((C, B, gf.dim), dtype=torch.float32, device="cuda")
+        self.lb = torch.empty((C, B, gf.m), dtype=torch.float32, device="cuda")
         self.snr = torch.empty(B, dtype=torch.float32, device="cuda")
         self.loss = torch.empty(1, dtype=torch.float64, device="cuda")
         self.grid = np.arange(cfg.snr_lo, cfg.snr_hi + 1e-9, cfg.snr_step)
@@ -116,17 +118,18 @@ class Trainer:
         mdgmi.mdgmi_generate(gf, c.seed, s2, c.chunk * self.per, snr_slot0=slot, y=self.y, tx_idx=self.tx)
         for q in range(c.slices):
             mdgmi.mdgmi_llr(gf, self.y[q], float(s2[q]), path=c.path, llr=self.lam[q], ws=self.llr_ws)
+        S, per = c.slices, self.per
+        self.yb.view(c.chunk, S, per, gf.dim).copy_(self.y.view(S, c.chunk, per, gf.dim).transpose(0, 1))
+        self.lb.view(c.chunk, S, per, gf.m).copy_(self.lam.view(S, c.chunk, per, gf.m).transpose(0, 1))
         self.snr.copy_(torch.from_numpy(np.repeat(snrs, self.per).astype(np.float32)))
 
     def step(self):
-        c, per = self.cfg, self.per
+        c = self.cfg
         k = self.step_no % c.chunk
         if k == 0:
             self._chunk()
-        sl = slice(k * per, (k + 1) * per)
-        self.yb.view(c.slices, per, self.gf.dim).copy_(self.y[:, sl])
-        self.lb.view(c.slices, per, self.gf.m).copy_(self.lam[:, sl])
-        self.net.train_step(self.yb, self.snr, self.lb, self.lr_at(self.step_no), loss=self.loss, ws=self.train_ws)
+        self.net.train_step(self.yb[k], self.snr, self.lb[k], self.lr_at(self.step_no), loss=self.loss,
+                            ws=self.train_ws)
         self.step_no += 1
 
     def train(self, steps=None, log=None, held_out: HeldOut | None = None, curve_points: int = 8):
