@@ -3,8 +3,9 @@
 // C[M x N] = sum_k A(m, k) B(k, n), A and B in bf16 addressed by element
 // strides (so row-major, transposed and batched-transposed operands share
 // one kernel), FP32 accumulation on v_mfma_f32_32x32x16_bf16. A block of 4
-// waves owns a 64 x 64 output tile and walks K in steps of 32 through LDS;
-// each wave owns a 32 x 32 quarter. Tiles are stored k-contiguous in LDS,
+// waves owns a 64 x 64 output tile and walks K through LDS (64 k per stage,
+// two stages' loads in flight, where both operands are k-contiguous with
+// 16-byte rows; else 32 k per step); each wave owns a 32 x 32 quarter. Tiles are stored k-contiguous in LDS,
 // so every lane's MFMA operand (8 consecutive k of one row / column) is one
 // 16-byte read. Operands whose k is contiguous in memory are fetched 8 at a
 // time; others are fetched along m / n and transposed on the way into LDS.
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     if constexpr (A_K_CONTIG && B_K_CONTIG) {
         // Both operands k-contiguous (every call of the training step): each
         // thread moves 8 consecutive k of one A row and one B column per
-        // K-step.
+        // 32 k.
         const int t = threadIdx.x, rr = t >> 2, kk = (t & 3) * 8;
         const bool avec = g.a_sk == 1 && g.a_sm % 8 == 0 && ((uintptr_t)g.A & 15) == 0;
         const bool bvec = g.b_sk == 1 && g.b_sn % 8 == 0 && ((uintptr_t)g.B & 15) == 0;
@@ -155,7 +156,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
             // 16-byte loads with no branch: rows past M / N and k past ke
             // read a clamped in-range address and are zeroed when stored to
             // LDS, so no load waits for another and each is first waited for
-            // where its K-step stores it.
+            // where its stage stores it.
             const bool arow = m0 + rr < g.M, brow = n0 + rr < g.N;
             const __bf16* pa = g.A + (arow ? m0 + rr : g.M - 1) * g.a_sm;
             const __bf16* pb = g.B + (brow ? n0 + rr : g.N - 1) * g.b_sn;
@@ -166,34 +167,50 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
                 const uint32_t m = keep ? ~0u : 0u;
                 return make_uint4(v.x & m, v.y & m, v.z & m, v.w & m);
             };
-            // One K-step: the operands loaded two steps earlier go to LDS, and
-            // the same registers take the loads for two steps later, so two
-            // steps' loads are in flight under each step's MFMAs.
-            auto step = [&](int64_t k0, uint4& ra, uint4& rb) {
-                const bool kin = k0 + kk < ke;
-                *(uint4*)(As + rr * kLdsPitch + kk) = masked(ra, arow && kin);
-                *(uint4*)(Bs + rr * kLdsPitch + kk) = masked(rb, brow && kin);
+            // One stage of kStage k: the operands loaded two stages earlier
+            // go to LDS, and the same registers take the loads for two stages
+            // later, so two stages' loads are in flight under each stage's
+            // MFMAs.
+            constexpr int kStage = 64, kSub = kStage / 32, kStagePitch = kStage + 8;
+            __shared__ __attribute__((aligned(16))) __bf16 Aw[kTile * kStagePitch];
+            __shared__ __attribute__((aligned(16))) __bf16 Bw[kTile * kStagePitch];
+            auto stage = [&](int64_t k0, uint4 (&ra)[kSub], uint4 (&rb)[kSub]) {
+#pragma unroll
+                for (int j = 0; j < kSub; j++) {
+                    const bool kin = k0 + 32 * j + kk < ke;
+                    *(uint4*)(Aw + rr * kStagePitch + 32 * j + kk) = masked(ra[j], arow && kin);
+                    *(uint4*)(Bw + rr * kStagePitch + 32 * j + kk) = masked(rb[j], brow && kin);
+                }
                 __syncthreads();
                 // unconditional (loads past ke read a clamped address and go
                 // unused): a conditional load would be merged with the old
                 // value, and that copy waits for the load
-                ra = ld(pa, k0 + 2 * kKStep + kk);
-                rb = ld(pb, k0 + 2 * kKStep + kk);
 #pragma unroll
-                for (int ks = 0; ks < kKStep; ks += 16) {
+                for (int j = 0; j < kSub; j++) {
+                    ra[j] = ld(pa, k0 + 2 * kStage + 32 * j + kk);
+                    rb[j] = ld(pb, k0 + 2 * kStage + 32 * j + kk);
+                }
+#pragma unroll
+                for (int ks = 0; ks < kStage; ks += 16) {
                     const int kofs = ks + 8 * (lane >> 5);
-                    const bf16x8 a = *(const bf16x8*)(As + (wm + (lane & 31)) * kLdsPitch + kofs);
-                    const bf16x8 b = *(const bf16x8*)(Bs + (wn + (lane & 31)) * kLdsPitch + kofs);
+                    const bf16x8 a = *(const bf16x8*)(Aw + (wm + (lane & 31)) * kStagePitch + kofs);
+                    const bf16x8 b = *(const bf16x8*)(Bw + (wn + (lane & 31)) * kStagePitch + kofs);
                     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
                 }
                 __syncthreads();
             };
-            uint4 ra0 = ld(pa, kb + kk), rb0 = ld(pb, kb + kk);
-            uint4 ra1 = ld(pa, kb + kKStep + kk), rb1 = ld(pb, kb + kKStep + kk);
-            // steps in pairs; a step past ke (odd count) multiplies zeros
-            for (int64_t k0 = kb; k0 < ke; k0 += 2 * kKStep) {
-                step(k0, ra0, rb0);
-                step(k0 + kKStep, ra1, rb1);
+            uint4 ra0[kSub], rb0[kSub], ra1[kSub], rb1[kSub];
+#pragma unroll
+            for (int j = 0; j < kSub; j++) {
+                ra0[j] = ld(pa, kb + 32 * j + kk);
+                rb0[j] = ld(pb, kb + 32 * j + kk);
+                ra1[j] = ld(pa, kb + kStage + 32 * j + kk);
+                rb1[j] = ld(pb, kb + kStage + 32 * j + kk);
+            }
+            // stages in pairs; k past ke (in a stage or a whole stage) multiplies zeros
+            for (int64_t k0 = kb; k0 < ke; k0 += 2 * kStage) {
+                stage(k0, ra0, rb0);
+                stage(k0 + kStage, ra1, rb1);
             }
         } else {
             // any pitch, pointer or K range: element loads, zero past the edges
